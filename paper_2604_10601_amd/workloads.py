@@ -1,0 +1,291 @@
+"""Seeded synthetic workloads: data graphs, vertex labels and extracted queries.
+
+This module only builds inputs.  It holds none of the matching arithmetic, so
+both the GPU path and the CPU oracle can be fed from it.  Every generator takes
+an explicit integer seed and draws from numpy's PCG64, so a (recipe, seed) pair
+names one input exactly.
+
+Recipes (the paper's own datasets are not available; these stand in for them):
+
+* Erdos-Renyi G(n, M): M distinct undirected pairs drawn uniformly without
+  replacement, no self-loops (uniform labels as in the experimental setup,
+  Sec. 6.1, "Datasets").
+* R-MAT (the generator family behind the paper's ``rm`` graph, Sec. 6.1 and
+  Table 3): ``edge_factor * 2**scale`` draws; each of the ``scale`` bits of a
+  draw picks one quadrant (a, b, c, d) with one uniform number; the result is
+  symmetrised, self-loops and duplicates are dropped and vertex ids are
+  permuted at random.
+* Zipf labels (App. A, "label distribution skewness"): P(l) proportional to
+  (l+1)**-s for l in [0, |Sigma|-1].
+* Queries (Sec. 6.1, "Query Sets"): a random walk from a random seed vertex
+  adds unseen neighbours until k vertices are collected; the query is the
+  induced subgraph on them with labels copied, ids in discovery order.  Dense
+  means average query degree >= 3 (App. A, "query graph density").
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Graph:
+    """Undirected labelled graph in CSR form (both directions stored).
+
+    row_ptr: int64 [n+1]; col: int32 [row_ptr[n]], each row strictly ascending;
+    labels: int32 [n].
+    """
+
+    row_ptr: np.ndarray
+    col: np.ndarray
+    labels: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.row_ptr.shape[0] - 1)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    @property
+    def num_edges(self) -> int:
+        return self.nnz // 2
+
+    def degrees(self) -> np.ndarray:
+        return np.diff(self.row_ptr)
+
+
+@dataclasses.dataclass
+class Query:
+    """Connected query graph: k vertices, edges (m, 2) int32 with a < b, labels int32 [k].
+
+    ``witness`` is the data-vertex tuple the query was cut from (one known
+    embedding, indexed by query vertex id), or None for hand-built queries.
+    """
+
+    k: int
+    edges: np.ndarray
+    labels: np.ndarray
+    witness: Optional[np.ndarray] = None
+
+    @property
+    def m(self) -> int:
+        return int(self.edges.shape[0])
+
+    @property
+    def dense(self) -> bool:
+        return 2 * self.m >= 3 * self.k
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def csr_from_pairs(n: int, lo: np.ndarray, hi: np.ndarray) -> tuple:
+    """CSR (row_ptr int64, col int32) of the undirected graph with edges {lo[i], hi[i]}.
+
+    Pairs must already be distinct with lo != hi.
+    """
+    lo = np.asarray(lo, dtype=np.int64)
+    hi = np.asarray(hi, dtype=np.int64)
+    key = np.concatenate([lo * n + hi, hi * n + lo])
+    key.sort(kind="stable")
+    src = key // n
+    dst = (key - src * n).astype(np.int32)
+    counts = np.bincount(src, minlength=n).astype(np.int64)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    return row_ptr, dst
+
+
+def dedup_undirected(n: int, u: np.ndarray, v: np.ndarray) -> tuple:
+    """Canonical distinct undirected pairs (lo < hi) from arbitrary endpoint arrays."""
+    u = np.asarray(u, dtype=np.int64)
+    v = np.asarray(v, dtype=np.int64)
+    lo = np.minimum(u, v)
+    hi = np.maximum(u, v)
+    keep = lo != hi
+    key = np.unique(lo[keep] * n + hi[keep])
+    lo = key // n
+    return lo, key - lo * n
+
+
+def erdos_renyi(n: int, m: int, seed: int) -> tuple:
+    """G(n, M): m distinct non-loop pairs drawn uniformly without replacement."""
+    total = n * (n - 1) // 2
+    if m > total:
+        raise ValueError("too many edges for n")
+    rng = _rng(seed)
+    t = np.sort(rng.choice(total, size=m, replace=False)).astype(np.int64)
+    i_idx = np.arange(n, dtype=np.int64)
+    first = i_idx * (2 * n - i_idx - 1) // 2  # index of pair (i, i+1)
+    lo = np.searchsorted(first, t, side="right") - 1
+    hi = t - first[lo] + lo + 1
+    return csr_from_pairs(n, lo, hi)
+
+
+def rmat_pairs(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int,
+               chunk: int = 1 << 23) -> tuple:
+    """Raw R-MAT endpoint draws (before symmetrisation and dedup)."""
+    rng = _rng(seed)
+    draws = edge_factor << scale
+    src = np.empty(draws, dtype=np.int64)
+    dst = np.empty(draws, dtype=np.int64)
+    ab, abc = a + b, a + b + c
+    for s0 in range(0, draws, chunk):
+        cnt = min(chunk, draws - s0)
+        s = np.zeros(cnt, dtype=np.int64)
+        d = np.zeros(cnt, dtype=np.int64)
+        for _ in range(scale):
+            u = rng.random(cnt)
+            down = u >= ab
+            right = ((u >= a) & (u < ab)) | (u >= abc)
+            s = (s << 1) | down
+            d = (d << 1) | right
+        src[s0:s0 + cnt] = s
+        dst[s0:s0 + cnt] = d
+    return src, dst
+
+
+def rmat(scale: int, edge_factor: int, seed: int, a: float = 0.57, b: float = 0.19,
+         c: float = 0.19) -> tuple:
+    """Symmetrised, deduplicated, loop-free R-MAT graph with randomly permuted ids."""
+    n = 1 << scale
+    src, dst = rmat_pairs(scale, edge_factor, a, b, c, seed)
+    lo, hi = dedup_undirected(n, src, dst)
+    del src, dst
+    perm = _rng(seed + 1_000_003).permutation(n).astype(np.int64)
+    return csr_from_pairs(n, perm[lo], perm[hi])
+
+
+def uniform_labels(n: int, num_labels: int, seed: int) -> np.ndarray:
+    return _rng(seed).integers(0, num_labels, size=n).astype(np.int32)
+
+
+def zipf_labels(n: int, num_labels: int, s: float, seed: int) -> np.ndarray:
+    w = (np.arange(num_labels, dtype=np.float64) + 1.0) ** (-s)
+    return _rng(seed).choice(num_labels, size=n, p=w / w.sum()).astype(np.int32)
+
+
+def induced_query(g: Graph, verts: Sequence[int]) -> Query:
+    """Induced subgraph of g on verts (ids = positions in verts), labels copied."""
+    verts = np.asarray(verts, dtype=np.int64)
+    k = len(verts)
+    edges = []
+    for a in range(k):
+        lo, hi = g.row_ptr[verts[a]], g.row_ptr[verts[a] + 1]
+        nb = g.col[lo:hi]
+        for b in range(a + 1, k):
+            p = np.searchsorted(nb, verts[b])
+            if p < nb.shape[0] and nb[p] == verts[b]:
+                edges.append((a, b))
+    e = np.asarray(edges, dtype=np.int32).reshape(-1, 2)
+    return Query(k=k, edges=e, labels=g.labels[verts].astype(np.int32),
+                 witness=verts.astype(np.int32))
+
+
+def random_walk_vertices(g: Graph, k: int, rng: np.random.Generator) -> np.ndarray:
+    """k distinct vertices visited by a random walk; restarts after 100*k idle steps."""
+    deg = g.degrees()
+    live = np.flatnonzero(deg > 0)
+    if live.shape[0] == 0:
+        raise ValueError("graph has no edges")
+    while True:
+        cur = int(live[rng.integers(live.shape[0])])
+        seen = {cur: 0}
+        order = [cur]
+        idle = 0
+        while len(order) < k and idle < 100 * k:
+            nxt = int(g.col[g.row_ptr[cur] + rng.integers(deg[cur])])
+            if nxt in seen:
+                idle += 1
+            else:
+                seen[nxt] = len(order)
+                order.append(nxt)
+                idle = 0
+            cur = nxt
+        if len(order) == k:
+            return np.asarray(order, dtype=np.int64)
+
+
+def extract_queries(g: Graph, k_list: Sequence[int], n_dense: int, n_sparse: int, seed: int,
+                    max_attempts: int = 200000) -> List[Query]:
+    """For every k in k_list: n_dense dense and n_sparse sparse random-walk queries.
+
+    Queries whose density class is already full are rejected and redrawn.
+    Order of the result: grouped by k, dense first, then sparse.
+    """
+    rng = _rng(seed)
+    out: List[Query] = []
+    for k in k_list:
+        dense: List[Query] = []
+        sparse: List[Query] = []
+        attempts = 0
+        while len(dense) < n_dense or len(sparse) < n_sparse:
+            attempts += 1
+            if attempts > max_attempts:
+                raise RuntimeError(f"could not fill dense/sparse quotas for k={k}")
+            q = induced_query(g, random_walk_vertices(g, k, rng))
+            if q.dense and len(dense) < n_dense:
+                dense.append(q)
+            elif (not q.dense) and len(sparse) < n_sparse:
+                sparse.append(q)
+        out.extend(dense)
+        out.extend(sparse)
+    return out
+
+
+def extract_queries_any(g: Graph, k: int, count: int, seed: int) -> List[Query]:
+    """count random-walk queries of size k with no density quota."""
+    rng = _rng(seed)
+    return [induced_query(g, random_walk_vertices(g, k, rng)) for _ in range(count)]
+
+
+# ---------------------------------------------------------------------------
+# Named workloads
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    graph: Graph
+    queries: List[Query]
+    cap: int            # 0 = no cap
+    time_limit_s: float  # <= 0 = none
+
+
+def small_er(num_queries: int = 20) -> Workload:
+    """ER n=2,000, |E|=8,000 (average degree 8), 4 uniform labels, 4-vertex queries."""
+    row_ptr, col = erdos_renyi(2000, 8000, seed=101)
+    g = Graph(row_ptr, col, uniform_labels(2000, 4, seed=102))
+    qs = extract_queries_any(g, 4, num_queries, seed=103)
+    return Workload("er2k_deg8_l4_q4", g, qs, cap=0, time_limit_s=0.0)
+
+
+def rmat20_graph() -> Graph:
+    """R-MAT scale 20, edge factor 16, (0.57, 0.19, 0.19, 0.05), 16 Zipf(1.0) labels."""
+    row_ptr, col = rmat(20, 16, seed=20)
+    return Graph(row_ptr, col, zipf_labels(1 << 20, 16, 1.0, seed=21))
+
+
+def medium_rmat20(n_dense: int = 50, n_sparse: int = 50) -> Workload:
+    """R-MAT scale 20 with 8-vertex queries, half dense and half sparse, cap 1e8."""
+    g = rmat20_graph()
+    qs = extract_queries(g, [8], n_dense, n_sparse, seed=22)
+    return Workload("rmat20_ef16_zipf16_q8", g, qs, cap=100_000_000, time_limit_s=0.0)
+
+
+def rmat24_graph() -> Graph:
+    """R-MAT scale 24, edge factor 16, 8 Zipf(1.2) labels (about 2.2 GB as int32 CSR)."""
+    row_ptr, col = rmat(24, 16, seed=24)
+    return Graph(row_ptr, col, zipf_labels(1 << 24, 8, 1.2, seed=25))
+
+
+def large_rmat24(per_class: int = 25) -> Workload:
+    """R-MAT scale 24 with 12/16/24/32-vertex queries, cap 1e9, 60 s per query."""
+    g = rmat24_graph()
+    qs = extract_queries(g, [12, 16, 24, 32], per_class, per_class, seed=26)
+    return Workload("rmat24_ef16_zipf8_q12-32", g, qs, cap=1_000_000_000, time_limit_s=60.0)
