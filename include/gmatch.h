@@ -1,0 +1,159 @@
+/*
+ * gmatch.h -- C ABI of the MI355X (gfx950) subgraph-matching engine.
+ *
+ * Problem (gMatch paper, Sec. 2.1, Def. 1): given an undirected vertex-labelled
+ * data graph G and a connected query graph Q, find every injective map
+ * M: V(Q) -> V(G) with L(u) = L(M[u]) for all query vertices u and
+ * (M[u], M[u']) in E(G) for every query edge (u, u').  Matching is
+ * non-induced and every map is counted (no symmetry breaking).  Algorithm 2's
+ * interface takes Q, G, a matching order phi and the initial pool size tau and
+ * outputs all matches; the calls below expose exactly that, with a result cap
+ * and a time limit added.
+ *
+ * Conventions shared by every call:
+ *   - Every call returns gm_status: GM_OK (0) or a negative error.  Nothing
+ *     throws across the ABI.  gm_last_error() returns a message for the last
+ *     failing call on an engine (or, with NULL, on this thread's gm_create).
+ *   - Host pointers are only read during the call; the caller keeps ownership.
+ *   - One engine holds one resident data graph on one GPU.  Calls on one engine
+ *     are serialised by an internal mutex; engines are independent.
+ *   - Counts are uint64.  Vertex ids are int32 in [0, n).
+ */
+#ifndef GMATCH_H
+#define GMATCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GM_OK = 0,
+    GM_ERR_ARG = -1,    /* null pointer, negative size, bad option value */
+    GM_ERR_GRAPH = -2,  /* G is not a simple undirected CSR graph, or exceeds layout limits */
+    GM_ERR_QUERY = -3,  /* Q is empty, larger than 32 vertices, not simple or not connected */
+    GM_ERR_ORDER = -4,  /* order is not a permutation or not connected (Sec. 2.2) */
+    GM_ERR_NOMEM = -5,  /* host or device allocation failed */
+    GM_ERR_DEVICE = -6, /* HIP runtime error, or the engine has no GPU */
+    GM_ERR_BUFFER = -7, /* output buffer missing or too small */
+    GM_ERR_STATE = -8   /* no graph loaded, or unknown / freed query id */
+} gm_status;
+
+typedef enum {
+    GM_DONE = 0,    /* search finished: count is exact */
+    GM_CAPPED = 1,  /* the count reached the cap: count == cap (the true number is >= cap) */
+    GM_TIMEOUT = 2  /* time limit hit first: count is a lower bound (an unsolved query, Sec. 6.1) */
+} gm_outcome;
+
+typedef struct gm_engine gm_engine;
+
+/* Engine options.  A zero-initialised struct selects every default. */
+typedef struct {
+    /* Initial task pool threshold tau (Sec. 4.3, "Initialization Phase"): the
+     * breadth-first expansion stops at the first level holding >= tau partial
+     * matches.  0 = default 1,000,000.  Negative = no expansion: the pool is the
+     * candidate set of the first query vertex (the BFS-disabled mode of Sec. 6.2). */
+    int64_t tau;
+    /* Largest pool the expansion may build, in rows; 0 = default 64 * tau. */
+    int64_t pool_row_limit;
+    /* 0 = idle wavefronts steal work from busy ones (Sec. 4.3, "Dynamic Balancing
+     * Phase"); 1 = no stealing. */
+    int32_t disable_stealing;
+    /* A busy wavefront donates work only from a level with at least this many
+     * unscattered tasks.  0 = default 128. */
+    int32_t steal_threshold;
+    /* Wavefronts launched per compute unit; 0 = as many as fit. */
+    int32_t waves_per_cu;
+    /* 1 = skip the symmetry check of gm_load_graph (trusted input). */
+    int32_t skip_symmetry_check;
+    /* Below this neighbour-list length a membership test scans the list with
+     * independent loads instead of bisecting it; 0 = default 8, max 16. */
+    int32_t linear_probe_len;
+    int32_t reserved[7];
+} gm_options;
+
+/* Result of one count or enumerate call. */
+typedef struct {
+    uint64_t count;        /* min(#matches, cap) */
+    int32_t outcome;       /* gm_outcome */
+    int32_t pool_depth;    /* matched positions per initial-pool row */
+    double search_ms;      /* wall time of the search on the device: from the first
+                              launch to the result being back on the host */
+    uint64_t pool_rows;    /* size of the initial task pool */
+    uint64_t groups;       /* task groups: valid partial matches of length 1..k-1 extended (Sec. 4.1) */
+    uint64_t tasks;        /* tasks: local candidates examined, sum of |C^L| over groups (Sec. 4.1) */
+    uint64_t lanes_active; /* lanes that held a task, summed over scatter rounds */
+    uint64_t lanes_issued; /* 64 x scatter rounds; idle rate = 1 - active/issued (Sec. 2.3) */
+    uint64_t probes;       /* 4-byte neighbour-list reads made by membership tests */
+    uint64_t steals;       /* work donations taken by idle wavefronts */
+    uint64_t rows;         /* enumerate: rows written */
+    double kernel_ms;      /* device time of the depth-first search launch alone (HIP events) */
+    int32_t grid_waves;    /* wavefronts in that launch */
+    int32_t reserved;
+    uint64_t kernel_tasks;  /* tasks, probes and matches of that launch alone (the pool */
+    uint64_t kernel_probes; /* expansion before it is excluded) */
+    uint64_t kernel_groups;
+} gm_result;
+
+/* Create an engine on HIP device `device` (>= 0).  device = -1 creates a
+ * host-only engine: graphs and queries are checked and planned, but count and
+ * enumerate return GM_ERR_DEVICE.  opt may be NULL (all defaults). */
+gm_status gm_create(int32_t device, const gm_options *opt, gm_engine **out);
+
+/* Free the engine, its device memory and its queries.  NULL is ignored. */
+void gm_destroy(gm_engine *engine);
+
+/* Load G from host CSR arrays, replacing any previous graph (and keeping the
+ * loaded queries).  row_ptr[n+1] (row_ptr[0] = 0, non-decreasing),
+ * col[row_ptr[n]] with every row strictly ascending, ids in [0, n), no
+ * self-loops, and every edge stored in both directions (Sec. 2.1: undirected).
+ * labels[n]: any int32 values; at most 255 distinct values.  Layout limits:
+ * row_ptr[n] < 2^32 and every degree < 2^24.  Violations: GM_ERR_GRAPH. */
+gm_status gm_load_graph(gm_engine *engine, int32_t n, const int64_t *row_ptr, const int32_t *col,
+                        const int32_t *labels);
+
+/* Load Q: k vertices (1..32), m undirected edges given as pairs
+ * edges[2e], edges[2e+1], labels[k].  Q must be simple and connected.  On
+ * success *qid_out receives a handle; its matching order is the heuristic
+ * order (see gm_set_order). */
+gm_status gm_load_query(gm_engine *engine, int32_t k, int32_t m, const int32_t *edges,
+                        const int32_t *labels, int32_t *qid_out);
+
+/* Set the matching order phi of a query (Sec. 2.2): order[i] is the query
+ * vertex mapped i-th.  It must be a permutation in which every vertex after the
+ * first has an earlier neighbour.  order = NULL restores the heuristic order:
+ * RI's greatest-constraint-first rule (Sec. 3 uses RI): start from the largest
+ * query degree, then repeatedly take the vertex with the most already-ordered
+ * neighbours, then the most ordered vertices adjacent to its unordered
+ * neighbours, then the most unordered neighbours with no ordered neighbour;
+ * ties go to the smaller vertex id. */
+gm_status gm_set_order(gm_engine *engine, int32_t qid, const int32_t *order);
+
+/* Copy the current matching order of a query into order_out[k]. */
+gm_status gm_get_order(const gm_engine *engine, int32_t qid, int32_t *order_out);
+
+/* Count the matches of query qid in the loaded graph (Alg. 2 with counting as
+ * its output).  cap = 0: no cap.  time_limit_s <= 0: no limit.  out receives
+ * the count, the outcome and the work counters. */
+gm_status gm_count(gm_engine *engine, int32_t qid, uint64_t cap, double time_limit_s, gm_result *out);
+
+/* List matches: rows is a host buffer of cap * k int32 (cap >= 1); row r holds
+ * the data vertex of query vertex 0..k-1 of the r-th match found.  Rows come in
+ * no particular order.  At most cap rows are written; out->count follows
+ * gm_count's rules with this cap and out->rows equals min(count, cap). */
+gm_status gm_enumerate(gm_engine *engine, int32_t qid, int32_t *rows, uint64_t cap, double time_limit_s,
+                       gm_result *out);
+
+/* Forget a query; its id is not reused. */
+gm_status gm_free_query(gm_engine *engine, int32_t qid);
+
+/* Message describing the last failed call on this engine (NULL: the last failed
+ * gm_create on this thread).  The pointer stays valid until the next call. */
+const char *gm_last_error(const gm_engine *engine);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMATCH_H */

@@ -1,0 +1,226 @@
+"""Python binding of libgmatch (the gfx950 subgraph-matching engine).
+
+Argument marshalling only: every step of a search runs in the HIP kernels
+behind the C ABI declared in include/gmatch.h.  The shared library is built
+in-tree by ``paper_2604_10601_amd/build.py`` (or ``__graft_entry__.build()``);
+importing this module without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgmatch.so")
+
+GM_OK, GM_ERR_ARG, GM_ERR_GRAPH, GM_ERR_QUERY, GM_ERR_ORDER = 0, -1, -2, -3, -4
+GM_ERR_NOMEM, GM_ERR_DEVICE, GM_ERR_BUFFER, GM_ERR_STATE = -5, -6, -7, -8
+GM_DONE, GM_CAPPED, GM_TIMEOUT = 0, 1, 2
+
+ABI_FUNCTIONS = ("gm_create", "gm_destroy", "gm_load_graph", "gm_load_query", "gm_set_order",
+                 "gm_get_order", "gm_count", "gm_enumerate", "gm_free_query", "gm_last_error")
+
+
+class GmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"gmatch error {status}: {message}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("tau", ctypes.c_int64),
+        ("pool_row_limit", ctypes.c_int64),
+        ("disable_stealing", ctypes.c_int32),
+        ("steal_threshold", ctypes.c_int32),
+        ("waves_per_cu", ctypes.c_int32),
+        ("skip_symmetry_check", ctypes.c_int32),
+        ("linear_probe_len", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+class _CResult(ctypes.Structure):
+    _fields_ = [
+        ("count", ctypes.c_uint64),
+        ("outcome", ctypes.c_int32),
+        ("pool_depth", ctypes.c_int32),
+        ("search_ms", ctypes.c_double),
+        ("pool_rows", ctypes.c_uint64),
+        ("groups", ctypes.c_uint64),
+        ("tasks", ctypes.c_uint64),
+        ("lanes_active", ctypes.c_uint64),
+        ("lanes_issued", ctypes.c_uint64),
+        ("probes", ctypes.c_uint64),
+        ("steals", ctypes.c_uint64),
+        ("rows", ctypes.c_uint64),
+        ("kernel_ms", ctypes.c_double),
+        ("grid_waves", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("kernel_tasks", ctypes.c_uint64),
+        ("kernel_probes", ctypes.c_uint64),
+        ("kernel_groups", ctypes.c_uint64),
+    ]
+
+
+@dataclasses.dataclass
+class Result:
+    count: int
+    outcome: int
+    pool_depth: int
+    search_ms: float
+    pool_rows: int
+    groups: int
+    tasks: int
+    lanes_active: int
+    lanes_issued: int
+    probes: int
+    steals: int
+    rows: int
+    kernel_ms: float
+    grid_waves: int
+    kernel_tasks: int = 0
+    kernel_probes: int = 0
+    kernel_groups: int = 0
+    matches: Optional[np.ndarray] = None
+
+    @property
+    def idle_rate(self) -> float:
+        return 1.0 - self.lanes_active / self.lanes_issued if self.lanes_issued else 0.0
+
+
+_lib = None
+
+
+def load_library():
+    """Load libgmatch.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2604_10601_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    p, i32, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
+    lib.gm_create.argtypes = [i32, ctypes.POINTER(Options), ctypes.POINTER(p)]
+    lib.gm_destroy.argtypes = [p]
+    lib.gm_destroy.restype = None
+    lib.gm_load_graph.argtypes = [p, i32, p, p, p]
+    lib.gm_load_query.argtypes = [p, i32, i32, p, p, ctypes.POINTER(i32)]
+    lib.gm_set_order.argtypes = [p, i32, p]
+    lib.gm_get_order.argtypes = [p, i32, p]
+    lib.gm_count.argtypes = [p, i32, u64, dbl, ctypes.POINTER(_CResult)]
+    lib.gm_enumerate.argtypes = [p, i32, p, u64, dbl, ctypes.POINTER(_CResult)]
+    lib.gm_free_query.argtypes = [p, i32]
+    lib.gm_last_error.argtypes = [p]
+    lib.gm_last_error.restype = ctypes.c_char_p
+    for name in ("gm_create", "gm_load_graph", "gm_load_query", "gm_set_order", "gm_get_order", "gm_count",
+                 "gm_enumerate", "gm_free_query"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Engine:
+    """One resident data graph on one GPU (device=-1: host-only checks and planning)."""
+
+    def __init__(self, device: int = 0, tau: int = 0, pool_row_limit: int = 0, disable_stealing: bool = False,
+                 steal_threshold: int = 0, waves_per_cu: int = 0, skip_symmetry_check: bool = False,
+                 linear_probe_len: int = 0):
+        self._lib = load_library()
+        opt = Options()
+        opt.tau = tau
+        opt.pool_row_limit = pool_row_limit
+        opt.disable_stealing = int(disable_stealing)
+        opt.steal_threshold = steal_threshold
+        opt.waves_per_cu = waves_per_cu
+        opt.skip_symmetry_check = int(skip_symmetry_check)
+        opt.linear_probe_len = linear_probe_len
+        h = ctypes.c_void_p()
+        st = self._lib.gm_create(device, ctypes.byref(opt), ctypes.byref(h))
+        if st != GM_OK:
+            raise GmError(st, self._lib.gm_last_error(None).decode())
+        self._h = h
+        self._k = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.gm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, st: int):
+        if st != GM_OK:
+            raise GmError(st, self._lib.gm_last_error(self._h).decode())
+
+    def load_graph(self, row_ptr, col, labels) -> None:
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        lb = np.ascontiguousarray(labels, dtype=np.int32)
+        self._check(self._lib.gm_load_graph(self._h, rp.shape[0] - 1, _ptr(rp), _ptr(cl), _ptr(lb)))
+
+    def load_query(self, k: int, edges, labels) -> int:
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+        lb = np.ascontiguousarray(labels, dtype=np.int32)
+        qid = ctypes.c_int32()
+        self._check(self._lib.gm_load_query(self._h, k, e.shape[0], _ptr(e), _ptr(lb), ctypes.byref(qid)))
+        self._k[qid.value] = k
+        return qid.value
+
+    def set_order(self, qid: int, order: Optional[Sequence[int]]) -> None:
+        o = None if order is None else np.ascontiguousarray(order, dtype=np.int32)
+        self._check(self._lib.gm_set_order(self._h, qid, _ptr(o)))
+
+    def get_order(self, qid: int) -> np.ndarray:
+        out = np.zeros(self._k.get(qid, 32), dtype=np.int32)
+        self._check(self._lib.gm_get_order(self._h, qid, _ptr(out)))
+        return out
+
+    @staticmethod
+    def _result(r: _CResult, matches=None) -> Result:
+        return Result(int(r.count), int(r.outcome), int(r.pool_depth), float(r.search_ms), int(r.pool_rows),
+                      int(r.groups), int(r.tasks), int(r.lanes_active), int(r.lanes_issued), int(r.probes),
+                      int(r.steals), int(r.rows), float(r.kernel_ms), int(r.grid_waves), int(r.kernel_tasks),
+                      int(r.kernel_probes), int(r.kernel_groups), matches)
+
+    def count(self, qid: int, cap: int = 0, time_limit_s: float = 0.0) -> Result:
+        r = _CResult()
+        self._check(self._lib.gm_count(self._h, qid, int(cap), float(time_limit_s), ctypes.byref(r)))
+        return self._result(r)
+
+    def enumerate(self, qid: int, cap: int, time_limit_s: float = 0.0) -> Result:
+        k = self._k.get(qid, 1)
+        rows = np.zeros((int(cap), k), dtype=np.int32)
+        r = _CResult()
+        self._check(self._lib.gm_enumerate(self._h, qid, _ptr(rows), int(cap), float(time_limit_s),
+                                           ctypes.byref(r)))
+        return self._result(r, rows[: int(r.rows)])
+
+    def free_query(self, qid: int) -> None:
+        self._check(self._lib.gm_free_query(self._h, qid))
+        self._k.pop(qid, None)
+
+    # convenience for workloads.Graph / workloads.Query
+    def load(self, g) -> None:
+        self.load_graph(g.row_ptr, g.col, g.labels)
+
+    def add(self, q) -> int:
+        return self.load_query(q.k, q.edges, q.labels)

@@ -1,0 +1,79 @@
+// Types shared by the host engine (engine.cpp) and the gfx950 kernels (kernels.hip).
+#pragma once
+
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace gm {
+
+constexpr int kMaxK = 32;  // largest query supported
+constexpr int kWave = 64;  // CDNA wavefront width
+
+// Packed per-vertex record, one 8-byte load per candidate:
+//   x = first adjacency slot of v in col[], y = (degree << 8) | compact label.
+using VInfo = uint2;
+
+__host__ __device__ inline uint32_t vi_deg(VInfo a) { return a.y >> 8; }
+__host__ __device__ inline uint32_t vi_lab(VInfo a) { return a.y & 0xffu; }
+
+// Query along the matching order: position i maps query vertex phi[i].
+struct Plan {
+    int32_t k;                // query size
+    int32_t depth;            // matched positions per pool row (>= 1)
+    int32_t phi[kMaxK];       // query vertex at position i
+    int32_t lab[kMaxK];       // compact label of phi[i] (255 = absent from G)
+    int32_t qdeg[kMaxK];      // query degree of phi[i] (degree filter)
+    uint32_t bwd[kMaxK];      // bit j set: phi[j] (j < i) is a backward neighbour of phi[i]
+};
+
+// Device-resident control block, cleared before every search.
+struct Control {
+    unsigned long long count;        // matches found (flushed by wavefronts)
+    unsigned long long pool_next;    // next unclaimed pool row
+    unsigned long long out_rows;     // rows appended (root scan, expansion, enumerate)
+    unsigned long long measure;      // expansion bound: sum of |C^L| over pool rows
+    unsigned long long groups;
+    unsigned long long tasks;
+    unsigned long long lanes_active;
+    unsigned long long lanes_issued;
+    unsigned long long probes;
+    unsigned long long steals;
+    unsigned int abort;              // 0 running, 1 cap reached, 2 time limit
+    unsigned int busy;               // wavefronts holding work + queued donations
+    unsigned long long t0;           // device wall clock when the root scan started
+    unsigned long long pad[3];
+};
+
+enum : unsigned int { kAbortNone = 0, kAbortCap = 1, kAbortTime = 2 };
+
+// Arguments of every search kernel (passed by value in the kernarg segment).
+struct SearchArgs {
+    const VInfo *vinfo;        // [n]
+    const int32_t *col;        // [nnz]
+    const int32_t *pool;       // [pool_rows * depth]
+    unsigned long long pool_rows;
+    int32_t *out;              // expansion: next pool; enumerate: rows
+    unsigned long long out_cap; // rows that fit in out
+    Control *ctl;
+    unsigned long long cap;    // 0 = none
+    unsigned long long flush;  // local matches kept before an atomic flush
+    unsigned long long budget; // time limit in device wall-clock ticks from ctl->t0, 0 = none
+    void *steal;               // donation slots (work stealing), or null
+    int32_t steal_slots;
+    int32_t steal_threshold;
+    int32_t linear_probe;      // lists this short are scanned, longer ones bisected
+    int32_t pad0;
+    Plan plan;
+};
+
+// Launchers implemented in kernels.hip.  All return hipSuccess or the launch error.
+hipError_t launch_root_scan(const VInfo *vinfo, int32_t n, int32_t lab0, int32_t qdeg0, int32_t *pool,
+                            int count_only, Control *ctl, int num_cu, hipStream_t s);
+hipError_t launch_measure(const SearchArgs &a, int num_cu, hipStream_t s);
+hipError_t launch_expand(const SearchArgs &a, int num_cu, hipStream_t s);
+hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int waves_per_cu, hipStream_t s,
+                         int *grid_waves_out);
+size_t steal_slot_bytes();
+
+}  // namespace gm

@@ -1,0 +1,508 @@
+// gfx950 (CDNA4) kernels of the matching engine.
+//
+// Method (gMatch paper, arXiv 2604.10601):
+//   * Fine-grained tasks (Sec. 4.1): extending a partial match M by the next query
+//     vertex u is split into one task per local candidate v in C^L_M(u), the
+//     neighbour list of the backward neighbour whose image has the fewest
+//     neighbours.  One lane validates one task.
+//   * Batch exploration (Sec. 4.2, Alg. 2): a wavefront keeps up to 64 partial
+//     matches per level in an LDS stack S[level][lane] = {v, parent lane}; the
+//     task groups of all of them form one virtual task pool that two cursors
+//     (parent lane, offset in its list) walk 64 tasks at a time.  Partial
+//     matches are rebuilt by following parent pointers down the stack.
+//   * Initial pool (Sec. 4.3): partial matches are first expanded breadth-first
+//     until a level holds at least tau of them; wavefronts then claim pool rows
+//     with an atomic counter.
+//
+// gfx950 design, which differs from the paper's 32-lane CUDA design:
+//   * 64-lane wavefronts: the stack is K x 64, ballots are 64-bit.
+//   * ScatterTask is done by the whole wavefront at once instead of a serial
+//     loop on one lane: an exclusive scan of the per-parent remaining list
+//     lengths (clamped to 64, so seven ballots + mbcnt give the scan), a start
+//     marker per parent in LDS, and a find-last-set per lane give every lane
+//     its parent and offset.
+//   * A wavefront claims 64 pool rows at a time, one per lane, so the first
+//     level is already a full batch.
+//   * Each stack entry caches the start and length of its vertex's neighbour
+//     list, so GenerateTask and the membership tests read no vertex records.
+//   * Per-vertex data is one packed 8-byte record (list start, degree, label):
+//     a single load decides the label and degree filters.
+//   * Membership is bisection while the remaining range is longer than a few
+//     entries, then one batch of independent loads (fewer dependent round trips).
+//   * The search is one persistent launch; waves exit when the pool is empty,
+//     or when the cap or the time limit sets the abort word.
+#include <hip/hip_runtime.h>
+
+#include "gm_internal.h"
+
+namespace gm {
+
+namespace {
+
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kLinear = 8;  // longest list tail scanned with independent loads
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
+
+// Number of set bits of m below this lane.
+__device__ __forceinline__ uint32_t popc_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Value of lane `src` (wave-uniform index) for every lane.
+__device__ __forceinline__ uint32_t read_lane(uint32_t x, uint32_t src) {
+    return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), static_cast<int>(src)));
+}
+
+__device__ __forceinline__ unsigned long long read_lane64(unsigned long long x, uint32_t src) {
+    uint32_t lo = read_lane(static_cast<uint32_t>(x), src);
+    uint32_t hi = read_lane(static_cast<uint32_t>(x >> 32), src);
+    return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
+// Value held by lane `src` (per-lane index), through the LDS crossbar.
+__device__ __forceinline__ uint32_t shfl(uint32_t x, uint32_t src) {
+    return static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(static_cast<int>(src << 2), static_cast<int>(x)));
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
+    for (int off = 32; off >= 1; off >>= 1) {
+        uint32_t lo = static_cast<uint32_t>(x), hi = static_cast<uint32_t>(x >> 32);
+        uint32_t src = lane_id() ^ off;
+        lo = shfl(lo, src);
+        hi = shfl(hi, src);
+        x += (static_cast<uint64_t>(hi) << 32) | lo;
+    }
+    return x;
+}
+
+// Is v in the ascending list col[lo, lo + n)?  Adds the 4-byte reads made to probes.
+__device__ __forceinline__ bool list_contains(const int32_t *__restrict__ col, uint32_t lo, uint32_t n, int32_t v,
+                                              uint32_t lin, uint32_t &probes) {
+    while (n > lin) {
+        uint32_t h = n >> 1;
+        int32_t x = col[lo + h];
+        ++probes;
+        if (x == v) return true;
+        if (x < v) {
+            lo += h + 1;
+            n -= h + 1;
+        } else {
+            n = h;
+        }
+    }
+    if (n == 0) return false;
+    // n <= kLinear: independent loads, indices clamped into the list
+    bool f = false;
+#pragma unroll
+    for (uint32_t i = 0; i < kLinear; ++i) {
+        uint32_t idx = lo + (i < n ? i : n - 1);
+        f |= (col[idx] == v);
+    }
+    probes += n;
+    return f;
+}
+
+// Per-wavefront stack in LDS (Sec. 5.1: S is |V(Q)| x warp width).
+template <int K>
+struct WaveStack {
+    int32_t v[K][kWave];     // data vertex of the task at (level, lane)
+    uint32_t st[K][kWave];   // start of N(v) in col[]
+    uint32_t dg[K][kWave];   // |N(v)|
+    uint8_t pid[K][kWave];   // lane of the parent entry at level - 1
+    uint8_t cj[K][kWave];    // local candidate list of parent lane: source level (0xff = none)
+    uint8_t cq[K][kWave];    //   ... and source lane at that level
+    uint32_t cur_j[K];       // scatter cursor: offset in the current parent's list
+    uint32_t cur_i[K];       // scatter cursor: current parent lane (64 = level exhausted)
+    uint8_t own[kWave];      // scatter scratch: parent starting at each slot
+};
+
+// GenerateTask (Alg. 2): for every parent lane in F at level l-1, pick the
+// backward neighbour with the fewest neighbours (earliest position on ties) and
+// record its list as the parent's local candidate set at level l.  Returns the
+// list length for this lane (0 if the lane is not a parent).
+template <int K>
+__device__ __forceinline__ uint32_t generate_tasks(WaveStack<K> &S, const Plan &P, int l, uint64_t F,
+                                                   uint32_t lane) {
+    uint32_t len = 0;
+    uint32_t bj = 0xffu, bq = 0;
+    if ((F >> lane) & 1ull) {
+        const uint32_t bw = P.bwd[l];
+        const int lowest = __builtin_ctz(bw);
+        uint32_t q = lane;
+        uint32_t best = 0xffffffffu;
+        for (int i = l - 1; i >= lowest; --i) {
+            if ((bw >> i) & 1u) {
+                uint32_t d = S.dg[i][q];
+                if (d <= best) {
+                    best = d;
+                    bj = static_cast<uint32_t>(i);
+                    bq = q;
+                }
+            }
+            q = S.pid[i][q];
+        }
+        len = best;
+    }
+    S.cj[l][lane] = static_cast<uint8_t>(bj);
+    S.cq[l][lane] = static_cast<uint8_t>(bq);
+    return len;
+}
+
+struct Round {
+    uint32_t ntask;  // tasks this round (0: level exhausted)
+    uint32_t owner;  // parent lane of this lane's task
+    int32_t v;       // candidate of this lane's task (valid if lane < ntask)
+};
+
+// ScatterTask (Alg. 2) for the whole wavefront: hand the next <= 64 tasks of
+// level l to lanes 0..ntask-1 and advance the level's cursor.
+template <int K>
+__device__ __forceinline__ Round scatter(WaveStack<K> &S, const int32_t *__restrict__ col, int l, uint32_t lane) {
+    Round r;
+    const uint32_t ci = __builtin_amdgcn_readfirstlane(S.cur_i[l]);
+    const uint32_t cjo = __builtin_amdgcn_readfirstlane(S.cur_j[l]);
+    uint32_t cst = 0, cln = 0;
+    const uint32_t sj = S.cj[l][lane];
+    if (sj != 0xffu) {
+        const uint32_t sq = S.cq[l][lane];
+        cst = S.st[sj][sq];
+        cln = S.dg[sj][sq];
+    }
+    uint32_t rem = lane < ci ? 0u : (lane == ci ? cln - cjo : cln);
+    uint32_t rc = rem < 64u ? rem : 64u;
+    // exclusive scan of rc (values <= 64: seven bit planes)
+    uint32_t ex = 0, tot = 0;
+#pragma unroll
+    for (int b = 0; b < 7; ++b) {
+        uint64_t m = ballot((rc >> b) & 1u);
+        ex += popc_below(m) << b;
+        tot += static_cast<uint32_t>(__popcll(m)) << b;
+    }
+    if (tot == 0) {
+        r.ntask = 0;
+        r.owner = 0;
+        r.v = -1;
+        return r;
+    }
+    r.ntask = tot < 64u ? tot : 64u;
+    volatile uint8_t *own = S.own;
+    own[lane] = 0xffu;
+    __builtin_amdgcn_wave_barrier();
+    if (rc != 0u && ex < 64u) own[ex] = static_cast<uint8_t>(lane);
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t o = own[lane];
+    const uint64_t starts = ballot(o != 0xffu);
+    const uint64_t upto = lane == 63u ? ~0ull : ((2ull << lane) - 1ull);
+    const uint32_t s = 63u - static_cast<uint32_t>(__clzll(starts & upto));
+    const uint32_t owner = shfl(o, s);
+    const uint32_t ocst = shfl(cst, owner);
+    const uint32_t j = lane - s + (owner == ci ? cjo : 0u);
+    r.owner = owner;
+    r.v = lane < r.ntask ? col[ocst + j] : -1;
+    // advance the cursor past slot 63
+    if (tot > 64u) {
+        const uint32_t p63 = read_lane(owner, 63);
+        const uint32_t s63 = read_lane(s, 63);
+        const uint32_t used = 64u - s63 + (p63 == ci ? cjo : 0u);
+        const uint32_t len63 = read_lane(cln, p63);
+        if (lane == 0) {
+            if (used >= len63) {
+                S.cur_i[l] = p63 + 1;
+                S.cur_j[l] = 0;
+            } else {
+                S.cur_i[l] = p63;
+                S.cur_j[l] = used;
+            }
+        }
+    } else if (lane == 0) {
+        S.cur_i[l] = 64;
+    }
+    return r;
+}
+
+// Process (Alg. 2): label and degree filters, then one walk down the parent
+// chain checking injectivity and membership in every backward neighbour's list
+// other than the one the candidate came from.
+template <int K>
+__device__ __forceinline__ bool process(WaveStack<K> &S, const SearchArgs &a, int l, const Round &r, uint32_t lane,
+                                        VInfo &vi, uint32_t &probes) {
+    bool ok = lane < r.ntask;
+    vi = make_uint2(0u, 0u);
+    if (ok) vi = a.vinfo[r.v];
+    ok = ok && vi_lab(vi) == static_cast<uint32_t>(a.plan.lab[l]) &&
+         vi_deg(vi) >= static_cast<uint32_t>(a.plan.qdeg[l]);
+    if (ok) {
+        const uint32_t bw = a.plan.bwd[l];
+        const uint32_t js = S.cj[l][r.owner];
+        uint32_t q = r.owner;
+        for (int i = l - 1; i >= 0; --i) {
+            const int32_t w = S.v[i][q];
+            if (w == r.v) {
+                ok = false;
+                break;
+            }
+            if (((bw >> i) & 1u) && static_cast<uint32_t>(i) != js) {
+                if (!list_contains(a.col, S.st[i][q], S.dg[i][q], r.v, a.linear_probe, probes)) {
+                    ok = false;
+                    break;
+                }
+            }
+            q = S.pid[i][q];
+        }
+    }
+    return ok;
+}
+
+__device__ __forceinline__ unsigned long long lane0_atomic_add(unsigned long long *p, unsigned long long x) {
+    unsigned long long old = 0;
+    if (lane_id() == 0) old = atomicAdd(p, x);
+    return read_lane64(old, 0);
+}
+
+__device__ __forceinline__ unsigned int load_abort(Control *ctl) {
+    unsigned int v = 0;
+    if (lane_id() == 0) v = __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return read_lane(v, 0);
+}
+
+__device__ __forceinline__ void set_abort(Control *ctl, unsigned int why) {
+    if (lane_id() == 0) atomicCAS(&ctl->abort, kAbortNone, why);
+}
+
+enum Mode { kCount = 0, kEnumerate = 1, kExpand = 2 };
+
+// Persistent search.  Every wavefront loops: claim 64 pool rows, load them as
+// the bottom of its stack, and run Alg. 2's Search iteratively until the stack
+// is empty.  kExpand stops at the pool level and appends the valid extensions
+// to the next pool instead (one breadth-first step of the initialisation).
+template <int K, int MODE>
+__global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
+    __shared__ WaveStack<K> stacks[kWavesPerBlock];
+    WaveStack<K> &S = stacks[threadIdx.x / kWave];
+    const uint32_t lane = lane_id();
+    const int k = a.plan.k;
+    const int d = a.plan.depth;
+    Control *ctl = a.ctl;
+
+    uint64_t my_tasks = 0;
+    uint32_t my_probes = 0;
+    uint64_t my_probes_total = 0;
+    uint64_t w_groups = 0, w_active = 0, w_issued = 0, w_count = 0;
+    uint32_t rounds = 0;
+    bool stop = false;
+    const unsigned long long deadline = a.budget ? a.ctl->t0 + a.budget : 0ull;
+
+    while (!stop) {
+        unsigned long long r0 = lane0_atomic_add(&ctl->pool_next, kWave);
+        if (r0 >= a.pool_rows) break;
+        const unsigned long long left = a.pool_rows - r0;
+        const uint32_t nrows = left < kWave ? static_cast<uint32_t>(left) : kWave;
+        const bool have = lane < nrows;
+        for (int i = 0; i < d; ++i) {
+            int32_t v = 0;
+            VInfo vi = make_uint2(0u, 0u);
+            if (have) {
+                v = a.pool[(r0 + lane) * static_cast<unsigned long long>(d) + i];
+                vi = a.vinfo[v];
+            }
+            S.v[i][lane] = v;
+            S.st[i][lane] = vi.x;
+            S.dg[i][lane] = vi_deg(vi);
+            S.pid[i][lane] = static_cast<uint8_t>(lane);
+        }
+        const uint64_t F0 = ballot(have);
+        my_tasks += generate_tasks(S, a.plan, d, F0, lane);
+        w_groups += __popcll(F0);
+        if (lane == 0) {
+            S.cur_i[d] = 0;
+            S.cur_j[d] = 0;
+        }
+        int l = d;
+        while (l >= d) {
+            const Round r = scatter(S, a.col, l, lane);
+            if (r.ntask == 0) {
+                --l;
+                continue;
+            }
+            w_active += r.ntask;
+            w_issued += kWave;
+            VInfo vi;
+            const bool ok = process(S, a, l, r, lane, vi, my_probes);
+            const uint64_t m = ballot(ok);
+            if (MODE == kExpand) {
+                if (m) {
+                    const unsigned long long base = lane0_atomic_add(&ctl->out_rows, __popcll(m));
+                    const unsigned long long slot = base + popc_below(m);
+                    if (ok && slot < a.out_cap) {
+                        int32_t *row = a.out + slot * static_cast<unsigned long long>(d + 1);
+                        for (int i = 0; i < d; ++i) row[i] = S.v[i][r.owner];
+                        row[d] = r.v;
+                    }
+                }
+            } else if (l == k - 1) {
+                if (MODE == kEnumerate && m) {
+                    const unsigned long long base = lane0_atomic_add(&ctl->out_rows, __popcll(m));
+                    const unsigned long long slot = base + popc_below(m);
+                    if (ok && slot < a.out_cap) {
+                        int32_t *row = a.out + slot * static_cast<unsigned long long>(k);
+                        row[a.plan.phi[l]] = r.v;
+                        uint32_t q = r.owner;
+                        for (int i = l - 1; i >= 0; --i) {
+                            row[a.plan.phi[i]] = S.v[i][q];
+                            q = S.pid[i][q];
+                        }
+                    }
+                }
+                w_count += __popcll(m);
+            } else if (m) {
+                S.v[l][lane] = r.v;
+                S.st[l][lane] = vi.x;
+                S.dg[l][lane] = vi_deg(vi);
+                S.pid[l][lane] = static_cast<uint8_t>(r.owner);
+                my_tasks += generate_tasks(S, a.plan, l + 1, m, lane);
+                w_groups += __popcll(m);
+                if (lane == 0) {
+                    S.cur_i[l + 1] = 0;
+                    S.cur_j[l + 1] = 0;
+                }
+                ++l;
+            }
+            ++rounds;
+            if (w_count >= a.flush || (rounds & 31u) == 0) {
+                if (w_count) {
+                    const unsigned long long before = lane0_atomic_add(&ctl->count, w_count);
+                    if (a.cap && before + w_count >= a.cap) set_abort(ctl, kAbortCap);
+                    w_count = 0;
+                }
+                if ((rounds & 31u) == 0) {
+                    if (deadline && wall_clock64() > deadline) set_abort(ctl, kAbortTime);
+                    if (load_abort(ctl) != kAbortNone) stop = true;
+                }
+                my_probes_total += my_probes;
+                my_probes = 0;
+                if (stop) break;
+            }
+        }
+    }
+    my_probes_total += my_probes;
+    const uint64_t tasks = wave_sum64(my_tasks);
+    const uint64_t probes = wave_sum64(my_probes_total);
+    if (lane == 0) {
+        if (w_count) atomicAdd(&ctl->count, w_count);
+        atomicAdd(&ctl->groups, w_groups);
+        atomicAdd(&ctl->tasks, tasks);
+        atomicAdd(&ctl->lanes_active, w_active);
+        atomicAdd(&ctl->lanes_issued, w_issued);
+        atomicAdd(&ctl->probes, probes);
+    }
+}
+
+// Candidates of the first query vertex: label and degree filter over all of V(G).
+__global__ __launch_bounds__(256) void root_scan_kernel(const VInfo *__restrict__ vinfo, int32_t n, int32_t lab0,
+                                                        int32_t qdeg0, int32_t *__restrict__ pool, int count_only,
+                                                        Control *ctl) {
+    const uint32_t lane = lane_id();
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->t0 = wall_clock64();
+    const long long stride = static_cast<long long>(gridDim.x) * blockDim.x;
+    for (long long base = static_cast<long long>(blockIdx.x) * blockDim.x + (threadIdx.x & ~(kWave - 1)); base < n;
+         base += stride) {
+        const long long v = base + lane;
+        bool ok = false;
+        if (v < n) {
+            const VInfo vi = vinfo[v];
+            ok = vi_lab(vi) == static_cast<uint32_t>(lab0) && vi_deg(vi) >= static_cast<uint32_t>(qdeg0);
+        }
+        const uint64_t m = ballot(ok);
+        if (m) {
+            const unsigned long long b = lane0_atomic_add(&ctl->out_rows, __popcll(m));
+            if (ok && !count_only) pool[b + popc_below(m)] = static_cast<int32_t>(v);
+        }
+    }
+}
+
+// Upper bound on the size of the next pool level: sum over rows of |C^L|.
+__global__ __launch_bounds__(256) void measure_kernel(SearchArgs a) {
+    const int d = a.plan.depth;
+    const uint32_t bw = a.plan.bwd[d];
+    uint64_t sum = 0;
+    const unsigned long long stride = static_cast<unsigned long long>(gridDim.x) * blockDim.x;
+    for (unsigned long long r = static_cast<unsigned long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+         r < a.pool_rows; r += stride) {
+        uint32_t best = 0xffffffffu;
+        for (int i = 0; i < d; ++i) {
+            if ((bw >> i) & 1u) {
+                const uint32_t dg = vi_deg(a.vinfo[a.pool[r * static_cast<unsigned long long>(d) + i]]);
+                best = dg < best ? dg : best;
+            }
+        }
+        sum += best;
+    }
+    sum = wave_sum64(sum);
+    if (lane_id() == 0 && sum) atomicAdd(&a.ctl->measure, static_cast<unsigned long long>(sum));
+}
+
+
+template <int K, int MODE>
+hipError_t launch_persistent(const SearchArgs &a, int num_cu, int waves_per_cu, hipStream_t s, int *grid_waves) {
+    auto kern = search_kernel<K, MODE>;
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    if (waves_per_cu > 0) {
+        int want = (waves_per_cu + kWavesPerBlock - 1) / kWavesPerBlock;
+        if (want < per_cu) per_cu = want;
+    }
+    const int blocks = num_cu * per_cu;
+    if (grid_waves) *grid_waves = blocks * kWavesPerBlock;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_levels(int levels, const SearchArgs &a, int num_cu, int waves_per_cu, hipStream_t s,
+                         int *grid_waves) {
+    if (levels <= 8) return launch_persistent<8, MODE>(a, num_cu, waves_per_cu, s, grid_waves);
+    if (levels <= 16) return launch_persistent<16, MODE>(a, num_cu, waves_per_cu, s, grid_waves);
+    if (levels <= kMaxK) return launch_persistent<32, MODE>(a, num_cu, waves_per_cu, s, grid_waves);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_root_scan(const VInfo *vinfo, int32_t n, int32_t lab0, int32_t qdeg0, int32_t *pool,
+                            int count_only, Control *ctl, int num_cu, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    long long blocks = (static_cast<long long>(n) + 255) / 256;
+    if (blocks > num_cu * 8LL) blocks = num_cu * 8LL;
+    hipLaunchKernelGGL(root_scan_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, vinfo, n, lab0,
+                       qdeg0, pool, count_only, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_measure(const SearchArgs &a, int num_cu, hipStream_t s) {
+    if (a.pool_rows == 0) return hipSuccess;
+    unsigned long long blocks = (a.pool_rows + 255) / 256;
+    if (blocks > static_cast<unsigned long long>(num_cu) * 8ull) blocks = static_cast<unsigned long long>(num_cu) * 8ull;
+    hipLaunchKernelGGL(measure_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand(const SearchArgs &a, int num_cu, hipStream_t s) {
+    return launch_levels<kExpand>(a.plan.depth + 1, a, num_cu, 0, s, nullptr);
+}
+
+hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int waves_per_cu, hipStream_t s,
+                         int *grid_waves_out) {
+    if (enumerate) return launch_levels<kEnumerate>(a.plan.k, a, num_cu, waves_per_cu, s, grid_waves_out);
+    return launch_levels<kCount>(a.plan.k, a, num_cu, waves_per_cu, s, grid_waves_out);
+}
+
+size_t steal_slot_bytes() { return 0; }
+
+}  // namespace gm
