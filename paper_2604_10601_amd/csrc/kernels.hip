@@ -204,8 +204,9 @@ __device__ __forceinline__ Round scatter(WaveStack<K> &S, const int32_t *__restr
     const uint32_t j = lane - s + (owner == ci ? cjo : 0u);
     r.owner = owner;
     r.v = lane < r.ntask ? col[ocst + j] : -1;
-    // advance the cursor past slot 63
-    if (tot > 64u) {
+    // advance the cursor past slot 63; rc is clamped, so a lone parent with more
+    // than 64 tasks left shows up only in rem
+    if (tot > 64u || ballot(rem > rc) != 0ull) {
         const uint32_t p63 = read_lane(owner, 63);
         const uint32_t s63 = read_lane(s, 63);
         const uint32_t used = 64u - s63 + (p63 == ci ? cjo : 0u);

@@ -221,6 +221,23 @@ def test_degenerate_inputs(engine):
     assert engine.count(qid).count == 0
 
 
+@pytest.mark.parametrize("tau", [-1, 0])
+def test_single_parent_with_long_list(tau):
+    """One parent whose local candidate list is much longer than a wavefront, alone
+    in its scatter rounds (star centre, 1000 leaves, edge query)."""
+    g = S.star_graph(1000)
+    with gm.Engine(device=0, tau=tau) as e:
+        e.load(g)
+        qid = e.add(S.path_q(2))
+        r = e.count(qid)
+        assert (r.count, r.groups, r.tasks) == (2000, 1001, 2000)
+        qid = e.add(S.path_q(3))
+        r = e.count(qid)
+        o = oracle.count(g, S.path_q(3), order=e.get_order(qid))
+        assert r.count == 1000 * 999   # paths leaf-centre-leaf
+        assert_same(r, o)
+
+
 def test_hub_and_long_lists():
     """A hub (label 0) with 5000 neighbours: 119 core vertices (label 1, dense among
     themselves) and 4881 leaves (label 2).  Lists are far longer than a wavefront and
