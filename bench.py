@@ -98,8 +98,70 @@ def cpu_baseline(w, phis, budget_s: float, cap: int, per_query_s: float) -> dict
         capped += r.outcome == oracle.CAPPED
     rate = total / secs if secs > 0 else 0.0
     return {"value": rate, "unit": "embeddings/s", "cores": threads, "kind": "oracle",
-            "sample": (f"first {used} of the {len(w.queries)} queries, each capped at {cap} embeddings and "
-                       f"{per_query_s} s ({capped} reached the cap); {secs:.1f} s of oracle time")}
+            "sample": (f"first {used} of the {len(w.queries)} queries in workload order, each with the "
+                       f"workload's cap ({cap}) and at most {per_query_s} s ({capped} reached the cap); "
+                       f"stopped after {secs:.1f} s of oracle time")}
+
+
+def copy_probe(nbytes: int) -> None:
+    """One device-to-device copy of nbytes (a plain copy kernel of known size, used to
+    calibrate the FETCH_SIZE / WRITE_SIZE counters)."""
+    hip = ctypes.CDLL("libamdhip64.so")
+    src, dst = ctypes.c_void_p(), ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(src), ctypes.c_size_t(nbytes)) == 0
+    assert hip.hipMalloc(ctypes.byref(dst), ctypes.c_size_t(nbytes)) == 0
+    assert hip.hipMemset(src, 1, ctypes.c_size_t(nbytes)) == 0
+    assert hip.hipDeviceSynchronize() == 0
+    assert hip.hipMemcpy(dst, src, ctypes.c_size_t(nbytes), 3) == 0   # device to device
+    assert hip.hipDeviceSynchronize() == 0
+    hip.hipFree(src)
+    hip.hipFree(dst)
+
+
+def _csvs(root: str, suffix: str):
+    import glob
+    return sorted(glob.glob(os.path.join(root, "**", f"*{suffix}"), recursive=True))
+
+
+def kernel_key(name: str) -> str:
+    """Short name of a dispatched kernel: search kernels by mode, copies, others by function name."""
+    import re
+    m = re.search(r"search_kernel<(\d+), (\d+)>", name)
+    if m:
+        return {"0": "search", "1": "enumerate", "2": "expand"}[m.group(2)] + f"<K={m.group(1)}>"
+    if "copyBuffer" in name:
+        return "copy"
+    base = name[:-1].rsplit("(", 1)[0] if name.endswith(")") else name
+    return base.replace("gm::(anonymous namespace)::", "").replace("void ", "")
+
+
+def summarize_stats(root: str) -> str:
+    """Kernel table from a rocprofv3 --kernel-trace --stats run (csv output)."""
+    import csv
+    lines = []
+    for path in _csvs(root, "kernel_stats.csv"):
+        for row in csv.DictReader(open(path)):
+            lines.append(f"{kernel_key(row.get('Name', '')):<34} calls={row.get('Calls'):>5} "
+                         f"total_ms={float(row.get('TotalDurationNs', 0)) / 1e6:10.3f} "
+                         f"avg_ms={float(row.get('AverageNs', 0)) / 1e6:9.4f} "
+                         f"min_ms={float(row.get('MinNs', 0)) / 1e6:9.4f} "
+                         f"max_ms={float(row.get('MaxNs', 0)) / 1e6:9.4f} pct={float(row.get('Percentage', 0)):6.2f}")
+    return "\n".join(lines)
+
+
+def pmc_per_kernel(root: str, counter: str) -> dict:
+    """Mean counter value per dispatch for each kernel key; for the calibration copy, the largest dispatch."""
+    import csv
+    acc = {}
+    for path in _csvs(root, "counter_collection.csv"):
+        for row in csv.DictReader(open(path)):
+            if row.get("Counter_Name") != counter:
+                continue
+            acc.setdefault(kernel_key(row.get("Kernel_Name", "")), []).append(float(row["Counter_Value"]))
+    out = {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+    if "copy" in acc:
+        out["copy"] = (max(acc["copy"]), 1)
+    return out
 
 
 def main() -> int:
@@ -113,7 +175,37 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tau", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the timed steps, copy this many MiB device-to-device (counter calibration)")
+    ap.add_argument("--summarize-stats", metavar="DIR", help="print the kernel table of a rocprofv3 --stats run")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print HBM traffic per search launch from two rocprofv3 --pmc runs")
+    ap.add_argument("--copy-bytes", type=int, default=0, help="size of the calibration copy in those runs")
     args = ap.parse_args()
+
+    if args.summarize_stats:
+        print(summarize_stats(args.summarize_stats))
+        return 0
+    if args.summarize_traffic:
+        fetch = pmc_per_kernel(args.summarize_traffic[0], "FETCH_SIZE")
+        write = pmc_per_kernel(args.summarize_traffic[1], "WRITE_SIZE")
+        key = next(k for k in fetch if k.startswith("search<"))
+        f_search, n_f = fetch[key]
+        w_search, n_w = write[key]
+        f_copy = fetch["copy"][0]
+        w_copy = write["copy"][0]
+        kf = args.copy_bytes / (f_copy * 1024.0)
+        kw = args.copy_bytes / (w_copy * 1024.0)
+        traffic = f_search * 1024.0 * kf + w_search * 1024.0 * kw
+        print(f"kernel: {key}")
+        print(f"kernel_sha: {kernel_sha()}")
+        print(f"search_fetch_kib_per_dispatch: {f_search:.1f}  (dispatches {n_f})")
+        print(f"search_write_kib_per_dispatch: {w_search:.1f}  (dispatches {n_w})")
+        print(f"copy_fetch_kib: {f_copy:.1f}  copy_write_kib: {w_copy:.1f}  copy_bytes: {args.copy_bytes}")
+        print(f"fetch_scale: {kf:.4f}")
+        print(f"write_scale: {kw:.4f}")
+        print(f"traffic_bytes_per_launch: {traffic:.0f}")
+        return 0
 
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -205,9 +297,10 @@ def main() -> int:
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(w, phis, args.cpu_seconds, min(cap, 1_000_000) if cap else 1_000_000,
-                                           per_query_s=5.0)
+        out["cpu_baseline"] = cpu_baseline(w, phis, args.cpu_seconds, cap, per_query_s=10.0)
     e.close()
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib << 20)
     print(json.dumps(out), flush=True)
     return 0
 
