@@ -175,6 +175,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tau", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--disable-stealing", action="store_true")
+    ap.add_argument("--steal-threshold", type=int, default=0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB device-to-device (counter calibration)")
     ap.add_argument("--summarize-stats", metavar="DIR", help="print the kernel table of a rocprofv3 --stats run")
@@ -218,7 +220,8 @@ def main() -> int:
     w = make_workload(args.workload, args.queries)
     log(f"workload {w.name}: n={w.graph.n} |E|={w.graph.num_edges} queries={len(w.queries)} "
         f"({time.time() - t:.1f} s to generate)")
-    e = gm.Engine(device=0, tau=args.tau, waves_per_cu=args.waves_per_cu)
+    e = gm.Engine(device=0, tau=args.tau, waves_per_cu=args.waves_per_cu,
+                  disable_stealing=args.disable_stealing, steal_threshold=args.steal_threshold)
     e.load(w.graph)
     qids = [e.add(q) for q in w.queries]
     phis = [e.get_order(qid) for qid in qids]
@@ -275,13 +278,14 @@ def main() -> int:
         "config": {"workload": w.name, "graph_vertices": w.graph.n, "graph_edges": w.graph.num_edges,
                    "queries": len(w.queries), "query_sizes": sorted({q.k for q in w.queries}),
                    "cap": cap, "time_limit_s": limit, "order": "RI heuristic",
-                   "tau": args.tau if args.tau else 1000000},
+                   "tau": args.tau if args.tau else 1000000, "work_stealing": not args.disable_stealing},
         "intersected_edges_per_s": tasks / wall,
         "query_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                              "mean": float(lat.mean())},
         "outcomes_per_step": outcomes,
         "solved_queries": len(solved) // max(1, args.steps),
         "idle_rate": 1.0 - sum(r.lanes_active for r in flat) / max(1, sum(r.lanes_issued for r in flat)),
+        "steals_per_step": sum(r.steals for r in flat) // max(1, args.steps),
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,

@@ -126,6 +126,8 @@ struct gm_engine {
     int32_t *d_rows = nullptr;
     size_t rows_cap = 0;           // in int32
     Control *d_ctl = nullptr;
+    gm::StealSlot *d_steal = nullptr;
+    int32_t steal_slots = 0;
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int num_cu = 0;
@@ -306,6 +308,19 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
     a.linear_probe = e->opt.linear_probe_len > 0 ? std::min(e->opt.linear_probe_len, 8) : 8;
     a.steal = nullptr;
     a.steal_slots = 0;
+    if (!e->opt.disable_stealing) {
+        if (!e->d_steal) {
+            const int32_t slots = 1024;
+            hipError_t h = hipMalloc(reinterpret_cast<void **>(&e->d_steal), sizeof(gm::StealSlot) * slots);
+            if (h != hipSuccess) {
+                e->d_steal = nullptr;
+                return e->fail(GM_ERR_NOMEM, "donation ring allocation failed");
+            }
+            e->steal_slots = slots;
+        }
+        a.steal = e->d_steal;
+        a.steal_slots = e->steal_slots;
+    }
     a.steal_threshold = e->opt.steal_threshold > 0 ? e->opt.steal_threshold : 128;
     a.plan = plan;
 
@@ -343,7 +358,8 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
         if (bound > static_cast<uint64_t>(row_limit)) break;
         st = ensure_buffer(e, &e->d_pool[cur ^ 1], &e->pool_cap[cur ^ 1], bound * static_cast<size_t>(depth + 1));
         if (st) return st;
-        HIP_TRY(e, hipMemsetAsync(&e->d_ctl->pool_next, 0, 2 * sizeof(unsigned long long), e->stream));
+        HIP_TRY(e, hipMemsetAsync(&e->d_ctl->pool_next, 0, sizeof(unsigned long long), e->stream));
+        HIP_TRY(e, hipMemsetAsync(&e->d_ctl->out_rows, 0, sizeof(unsigned long long), e->stream));
         a.out = e->d_pool[cur ^ 1];
         a.out_cap = bound;
         HIP_TRY(e, gm::launch_expand(a, e->num_cu, e->stream));
@@ -375,7 +391,9 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
             const unsigned long long per = cap / (static_cast<unsigned long long>(e->num_cu) * 64ull);
             a.flush = std::max<unsigned long long>(1, std::min<unsigned long long>(4096, per));
         }
-        HIP_TRY(e, hipMemsetAsync(&e->d_ctl->pool_next, 0, 2 * sizeof(unsigned long long), e->stream));
+        HIP_TRY(e, hipMemsetAsync(&e->d_ctl->pool_next, 0, sizeof(unsigned long long), e->stream));
+        HIP_TRY(e, hipMemsetAsync(&e->d_ctl->out_rows, 0, sizeof(unsigned long long), e->stream));
+        if (a.steal) HIP_TRY(e, gm::launch_steal_init(a.steal, a.steal_slots, e->stream));
         before = c;
         HIP_TRY(e, hipEventRecord(e->ev0, e->stream));
         HIP_TRY(e, gm::launch_search(a, enumerate, e->num_cu, e->opt.waves_per_cu, e->stream, &grid_waves));
@@ -485,6 +503,7 @@ void gm_destroy(gm_engine *e) {
             if (e->d_pool[i]) hipFree(e->d_pool[i]);
         if (e->d_rows) hipFree(e->d_rows);
         if (e->d_ctl) hipFree(e->d_ctl);
+        if (e->d_steal) hipFree(e->d_steal);
         if (e->ev0) hipEventDestroy(e->ev0);
         if (e->ev1) hipEventDestroy(e->ev1);
         if (e->stream) hipStreamDestroy(e->stream);

@@ -27,11 +27,24 @@ struct Plan {
     uint32_t bwd[kMaxK];      // bit j set: phi[j] (j < i) is a backward neighbour of phi[i]
 };
 
-// Device-resident control block, cleared before every search.
-struct Control {
+// Device-resident control block, cleared before every search.  Words that many
+// wavefronts hit with atomics or polls live on cache lines of their own (128 B).
+struct alignas(128) Control {
     unsigned long long count;        // matches found (flushed by wavefronts)
+    unsigned long long pad_count[15];
     unsigned long long pool_next;    // next unclaimed pool row
+    unsigned long long pad_pool[15];
     unsigned long long out_rows;     // rows appended (root scan, expansion, enumerate)
+    unsigned long long pad_rows[15];
+    unsigned int abort;              // 0 running, 1 cap reached, 2 time limit
+    unsigned int pad_abort[31];
+    int busy;                        // wavefronts holding work + donations in the ring
+    int idle;                        // wavefronts waiting for a donation
+    int pad_busy[30];
+    unsigned long long q_head;       // donation ring: next position to take
+    unsigned long long q_tail;       // donation ring: next position to fill
+    unsigned long long pad_ring[14];
+    // written once per launch or read by the host only
     unsigned long long measure;      // expansion bound: sum of |C^L| over pool rows
     unsigned long long groups;
     unsigned long long tasks;
@@ -39,10 +52,18 @@ struct Control {
     unsigned long long lanes_issued;
     unsigned long long probes;
     unsigned long long steals;
-    unsigned int abort;              // 0 running, 1 cap reached, 2 time limit
-    unsigned int busy;               // wavefronts holding work + queued donations
     unsigned long long t0;           // device wall clock when the root scan started
-    unsigned long long pad[3];
+};
+
+// One donated piece of work (Sec. 4.3, dynamic balancing): the partial matches
+// of the donor's parent lanes pi..ei at level `depth`, and the task range that
+// changes hands: from (pi, pj) up to, not including, (ei, ej) in the level's
+// virtual task pool.
+struct alignas(128) StealSlot {
+    unsigned long long seq;          // ring sequence number (lock-free bounded queue)
+    unsigned long long lanes;        // parent lanes present
+    int32_t depth, pi, pj, ei, ej, pad[27];
+    int32_t rows[kWave * kMaxK];     // rows[q * kMaxK + i] = image of position i for parent lane q
 };
 
 enum : unsigned int { kAbortNone = 0, kAbortCap = 1, kAbortTime = 2 };
@@ -59,7 +80,7 @@ struct SearchArgs {
     unsigned long long cap;    // 0 = none
     unsigned long long flush;  // local matches kept before an atomic flush
     unsigned long long budget; // time limit in device wall-clock ticks from ctl->t0, 0 = none
-    void *steal;               // donation slots (work stealing), or null
+    StealSlot *steal;          // donation ring (work stealing), or null
     int32_t steal_slots;
     int32_t steal_threshold;
     int32_t linear_probe;      // lists this short are scanned, longer ones bisected
@@ -74,6 +95,6 @@ hipError_t launch_measure(const SearchArgs &a, int num_cu, hipStream_t s);
 hipError_t launch_expand(const SearchArgs &a, int num_cu, hipStream_t s);
 hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int waves_per_cu, hipStream_t s,
                          int *grid_waves_out);
-size_t steal_slot_bytes();
+hipError_t launch_steal_init(StealSlot *slots, int32_t n, hipStream_t s);
 
 }  // namespace gm

@@ -118,6 +118,8 @@ struct WaveStack {
     uint8_t cq[K][kWave];    //   ... and source lane at that level
     uint32_t cur_j[K];       // scatter cursor: offset in the current parent's list
     uint32_t cur_i[K];       // scatter cursor: current parent lane (64 = level exhausted)
+    uint32_t end_j[K];       // end of the level's task range: offset in parent end_i's list
+    uint32_t end_i[K];       //   ... parent lane (64 = no bound: the whole pool)
     uint8_t own[kWave];      // scatter scratch: parent starting at each slot
 };
 
@@ -153,6 +155,35 @@ __device__ __forceinline__ uint32_t generate_tasks(WaveStack<K> &S, const Plan &
     return len;
 }
 
+template <int K>
+__device__ __forceinline__ void open_level(WaveStack<K> &S, int l, uint32_t lane) {
+    if (lane == 0) {
+        S.cur_i[l] = 0;
+        S.cur_j[l] = 0;
+        S.end_i[l] = kWave;
+        S.end_j[l] = 0;
+    }
+}
+
+// Unscattered tasks of this lane's task group at level l, given the level's
+// cursor (ci, cjo) and end (ei, ej).  Also returns the group's list.
+template <int K>
+__device__ __forceinline__ uint32_t remaining(const WaveStack<K> &S, int l, uint32_t lane, uint32_t ci, uint32_t cjo,
+                                              uint32_t ei, uint32_t ej, uint32_t &cst, uint32_t &cln) {
+    cst = 0;
+    cln = 0;
+    const uint32_t sj = S.cj[l][lane];
+    if (sj != 0xffu) {
+        const uint32_t sq = S.cq[l][lane];
+        cst = S.st[sj][sq];
+        cln = S.dg[sj][sq];
+    }
+    if (lane < ci || lane > ei) return 0u;
+    const uint32_t lo = lane == ci ? cjo : 0u;
+    const uint32_t hi = lane == ei ? (ej < cln ? ej : cln) : cln;
+    return hi > lo ? hi - lo : 0u;
+}
+
 struct Round {
     uint32_t ntask;  // tasks this round (0: level exhausted)
     uint32_t owner;  // parent lane of this lane's task
@@ -166,15 +197,11 @@ __device__ __forceinline__ Round scatter(WaveStack<K> &S, const int32_t *__restr
     Round r;
     const uint32_t ci = __builtin_amdgcn_readfirstlane(S.cur_i[l]);
     const uint32_t cjo = __builtin_amdgcn_readfirstlane(S.cur_j[l]);
-    uint32_t cst = 0, cln = 0;
-    const uint32_t sj = S.cj[l][lane];
-    if (sj != 0xffu) {
-        const uint32_t sq = S.cq[l][lane];
-        cst = S.st[sj][sq];
-        cln = S.dg[sj][sq];
-    }
-    uint32_t rem = lane < ci ? 0u : (lane == ci ? cln - cjo : cln);
-    uint32_t rc = rem < 64u ? rem : 64u;
+    const uint32_t ei = __builtin_amdgcn_readfirstlane(S.end_i[l]);
+    const uint32_t ej = __builtin_amdgcn_readfirstlane(S.end_j[l]);
+    uint32_t cst, cln;
+    const uint32_t rem = remaining(S, l, lane, ci, cjo, ei, ej, cst, cln);
+    const uint32_t rc = rem < 64u ? rem : 64u;
     // exclusive scan of rc (values <= 64: seven bit planes)
     uint32_t ex = 0, tot = 0;
 #pragma unroll
@@ -211,8 +238,9 @@ __device__ __forceinline__ Round scatter(WaveStack<K> &S, const int32_t *__restr
         const uint32_t s63 = read_lane(s, 63);
         const uint32_t used = 64u - s63 + (p63 == ci ? cjo : 0u);
         const uint32_t len63 = read_lane(cln, p63);
+        const uint32_t stop63 = p63 == ei ? (ej < len63 ? ej : len63) : len63;
         if (lane == 0) {
-            if (used >= len63) {
+            if (used >= stop63) {
                 S.cur_i[l] = p63 + 1;
                 S.cur_j[l] = 0;
             } else {
@@ -265,6 +293,10 @@ __device__ __forceinline__ unsigned long long lane0_atomic_add(unsigned long lon
     return read_lane64(old, 0);
 }
 
+__device__ __forceinline__ void lane0_add(int *p, int x) {
+    if (lane_id() == 0) atomicAdd(p, x);
+}
+
 __device__ __forceinline__ unsigned int load_abort(Control *ctl) {
     unsigned int v = 0;
     if (lane_id() == 0) v = __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -275,56 +307,284 @@ __device__ __forceinline__ void set_abort(Control *ctl, unsigned int why) {
     if (lane_id() == 0) atomicCAS(&ctl->abort, kAbortNone, why);
 }
 
+template <class T>
+__device__ __forceinline__ T load_agent(T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class T>
+__device__ __forceinline__ void store_agent(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// Donation ring: bounded lock-free multi-producer / multi-consumer queue with a
+// sequence number per slot (slot i starts at seq = i).  A producer owns the
+// slot at tail position p when seq == p and publishes it with seq = p + 1; a
+// consumer owns it at head position p when seq == p + 1 and frees it with
+// seq = p + N.  Only lane 0 touches the counters.
+//
+// Every access to a slot (payload and seq) is an agent-scope atomic, which on
+// gfx950 reads and writes at the device coherence point without cache-wide
+// maintenance; an agent-scope release/acquire fence would instead write back
+// and invalidate the whole L2 of the XCD, evicting the graph for every
+// wavefront there.  Order is kept by waiting for all of the wavefront's memory
+// operations (s_waitcnt 0) before the seq store that hands the slot over; a
+// consumer issues its payload loads only after it has read that seq.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void wait_memory() { __builtin_amdgcn_s_waitcnt(0); }
+
+// Claim a slot for writing; returns its index or -1 when the ring is full.
+__device__ int ring_claim(Control *ctl, StealSlot *slots, int nslots, unsigned long long *pos_out) {
+    int idx = -1;
+    unsigned long long pos = 0;
+    if (lane_id() == 0) {
+        pos = load_agent(&ctl->q_tail);
+        for (int attempt = 0; attempt < 8; ++attempt) {
+            StealSlot &sl = slots[pos % static_cast<unsigned long long>(nslots)];
+            const unsigned long long seq = load_agent(&sl.seq);
+            if (seq == pos) {
+                if (__hip_atomic_compare_exchange_strong(&ctl->q_tail, &pos, pos + 1, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    idx = static_cast<int>(pos % static_cast<unsigned long long>(nslots));
+                    break;
+                }
+                // pos now holds the current tail; retry
+            } else if (seq < pos) {
+                break;  // full
+            } else {
+                pos = load_agent(&ctl->q_tail);
+            }
+        }
+    }
+    *pos_out = read_lane64(pos, 0);
+    return static_cast<int>(read_lane(static_cast<uint32_t>(idx), 0));
+}
+
+__device__ void ring_publish(StealSlot *slots, int idx, unsigned long long pos) {
+    wait_memory();
+    if (lane_id() == 0) store_agent(&slots[idx].seq, pos + 1);
+}
+
+// Take a published slot; returns its index or -1 when the ring is empty.
+__device__ int ring_take(Control *ctl, StealSlot *slots, int nslots, unsigned long long *pos_out) {
+    int idx = -1;
+    unsigned long long pos = 0;
+    if (lane_id() == 0) {
+        pos = load_agent(&ctl->q_head);
+        for (int attempt = 0; attempt < 8; ++attempt) {
+            StealSlot &sl = slots[pos % static_cast<unsigned long long>(nslots)];
+            const unsigned long long seq = load_agent(&sl.seq);
+            if (seq == pos + 1) {
+                if (__hip_atomic_compare_exchange_strong(&ctl->q_head, &pos, pos + 1, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    idx = static_cast<int>(pos % static_cast<unsigned long long>(nslots));
+                    break;
+                }
+            } else if (seq < pos + 1) {
+                break;  // empty
+            } else {
+                pos = load_agent(&ctl->q_head);
+            }
+        }
+    }
+    *pos_out = read_lane64(pos, 0);
+    return static_cast<int>(read_lane(static_cast<uint32_t>(idx), 0));
+}
+
+__device__ void ring_release(StealSlot *slots, int nslots, int idx, unsigned long long pos) {
+    wait_memory();
+    if (lane_id() == 0) store_agent(&slots[idx].seq, pos + static_cast<unsigned long long>(nslots));
+}
+
+// Inclusive prefix sum over the wavefront.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (uint32_t off = 1; off < kWave; off <<= 1) {
+        const uint32_t y = shfl(x, lane >= off ? lane - off : lane);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+// Dynamic balancing (Sec. 4.3): give the upper half of the unscattered tasks of
+// the shallowest non-leaf level with at least `threshold` of them to an idle
+// wavefront.  The donor keeps the lower half by moving that level's end.
+// Returns true if a donation was published.
+template <int K>
+__device__ __forceinline__ bool donate(WaveStack<K> &S, const SearchArgs &a, int base, int l, uint32_t lane) {
+    const int k = a.plan.k;
+    const int top = l < k - 2 ? l : k - 2;
+    for (int L = base; L <= top; ++L) {
+        const uint32_t ci = __builtin_amdgcn_readfirstlane(S.cur_i[L]);
+        if (ci >= kWave) continue;
+        const uint32_t cjo = __builtin_amdgcn_readfirstlane(S.cur_j[L]);
+        const uint32_t ei = __builtin_amdgcn_readfirstlane(S.end_i[L]);
+        const uint32_t ej = __builtin_amdgcn_readfirstlane(S.end_j[L]);
+        uint32_t cst, cln;
+        const uint32_t rem = remaining(S, L, lane, ci, cjo, ei, ej, cst, cln);
+        const uint32_t incl = wave_incl_scan(rem);
+        const uint32_t total = read_lane(incl, 63);
+        if (total < static_cast<uint32_t>(a.steal_threshold)) continue;
+        // split at h: the donor keeps tasks [0, h), the thief takes [h, total)
+        const uint32_t h = total / 2;
+        const uint32_t excl = incl - rem;
+        const uint64_t hit = ballot(rem > 0 && excl <= h && h < incl);
+        const uint32_t p = static_cast<uint32_t>(__builtin_ctzll(hit));
+        const uint32_t excl_p = read_lane(excl, p);
+        const uint32_t pj = (p == ci ? cjo : 0u) + (h - excl_p);
+        Control *ctl = a.ctl;
+        lane0_add(&ctl->busy, 1);  // counted before it becomes visible
+        unsigned long long pos;
+        const int idx = ring_claim(ctl, a.steal, a.steal_slots, &pos);
+        if (idx < 0) {
+            lane0_add(&ctl->busy, -1);
+            return false;
+        }
+        StealSlot &sl = a.steal[idx];
+        const bool mine = lane >= p && lane <= ei && S.cj[L][lane] != 0xffu;
+        const uint64_t lanes = ballot(mine);
+        if (mine) {
+            uint32_t q = lane;
+            for (int i = L - 1; i >= 0; --i) {
+                store_agent(&sl.rows[lane * kMaxK + i], S.v[i][q]);
+                q = S.pid[i][q];
+            }
+        }
+        if (lane == 0) {
+            store_agent(&sl.lanes, static_cast<unsigned long long>(lanes));
+            store_agent(&sl.depth, L);
+            store_agent(&sl.pi, static_cast<int32_t>(p));
+            store_agent(&sl.pj, static_cast<int32_t>(pj));
+            store_agent(&sl.ei, static_cast<int32_t>(ei));
+            store_agent(&sl.ej, static_cast<int32_t>(ej));
+            S.end_i[L] = p;
+            S.end_j[L] = pj;
+        }
+        ring_publish(a.steal, idx, pos);
+        return true;
+    }
+    return false;
+}
+
 enum Mode { kCount = 0, kEnumerate = 1, kExpand = 2 };
 
-// Persistent search.  Every wavefront loops: claim 64 pool rows, load them as
-// the bottom of its stack, and run Alg. 2's Search iteratively until the stack
-// is empty.  kExpand stops at the pool level and appends the valid extensions
-// to the next pool instead (one breadth-first step of the initialisation).
+// Persistent search.  Every wavefront loops: take work (64 pool rows, or a
+// donation once the pool is empty), load it as the bottom of its stack, and run
+// Alg. 2's Search iteratively until the stack is empty.  kExpand stops at the
+// pool level and appends the valid extensions to the next pool instead (one
+// breadth-first step of the initialisation); it never steals.
 template <int K, int MODE>
-__global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
+__global__ __launch_bounds__(kBlock, 5) void search_kernel(SearchArgs a) {
     __shared__ WaveStack<K> stacks[kWavesPerBlock];
     WaveStack<K> &S = stacks[threadIdx.x / kWave];
     const uint32_t lane = lane_id();
     const int k = a.plan.k;
     const int d = a.plan.depth;
     Control *ctl = a.ctl;
+    const bool stealing = MODE != kExpand && a.steal != nullptr;
 
     uint64_t my_tasks = 0;
     uint32_t my_probes = 0;
     uint64_t my_probes_total = 0;
-    uint64_t w_groups = 0, w_active = 0, w_issued = 0, w_count = 0;
+    uint64_t w_groups = 0, w_active = 0, w_issued = 0, w_count = 0, w_steals = 0;
     uint32_t rounds = 0;
     bool stop = false;
+    bool pool_left = true;
     const unsigned long long deadline = a.budget ? a.ctl->t0 + a.budget : 0ull;
+    if (stealing) lane0_add(&ctl->busy, 1);
 
     while (!stop) {
-        unsigned long long r0 = lane0_atomic_add(&ctl->pool_next, kWave);
-        if (r0 >= a.pool_rows) break;
-        const unsigned long long left = a.pool_rows - r0;
-        const uint32_t nrows = left < kWave ? static_cast<uint32_t>(left) : kWave;
-        const bool have = lane < nrows;
-        for (int i = 0; i < d; ++i) {
-            int32_t v = 0;
-            VInfo vi = make_uint2(0u, 0u);
-            if (have) {
-                v = a.pool[(r0 + lane) * static_cast<unsigned long long>(d) + i];
-                vi = a.vinfo[v];
+        int base = d;
+        bool have = false;
+        if (pool_left) {
+            const unsigned long long r0 = lane0_atomic_add(&ctl->pool_next, kWave);
+            if (r0 < a.pool_rows) {
+                const unsigned long long left = a.pool_rows - r0;
+                const uint32_t nrows = left < kWave ? static_cast<uint32_t>(left) : kWave;
+                const bool mine = lane < nrows;
+                for (int i = 0; i < d; ++i) {
+                    int32_t v = 0;
+                    VInfo vi = make_uint2(0u, 0u);
+                    if (mine) {
+                        v = a.pool[(r0 + lane) * static_cast<unsigned long long>(d) + i];
+                        vi = a.vinfo[v];
+                    }
+                    S.v[i][lane] = v;
+                    S.st[i][lane] = vi.x;
+                    S.dg[i][lane] = vi_deg(vi);
+                    S.pid[i][lane] = static_cast<uint8_t>(lane);
+                }
+                const uint64_t F0 = ballot(mine);
+                my_tasks += generate_tasks(S, a.plan, d, F0, lane);
+                w_groups += __popcll(F0);
+                open_level(S, d, lane);
+                have = true;
+            } else {
+                pool_left = false;
             }
-            S.v[i][lane] = v;
-            S.st[i][lane] = vi.x;
-            S.dg[i][lane] = vi_deg(vi);
-            S.pid[i][lane] = static_cast<uint8_t>(lane);
         }
-        const uint64_t F0 = ballot(have);
-        my_tasks += generate_tasks(S, a.plan, d, F0, lane);
-        w_groups += __popcll(F0);
-        if (lane == 0) {
-            S.cur_i[d] = 0;
-            S.cur_j[d] = 0;
+        if (!have) {
+            if (!stealing) break;
+            // idle: wait for a donation until nobody holds work or the search aborts
+            lane0_add(&ctl->busy, -1);
+            lane0_add(&ctl->idle, 1);
+            int idx = -1;
+            unsigned long long pos = 0;
+            uint32_t nap = 1;  // exponential back-off keeps idle polling off the memory system
+            for (;;) {
+                for (uint32_t z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(32);
+                nap = nap < 64u ? nap * 2u : 64u;
+                if (deadline && wall_clock64() > deadline) set_abort(ctl, kAbortTime);
+                unsigned int ab = 0;
+                int busy = 0;
+                unsigned long long queued = 0;
+                if (lane == 0) {
+                    ab = load_agent(&ctl->abort);
+                    busy = load_agent(&ctl->busy);
+                    queued = load_agent(&ctl->q_tail) - load_agent(&ctl->q_head);
+                }
+                if (read_lane(ab, 0) != kAbortNone) break;
+                if (read_lane(static_cast<uint32_t>(busy), 0) == 0) break;
+                if (read_lane64(queued, 0) == 0) continue;
+                idx = ring_take(ctl, a.steal, a.steal_slots, &pos);
+                if (idx >= 0) break;
+                nap = 1;
+            }
+            if (idx < 0) break;
+            lane0_add(&ctl->idle, -1);
+            // the donated work: parent rows at level L-1 and a task range at level L
+            StealSlot &sl = a.steal[idx];
+            const int L = load_agent(&sl.depth);
+            const uint64_t lanes = load_agent(&sl.lanes);
+            const bool mine = (lanes >> lane) & 1ull;
+            for (int i = 0; i < L; ++i) {
+                int32_t v = 0;
+                VInfo vi = make_uint2(0u, 0u);
+                if (mine) {
+                    v = load_agent(&sl.rows[lane * kMaxK + i]);
+                    vi = a.vinfo[v];
+                }
+                S.v[i][lane] = v;
+                S.st[i][lane] = vi.x;
+                S.dg[i][lane] = vi_deg(vi);
+                S.pid[i][lane] = static_cast<uint8_t>(lane);
+            }
+            generate_tasks(S, a.plan, L, lanes, lane);  // already counted by the donor
+            if (lane == 0) {
+                S.cur_i[L] = static_cast<uint32_t>(load_agent(&sl.pi));
+                S.cur_j[L] = static_cast<uint32_t>(load_agent(&sl.pj));
+                S.end_i[L] = static_cast<uint32_t>(load_agent(&sl.ei));
+                S.end_j[L] = static_cast<uint32_t>(load_agent(&sl.ej));
+            }
+            ring_release(a.steal, a.steal_slots, idx, pos);
+            base = L;
+            ++w_steals;
         }
-        int l = d;
-        while (l >= d) {
+        int l = base;
+        while (l >= base) {
             const Round r = scatter(S, a.col, l, lane);
             if (r.ntask == 0) {
                 --l;
@@ -337,8 +597,8 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
             const uint64_t m = ballot(ok);
             if (MODE == kExpand) {
                 if (m) {
-                    const unsigned long long base = lane0_atomic_add(&ctl->out_rows, __popcll(m));
-                    const unsigned long long slot = base + popc_below(m);
+                    const unsigned long long b0 = lane0_atomic_add(&ctl->out_rows, __popcll(m));
+                    const unsigned long long slot = b0 + popc_below(m);
                     if (ok && slot < a.out_cap) {
                         int32_t *row = a.out + slot * static_cast<unsigned long long>(d + 1);
                         for (int i = 0; i < d; ++i) row[i] = S.v[i][r.owner];
@@ -347,8 +607,8 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
                 }
             } else if (l == k - 1) {
                 if (MODE == kEnumerate && m) {
-                    const unsigned long long base = lane0_atomic_add(&ctl->out_rows, __popcll(m));
-                    const unsigned long long slot = base + popc_below(m);
+                    const unsigned long long b0 = lane0_atomic_add(&ctl->out_rows, __popcll(m));
+                    const unsigned long long slot = b0 + popc_below(m);
                     if (ok && slot < a.out_cap) {
                         int32_t *row = a.out + slot * static_cast<unsigned long long>(k);
                         row[a.plan.phi[l]] = r.v;
@@ -367,10 +627,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
                 S.pid[l][lane] = static_cast<uint8_t>(r.owner);
                 my_tasks += generate_tasks(S, a.plan, l + 1, m, lane);
                 w_groups += __popcll(m);
-                if (lane == 0) {
-                    S.cur_i[l + 1] = 0;
-                    S.cur_j[l + 1] = 0;
-                }
+                open_level(S, l + 1, lane);
                 ++l;
             }
             ++rounds;
@@ -383,6 +640,17 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
                 if ((rounds & 31u) == 0) {
                     if (deadline && wall_clock64() > deadline) set_abort(ctl, kAbortTime);
                     if (load_abort(ctl) != kAbortNone) stop = true;
+                    if (stealing && !stop && (rounds & 127u) == 0) {  // idle wavefronts exist only once the pool is empty
+                        int idle = 0;
+                        unsigned long long queued = 0;
+                        if (lane == 0) {
+                            idle = load_agent(&ctl->idle);
+                            queued = load_agent(&ctl->q_tail) - load_agent(&ctl->q_head);
+                        }
+                        idle = static_cast<int>(read_lane(static_cast<uint32_t>(idle), 0));
+                        queued = read_lane64(queued, 0);
+                        if (idle > 0 && static_cast<unsigned long long>(idle) > queued) donate(S, a, base, l, lane);
+                    }
                 }
                 my_probes_total += my_probes;
                 my_probes = 0;
@@ -400,7 +668,13 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
         atomicAdd(&ctl->lanes_active, w_active);
         atomicAdd(&ctl->lanes_issued, w_issued);
         atomicAdd(&ctl->probes, probes);
+        atomicAdd(&ctl->steals, w_steals);
     }
+}
+
+__global__ void steal_init_kernel(StealSlot *slots, int32_t n) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) slots[i].seq = static_cast<unsigned long long>(i);
 }
 
 // Candidates of the first query vertex: label and degree filter over all of V(G).
@@ -504,6 +778,10 @@ hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int wa
     return launch_levels<kCount>(a.plan.k, a, num_cu, waves_per_cu, s, grid_waves_out);
 }
 
-size_t steal_slot_bytes() { return 0; }
+hipError_t launch_steal_init(StealSlot *slots, int32_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(steal_init_kernel, dim3((n + 255) / 256), dim3(256), 0, s, slots, n);
+    return hipGetLastError();
+}
 
 }  // namespace gm
