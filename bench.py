@@ -37,14 +37,14 @@ def kernel_sha() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def algorithmic_bytes(pool_rows: int, depth: int, tasks: int, probes: int) -> int:
+def algorithmic_bytes(pool_rows: int, depth: int, scanned: int, lookups: int, probes: int) -> int:
     """Bytes the search kernel must read by the method's own accounting.
 
-    per task: 4 B candidate id from the neighbour list + 8 B vertex record
-    (label, degree, list start); per membership probe: 4 B list entry; per pool
-    row: depth x (4 B id + 8 B vertex record).
+    per scanned candidate: 4 B id from the neighbour list + 8 B vertex record
+    (label, degree, list start); per label-slice lookup: 8 B (two bounds); per
+    membership probe: 4 B list entry; per pool row: depth x (4 B id + 8 B record).
     """
-    return 12 * tasks + 4 * probes + 12 * depth * pool_rows
+    return 12 * scanned + 8 * lookups + 4 * probes + 12 * depth * pool_rows
 
 
 def read_traffic() -> dict | None:
@@ -255,7 +255,8 @@ def main() -> int:
     lat = np.array([r.search_ms for r in flat])
     kernel_s = sum(r.kernel_ms for r in flat) / 1000.0
     launches = sum(1 for r in flat if r.kernel_ms > 0)
-    b_alg = sum(algorithmic_bytes(r.pool_rows, r.pool_depth, r.kernel_tasks, r.kernel_probes) for r in flat)
+    b_alg = sum(algorithmic_bytes(r.pool_rows, r.pool_depth, r.kernel_scanned, r.kernel_lookups, r.kernel_probes)
+                for r in flat)
     achieved = b_alg / kernel_s / 1e9 if kernel_s > 0 else 0.0
     traffic = read_traffic()
     outcomes = {"done": sum(r.outcome == gm.GM_DONE for r in steps[-1]),
@@ -280,6 +281,7 @@ def main() -> int:
                    "cap": cap, "time_limit_s": limit, "order": "RI heuristic",
                    "tau": args.tau if args.tau else 1000000, "work_stealing": not args.disable_stealing},
         "intersected_edges_per_s": tasks / wall,
+        "scanned_candidates_per_s": sum(r.scanned for r in flat) / wall,
         "query_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                              "mean": float(lat.mean())},
         "outcomes_per_step": outcomes,

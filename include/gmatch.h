@@ -70,7 +70,10 @@ typedef struct {
     /* Below this neighbour-list length a membership test scans the list with
      * independent loads instead of bisecting it; 0 = default 8, max 16. */
     int32_t linear_probe_len;
-    int32_t reserved[7];
+    /* 1 = do not build label-partitioned neighbour lists (every task group then
+     * scans its whole list and the label filter rejects the rest). */
+    int32_t disable_label_index;
+    int32_t reserved[6];
 } gm_options;
 
 /* Result of one count or enumerate call. */
@@ -94,6 +97,11 @@ typedef struct {
     uint64_t kernel_tasks;  /* tasks, probes and matches of that launch alone (the pool */
     uint64_t kernel_probes; /* expansion before it is excluded) */
     uint64_t kernel_groups;
+    uint64_t scanned;        /* candidates actually read: with label-partitioned neighbour
+                                lists a task group scans only the slice of its list whose
+                                label is the query vertex's label (<= tasks) */
+    uint64_t kernel_scanned; /* ... of the depth-first search launch alone */
+    uint64_t kernel_lookups; /* label-slice bound lookups (8 B each) of that launch */
 } gm_result;
 
 /* Create an engine on HIP device `device` (>= 0).  device = -1 creates a

@@ -40,7 +40,8 @@ class Options(ctypes.Structure):
         ("waves_per_cu", ctypes.c_int32),
         ("skip_symmetry_check", ctypes.c_int32),
         ("linear_probe_len", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("disable_label_index", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -64,6 +65,9 @@ class _CResult(ctypes.Structure):
         ("kernel_tasks", ctypes.c_uint64),
         ("kernel_probes", ctypes.c_uint64),
         ("kernel_groups", ctypes.c_uint64),
+        ("scanned", ctypes.c_uint64),
+        ("kernel_scanned", ctypes.c_uint64),
+        ("kernel_lookups", ctypes.c_uint64),
     ]
 
 
@@ -86,6 +90,9 @@ class Result:
     kernel_tasks: int = 0
     kernel_probes: int = 0
     kernel_groups: int = 0
+    scanned: int = 0
+    kernel_scanned: int = 0
+    kernel_lookups: int = 0
     matches: Optional[np.ndarray] = None
 
     @property
@@ -133,7 +140,7 @@ class Engine:
 
     def __init__(self, device: int = 0, tau: int = 0, pool_row_limit: int = 0, disable_stealing: bool = False,
                  steal_threshold: int = 0, waves_per_cu: int = 0, skip_symmetry_check: bool = False,
-                 linear_probe_len: int = 0):
+                 linear_probe_len: int = 0, disable_label_index: bool = False):
         self._lib = load_library()
         opt = Options()
         opt.tau = tau
@@ -143,6 +150,7 @@ class Engine:
         opt.waves_per_cu = waves_per_cu
         opt.skip_symmetry_check = int(skip_symmetry_check)
         opt.linear_probe_len = linear_probe_len
+        opt.disable_label_index = int(disable_label_index)
         h = ctypes.c_void_p()
         st = self._lib.gm_create(device, ctypes.byref(opt), ctypes.byref(h))
         if st != GM_OK:
@@ -199,7 +207,8 @@ class Engine:
         return Result(int(r.count), int(r.outcome), int(r.pool_depth), float(r.search_ms), int(r.pool_rows),
                       int(r.groups), int(r.tasks), int(r.lanes_active), int(r.lanes_issued), int(r.probes),
                       int(r.steals), int(r.rows), float(r.kernel_ms), int(r.grid_waves), int(r.kernel_tasks),
-                      int(r.kernel_probes), int(r.kernel_groups), matches)
+                      int(r.kernel_probes), int(r.kernel_groups), int(r.scanned), int(r.kernel_scanned),
+                      int(r.kernel_lookups), matches)
 
     def count(self, qid: int, cap: int = 0, time_limit_s: float = 0.0) -> Result:
         r = _CResult()

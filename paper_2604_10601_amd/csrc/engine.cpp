@@ -117,6 +117,9 @@ struct gm_engine {
     uint64_t nnz = 0;
     VInfo *d_vinfo = nullptr;
     int32_t *d_col = nullptr;
+    int32_t *d_lcol = nullptr;     // lists ordered by (label, id); aliases d_col when not partitioned
+    uint32_t *d_loff = nullptr;    // label slice bounds
+    int32_t loff_stride = 1;
     std::unordered_map<int32_t, int32_t> label_id;  // G's label value -> compact id
 
     std::vector<QueryRec> queries;
@@ -126,7 +129,8 @@ struct gm_engine {
     int32_t *d_rows = nullptr;
     size_t rows_cap = 0;           // in int32
     Control *d_ctl = nullptr;
-    gm::StealSlot *d_steal = nullptr;
+    gm::Mailbox *d_mail = nullptr;
+    unsigned long long *d_idle_bits = nullptr;
     int32_t steal_slots = 0;
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -177,9 +181,14 @@ gm_status ensure_buffer(gm_engine *e, int32_t **buf, size_t *cap, size_t need_in
 
 void free_graph(gm_engine *e) {
     if (e->d_vinfo) hipFree(e->d_vinfo);
+    if (e->d_lcol && e->d_lcol != e->d_col) hipFree(e->d_lcol);
     if (e->d_col) hipFree(e->d_col);
+    if (e->d_loff) hipFree(e->d_loff);
     e->d_vinfo = nullptr;
     e->d_col = nullptr;
+    e->d_lcol = nullptr;
+    e->d_loff = nullptr;
+    e->loff_stride = 1;
     e->has_graph = false;
     e->n = 0;
     e->nnz = 0;
@@ -244,6 +253,15 @@ gm_status read_ctl(gm_engine *e, Control *host) {
     return GM_OK;
 }
 
+// Empty idle bitmap and mailboxes, zero busy and idle counts before a launch that steals.
+gm_status reset_stealing(gm_engine *e, const SearchArgs &a) {
+    if (!a.mail) return GM_OK;
+    HIP_TRY(e, hipMemsetAsync(&e->d_ctl->busy, 0, sizeof(int), e->stream));
+    HIP_TRY(e, hipMemsetAsync(&e->d_ctl->idle_count, 0, sizeof(int), e->stream));
+    HIP_TRY(e, gm::launch_steal_init(a.mail, a.idle_bits, a.steal_slots, e->stream));
+    return GM_OK;
+}
+
 // One search (Alg. 2): root candidates, breadth-first pool to tau, then the
 // persistent depth-first kernel.  rows != null selects enumeration.
 gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_s, int32_t *rows,
@@ -301,24 +319,34 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
     SearchArgs a{};
     a.vinfo = e->d_vinfo;
     a.col = e->d_col;
+    a.lcol = e->d_lcol;
+    a.loff = e->d_loff;
+    a.loff_stride = e->loff_stride;
     a.ctl = e->d_ctl;
     a.cap = cap;
     a.flush = ~0ull;
     a.budget = static_cast<unsigned long long>(budget_ticks);
     a.linear_probe = e->opt.linear_probe_len > 0 ? std::min(e->opt.linear_probe_len, 8) : 8;
-    a.steal = nullptr;
+    a.mail = nullptr;
+    a.idle_bits = nullptr;
     a.steal_slots = 0;
     if (!e->opt.disable_stealing) {
-        if (!e->d_steal) {
-            const int32_t slots = 1024;
-            hipError_t h = hipMalloc(reinterpret_cast<void **>(&e->d_steal), sizeof(gm::StealSlot) * slots);
+        if (!e->d_mail) {
+            // one mailbox per wavefront that can be resident (at most 32 per CU)
+            const int32_t slots = e->num_cu * 32;
+            hipError_t h = hipMalloc(reinterpret_cast<void **>(&e->d_mail), sizeof(gm::Mailbox) * slots);
+            if (h == hipSuccess)
+                h = hipMalloc(reinterpret_cast<void **>(&e->d_idle_bits), sizeof(unsigned long long) * ((slots + 63) / 64));
             if (h != hipSuccess) {
-                e->d_steal = nullptr;
-                return e->fail(GM_ERR_NOMEM, "donation ring allocation failed");
+                if (e->d_mail) hipFree(e->d_mail);
+                e->d_mail = nullptr;
+                e->d_idle_bits = nullptr;
+                return e->fail(GM_ERR_NOMEM, "work-stealing mailbox allocation failed");
             }
             e->steal_slots = slots;
         }
-        a.steal = e->d_steal;
+        a.mail = e->d_mail;
+        a.idle_bits = e->d_idle_bits;
         a.steal_slots = e->steal_slots;
     }
     a.steal_threshold = e->opt.steal_threshold > 0 ? e->opt.steal_threshold : 128;
@@ -362,6 +390,8 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
         HIP_TRY(e, hipMemsetAsync(&e->d_ctl->out_rows, 0, sizeof(unsigned long long), e->stream));
         a.out = e->d_pool[cur ^ 1];
         a.out_cap = bound;
+        st = reset_stealing(e, a);
+        if (st) return st;
         HIP_TRY(e, gm::launch_expand(a, e->num_cu, e->stream));
         st = read_ctl(e, &c);
         if (st) return st;
@@ -393,7 +423,8 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
         }
         HIP_TRY(e, hipMemsetAsync(&e->d_ctl->pool_next, 0, sizeof(unsigned long long), e->stream));
         HIP_TRY(e, hipMemsetAsync(&e->d_ctl->out_rows, 0, sizeof(unsigned long long), e->stream));
-        if (a.steal) HIP_TRY(e, gm::launch_steal_init(a.steal, a.steal_slots, e->stream));
+        st = reset_stealing(e, a);
+        if (st) return st;
         before = c;
         HIP_TRY(e, hipEventRecord(e->ev0, e->stream));
         HIP_TRY(e, gm::launch_search(a, enumerate, e->num_cu, e->opt.waves_per_cu, e->stream, &grid_waves));
@@ -424,6 +455,9 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
     out->kernel_tasks = c.tasks - before.tasks;
     out->kernel_probes = c.probes - before.probes;
     out->kernel_groups = c.groups - before.groups;
+    out->scanned = c.scanned;
+    out->kernel_scanned = c.scanned - before.scanned;
+    out->kernel_lookups = c.lookups - before.lookups;
     if (enumerate) {
         const uint64_t nrows = std::min<uint64_t>(out->count, std::min<uint64_t>(c.out_rows, cap));
         if (nrows) {
@@ -503,7 +537,8 @@ void gm_destroy(gm_engine *e) {
             if (e->d_pool[i]) hipFree(e->d_pool[i]);
         if (e->d_rows) hipFree(e->d_rows);
         if (e->d_ctl) hipFree(e->d_ctl);
-        if (e->d_steal) hipFree(e->d_steal);
+        if (e->d_mail) hipFree(e->d_mail);
+        if (e->d_idle_bits) hipFree(e->d_idle_bits);
         if (e->ev0) hipEventDestroy(e->ev0);
         if (e->ev1) hipEventDestroy(e->ev1);
         if (e->stream) hipStreamDestroy(e->stream);
@@ -536,20 +571,59 @@ gm_status gm_load_graph(gm_engine *e, int32_t n, const int64_t *row_ptr, const i
         vinfo[v].y = static_cast<uint32_t>(deg << 8) | static_cast<uint32_t>(id);
     }
     const uint64_t nnz = static_cast<uint64_t>(row_ptr[n]);
+    // Label-partitioned copy of the lists: N(v) ordered by (label, id), with the
+    // bounds of every label slice, so a task group scans only candidates that
+    // carry its query vertex's label.  Skipped when asked, when there is one
+    // label, or when the bounds table would exceed 8 GiB.
+    const int32_t labels_used = static_cast<int32_t>(ids.size());
+    int32_t stride = labels_used + 1;
+    if (e->opt.disable_label_index || labels_used <= 1 ||
+        static_cast<uint64_t>(n) * static_cast<uint64_t>(stride) * 4ull > (8ull << 30))
+        stride = 1;
+    std::vector<uint32_t> loff;
+    std::vector<int32_t> lcol;
+    if (stride == 1) {
+        loff.resize(static_cast<size_t>(n) + 1);
+        for (int32_t v = 0; v <= n; ++v) loff[v] = static_cast<uint32_t>(row_ptr[v]);
+    } else {
+        loff.resize(static_cast<size_t>(n) * stride);
+        lcol.resize(nnz);
+        parallel_ranges(n, [&](int64_t b, int64_t end) {
+            std::vector<uint32_t> cnt(stride);
+            for (int64_t v = b; v < end; ++v) {
+                std::fill(cnt.begin(), cnt.end(), 0u);
+                for (int64_t p = row_ptr[v]; p < row_ptr[v + 1]; ++p) ++cnt[(vinfo[col[p]].y & 0xffu) + 1];
+                uint32_t *o = &loff[static_cast<size_t>(v) * stride];
+                o[0] = static_cast<uint32_t>(row_ptr[v]);
+                for (int32_t c = 1; c < stride; ++c) o[c] = o[c - 1] + cnt[c];
+                for (int32_t c = 0; c + 1 < stride; ++c) cnt[c] = o[c];  // fill cursors
+                for (int64_t p = row_ptr[v]; p < row_ptr[v + 1]; ++p) lcol[cnt[vinfo[col[p]].y & 0xffu]++] = col[p];
+            }
+        });
+    }
     if (e->device >= 0) {
         HIP_TRY(e, hipSetDevice(e->device));
         free_graph(e);
         hipError_t h = hipMalloc(reinterpret_cast<void **>(&e->d_vinfo), std::max<size_t>(n, 1) * sizeof(VInfo));
         if (h == hipSuccess)
             h = hipMalloc(reinterpret_cast<void **>(&e->d_col), std::max<uint64_t>(nnz, 1) * sizeof(int32_t));
+        if (h == hipSuccess)
+            h = hipMalloc(reinterpret_cast<void **>(&e->d_loff), std::max<size_t>(loff.size(), 1) * sizeof(uint32_t));
+        if (h == hipSuccess && stride > 1)
+            h = hipMalloc(reinterpret_cast<void **>(&e->d_lcol), std::max<uint64_t>(nnz, 1) * sizeof(int32_t));
         if (h != hipSuccess) {
             free_graph(e);
             return e->fail(GM_ERR_NOMEM, std::string("graph upload: ") + hipGetErrorString(h));
         }
+        if (stride == 1) e->d_lcol = e->d_col;
+        e->loff_stride = stride;
         if (n) HIP_TRY(e, hipMemcpy(e->d_vinfo, vinfo.data(), static_cast<size_t>(n) * sizeof(VInfo), hipMemcpyHostToDevice));
         if (nnz) HIP_TRY(e, hipMemcpy(e->d_col, col, nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIP_TRY(e, hipMemcpy(e->d_loff, loff.data(), loff.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+        if (stride > 1 && nnz) HIP_TRY(e, hipMemcpy(e->d_lcol, lcol.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
     } else {
         free_graph(e);
+        e->loff_stride = stride;
     }
     e->label_id = std::move(ids);
     e->n = n;

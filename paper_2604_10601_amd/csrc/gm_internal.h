@@ -38,12 +38,10 @@ struct alignas(128) Control {
     unsigned long long pad_rows[15];
     unsigned int abort;              // 0 running, 1 cap reached, 2 time limit
     unsigned int pad_abort[31];
-    int busy;                        // wavefronts holding work + donations in the ring
-    int idle;                        // wavefronts waiting for a donation
-    int pad_busy[30];
-    unsigned long long q_head;       // donation ring: next position to take
-    unsigned long long q_tail;       // donation ring: next position to fill
-    unsigned long long pad_ring[14];
+    int busy;                        // wavefronts holding work (donations count from hand-over)
+    int pad_busy[31];
+    int idle_count;                  // wavefronts whose bit is set in the idle bitmap
+    int pad_idle[31];
     // written once per launch or read by the host only
     unsigned long long measure;      // expansion bound: sum of |C^L| over pool rows
     unsigned long long groups;
@@ -53,25 +51,37 @@ struct alignas(128) Control {
     unsigned long long probes;
     unsigned long long steals;
     unsigned long long t0;           // device wall clock when the root scan started
+    unsigned long long scanned;      // candidates read from label slices
+    unsigned long long lookups;      // label-slice bound lookups
 };
 
-// One donated piece of work (Sec. 4.3, dynamic balancing): the partial matches
-// of the donor's parent lanes pi..ei at level `depth`, and the task range that
-// changes hands: from (pi, pj) up to, not including, (ei, ej) in the level's
+// Mailbox of one wavefront for dynamic balancing (Sec. 4.3): an idle wavefront
+// sets its bit in the idle bitmap and polls only its own mailbox; a busy one
+// claims a bit and writes the donated work here.  The work is the
+// partial matches of the donor's parent lanes pi..ei at level `depth` and the
+// task range from (pi, pj) up to, not including, (ei, ej) of that level's
 // virtual task pool.
-struct alignas(128) StealSlot {
-    unsigned long long seq;          // ring sequence number (lock-free bounded queue)
+struct alignas(128) Mailbox {
+    unsigned int status;             // kMailEmpty / kMailWaiting / kMailFull
+    int32_t depth, pi, pj, ei, ej;
     unsigned long long lanes;        // parent lanes present
-    int32_t depth, pi, pj, ei, ej, pad[27];
+    int32_t pad[24];
     int32_t rows[kWave * kMaxK];     // rows[q * kMaxK + i] = image of position i for parent lane q
 };
+
+enum : unsigned int { kMailEmpty = 0, kMailWaiting = 1, kMailFull = 2 };
 
 enum : unsigned int { kAbortNone = 0, kAbortCap = 1, kAbortTime = 2 };
 
 // Arguments of every search kernel (passed by value in the kernarg segment).
 struct SearchArgs {
     const VInfo *vinfo;        // [n]
-    const int32_t *col;        // [nnz]
+    const int32_t *col;        // [nnz] neighbour lists, ids ascending (membership tests)
+    const int32_t *lcol;       // [nnz] the same lists ordered by (label, id) (candidate scans)
+    const uint32_t *loff;      // label slice bounds: N(v) with label c is
+                               // lcol[loff[v*stride + c] .. loff[v*stride + c + 1])
+    int32_t loff_stride;       // labels + 1, or 1 when lists are not partitioned (c = 0)
+    int32_t pad_l;
     const int32_t *pool;       // [pool_rows * depth]
     unsigned long long pool_rows;
     int32_t *out;              // expansion: next pool; enumerate: rows
@@ -80,8 +90,9 @@ struct SearchArgs {
     unsigned long long cap;    // 0 = none
     unsigned long long flush;  // local matches kept before an atomic flush
     unsigned long long budget; // time limit in device wall-clock ticks from ctl->t0, 0 = none
-    StealSlot *steal;          // donation ring (work stealing), or null
-    int32_t steal_slots;
+    Mailbox *mail;             // one per wavefront (work stealing), or null
+    unsigned long long *idle_bits; // bit w set: wavefront w waits for work
+    int32_t steal_slots;       // number of mailboxes (>= wavefronts launched)
     int32_t steal_threshold;
     int32_t linear_probe;      // lists this short are scanned, longer ones bisected
     int32_t pad0;
@@ -95,6 +106,6 @@ hipError_t launch_measure(const SearchArgs &a, int num_cu, hipStream_t s);
 hipError_t launch_expand(const SearchArgs &a, int num_cu, hipStream_t s);
 hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int waves_per_cu, hipStream_t s,
                          int *grid_waves_out);
-hipError_t launch_steal_init(StealSlot *slots, int32_t n, hipStream_t s);
+hipError_t launch_steal_init(Mailbox *mail, unsigned long long *idle_bits, int32_t n, hipStream_t s);
 
 }  // namespace gm

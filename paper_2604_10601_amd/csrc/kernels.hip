@@ -39,7 +39,7 @@ namespace gm {
 
 namespace {
 
-constexpr int kWavesPerBlock = 4;
+constexpr int kWavesPerBlock = 1;
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kLinear = 8;  // longest list tail scanned with independent loads
 
@@ -107,52 +107,89 @@ __device__ __forceinline__ bool list_contains(const int32_t *__restrict__ col, u
     return f;
 }
 
-// Per-wavefront stack in LDS (Sec. 5.1: S is |V(Q)| x warp width).
+// Per-wavefront stack in LDS (Sec. 5.1: S is |V(Q)| x warp width), 20 bytes per
+// (level, lane).
 template <int K>
 struct WaveStack {
     int32_t v[K][kWave];     // data vertex of the task at (level, lane)
-    uint32_t st[K][kWave];   // start of N(v) in col[]
-    uint32_t dg[K][kWave];   // |N(v)|
-    uint8_t pid[K][kWave];   // lane of the parent entry at level - 1
-    uint8_t cj[K][kWave];    // local candidate list of parent lane: source level (0xff = none)
-    uint8_t cq[K][kWave];    //   ... and source lane at that level
-    uint32_t cur_j[K];       // scatter cursor: offset in the current parent's list
+    uint32_t st[K][kWave];   // start of N(v) in col[] (ids ascending)
+    uint32_t dp[K][kWave];   // |N(v)| << 8 | lane of the parent entry at level - 1
+    uint32_t cs[K][kWave];   // parent lane's local candidate slice: start in lcol[]
+    uint32_t cl[K][kWave];   //   ... length << 8 | level of its source list (0xff = no list)
+    uint32_t cur_j[K];       // scatter cursor: offset in the current parent's slice
     uint32_t cur_i[K];       // scatter cursor: current parent lane (64 = level exhausted)
-    uint32_t end_j[K];       // end of the level's task range: offset in parent end_i's list
+    uint32_t end_j[K];       // end of the level's task range: offset in parent end_i's slice
     uint32_t end_i[K];       //   ... parent lane (64 = no bound: the whole pool)
     uint8_t own[kWave];      // scatter scratch: parent starting at each slot
 };
 
-// GenerateTask (Alg. 2): for every parent lane in F at level l-1, pick the
-// backward neighbour with the fewest neighbours (earliest position on ties) and
-// record its list as the parent's local candidate set at level l.  Returns the
-// list length for this lane (0 if the lane is not a parent).
 template <int K>
-__device__ __forceinline__ uint32_t generate_tasks(WaveStack<K> &S, const Plan &P, int l, uint64_t F,
-                                                   uint32_t lane) {
-    uint32_t len = 0;
-    uint32_t bj = 0xffu, bq = 0;
+__device__ __forceinline__ uint32_t ent_deg(const WaveStack<K> &S, int i, uint32_t q) { return S.dp[i][q] >> 8; }
+template <int K>
+__device__ __forceinline__ uint32_t ent_pid(const WaveStack<K> &S, int i, uint32_t q) { return S.dp[i][q] & 0xffu; }
+
+template <int K>
+__device__ __forceinline__ void push_entry(WaveStack<K> &S, int i, uint32_t lane, int32_t v, VInfo vi, uint32_t pid) {
+    S.v[i][lane] = v;
+    S.st[i][lane] = vi.x;
+    S.dp[i][lane] = (vi_deg(vi) << 8) | pid;
+}
+
+struct Gen {
+    uint32_t tasks;    // |C^L| by the paper's rule: the smallest backward list
+    uint32_t scanned;  // length of the label slice that is actually scanned
+    uint32_t lookups;  // slice bounds read
+};
+
+// GenerateTask (Alg. 2): for every parent lane in F at level l-1, walk its chain
+// and choose the local candidates among its backward neighbours' lists.  The
+// paper takes the whole list of the neighbour with the fewest neighbours
+// (Sec. 4.1), and that length is what `tasks` counts.  With label-partitioned
+// lists only the slice of candidates labelled L(phi[l]) can pass the label
+// check, so the smallest such slice is scanned instead (earliest position on
+// ties); it yields exactly the same valid extensions.
+template <int K>
+__device__ __forceinline__ Gen generate_tasks(WaveStack<K> &S, const SearchArgs &a, int l, uint64_t F,
+                                              uint32_t lane) {
+    Gen g{0u, 0u, 0u};
+    uint32_t cs = 0, cl = 0xffu;
     if ((F >> lane) & 1ull) {
-        const uint32_t bw = P.bwd[l];
+        const uint32_t bw = a.plan.bwd[l];
         const int lowest = __builtin_ctz(bw);
+        const bool sliced = a.loff_stride > 1;
+        const uint32_t lab = sliced ? static_cast<uint32_t>(a.plan.lab[l]) : 0u;
         uint32_t q = lane;
-        uint32_t best = 0xffffffffu;
+        uint32_t best_full = 0xffffffffu, best_n = 0xffffffffu, best_a = 0, best_j = 0;
         for (int i = l - 1; i >= lowest; --i) {
             if ((bw >> i) & 1u) {
-                uint32_t d = S.dg[i][q];
-                if (d <= best) {
-                    best = d;
-                    bj = static_cast<uint32_t>(i);
-                    bq = q;
+                const uint32_t d = ent_deg(S, i, q);
+                best_full = d < best_full ? d : best_full;
+                uint32_t sa, sn;
+                if (sliced) {
+                    const uint32_t *o = a.loff + static_cast<unsigned long long>(S.v[i][q]) * a.loff_stride + lab;
+                    sa = o[0];
+                    sn = o[1] - sa;
+                    ++g.lookups;
+                } else {
+                    sa = S.st[i][q];
+                    sn = d;
+                }
+                if (sn <= best_n) {
+                    best_n = sn;
+                    best_a = sa;
+                    best_j = static_cast<uint32_t>(i);
                 }
             }
-            q = S.pid[i][q];
+            q = ent_pid(S, i, q);
         }
-        len = best;
+        g.tasks = best_full;
+        g.scanned = best_n;
+        cs = best_a;
+        cl = (best_n << 8) | best_j;
     }
-    S.cj[l][lane] = static_cast<uint8_t>(bj);
-    S.cq[l][lane] = static_cast<uint8_t>(bq);
-    return len;
+    S.cs[l][lane] = cs;
+    S.cl[l][lane] = cl;
+    return g;
 }
 
 template <int K>
@@ -166,18 +203,13 @@ __device__ __forceinline__ void open_level(WaveStack<K> &S, int l, uint32_t lane
 }
 
 // Unscattered tasks of this lane's task group at level l, given the level's
-// cursor (ci, cjo) and end (ei, ej).  Also returns the group's list.
+// cursor (ci, cjo) and end (ei, ej).  Also returns the group's slice.
 template <int K>
 __device__ __forceinline__ uint32_t remaining(const WaveStack<K> &S, int l, uint32_t lane, uint32_t ci, uint32_t cjo,
                                               uint32_t ei, uint32_t ej, uint32_t &cst, uint32_t &cln) {
-    cst = 0;
-    cln = 0;
-    const uint32_t sj = S.cj[l][lane];
-    if (sj != 0xffu) {
-        const uint32_t sq = S.cq[l][lane];
-        cst = S.st[sj][sq];
-        cln = S.dg[sj][sq];
-    }
+    const uint32_t cl = S.cl[l][lane];
+    cst = S.cs[l][lane];
+    cln = cl >> 8;
     if (lane < ci || lane > ei) return 0u;
     const uint32_t lo = lane == ci ? cjo : 0u;
     const uint32_t hi = lane == ei ? (ej < cln ? ej : cln) : cln;
@@ -193,7 +225,7 @@ struct Round {
 // ScatterTask (Alg. 2) for the whole wavefront: hand the next <= 64 tasks of
 // level l to lanes 0..ntask-1 and advance the level's cursor.
 template <int K>
-__device__ __forceinline__ Round scatter(WaveStack<K> &S, const int32_t *__restrict__ col, int l, uint32_t lane) {
+__device__ __forceinline__ Round scatter(WaveStack<K> &S, const int32_t *__restrict__ lcol, int l, uint32_t lane) {
     Round r;
     const uint32_t ci = __builtin_amdgcn_readfirstlane(S.cur_i[l]);
     const uint32_t cjo = __builtin_amdgcn_readfirstlane(S.cur_j[l]);
@@ -230,7 +262,7 @@ __device__ __forceinline__ Round scatter(WaveStack<K> &S, const int32_t *__restr
     const uint32_t ocst = shfl(cst, owner);
     const uint32_t j = lane - s + (owner == ci ? cjo : 0u);
     r.owner = owner;
-    r.v = lane < r.ntask ? col[ocst + j] : -1;
+    r.v = lane < r.ntask ? lcol[ocst + j] : -1;
     // advance the cursor past slot 63; rc is clamped, so a lone parent with more
     // than 64 tasks left shows up only in rem
     if (tot > 64u || ballot(rem > rc) != 0ull) {
@@ -267,7 +299,7 @@ __device__ __forceinline__ bool process(WaveStack<K> &S, const SearchArgs &a, in
          vi_deg(vi) >= static_cast<uint32_t>(a.plan.qdeg[l]);
     if (ok) {
         const uint32_t bw = a.plan.bwd[l];
-        const uint32_t js = S.cj[l][r.owner];
+        const uint32_t js = S.cl[l][r.owner] & 0xffu;
         uint32_t q = r.owner;
         for (int i = l - 1; i >= 0; --i) {
             const int32_t w = S.v[i][q];
@@ -276,12 +308,12 @@ __device__ __forceinline__ bool process(WaveStack<K> &S, const SearchArgs &a, in
                 break;
             }
             if (((bw >> i) & 1u) && static_cast<uint32_t>(i) != js) {
-                if (!list_contains(a.col, S.st[i][q], S.dg[i][q], r.v, a.linear_probe, probes)) {
+                if (!list_contains(a.col, S.st[i][q], ent_deg(S, i, q), r.v, a.linear_probe, probes)) {
                     ok = false;
                     break;
                 }
             }
-            q = S.pid[i][q];
+            q = ent_pid(S, i, q);
         }
     }
     return ok;
@@ -318,84 +350,52 @@ __device__ __forceinline__ void store_agent(T *p, T v) {
 }
 
 // ---------------------------------------------------------------------------
-// Donation ring: bounded lock-free multi-producer / multi-consumer queue with a
-// sequence number per slot (slot i starts at seq = i).  A producer owns the
-// slot at tail position p when seq == p and publishes it with seq = p + 1; a
-// consumer owns it at head position p when seq == p + 1 and frees it with
-// seq = p + N.  Only lane 0 touches the counters.
+// Dynamic balancing (Sec. 4.3): an idle wavefront sets its bit in the idle
+// bitmap and polls its own mailbox; a busy wavefront claims a set bit and
+// writes the donated work into that wavefront's mailbox.  Only the donor and
+// the one idle wavefront touch a mailbox, and the bitmap spreads the idle
+// wavefronts over many words, so neither waiting nor claiming funnels through
+// one hot word (a queue with one tail counter serialises thousands of
+// wavefronts that run dry at the same moment).
 //
-// Every access to a slot (payload and seq) is an agent-scope atomic, which on
-// gfx950 reads and writes at the device coherence point without cache-wide
+// Every access to the bitmap and the mailboxes is an agent-scope atomic, which
+// on gfx950 reads and writes at the device coherence point without cache-wide
 // maintenance; an agent-scope release/acquire fence would instead write back
 // and invalidate the whole L2 of the XCD, evicting the graph for every
 // wavefront there.  Order is kept by waiting for all of the wavefront's memory
-// operations (s_waitcnt 0) before the seq store that hands the slot over; a
-// consumer issues its payload loads only after it has read that seq.
+// operations (s_waitcnt 0) before the store that hands data over; a reader
+// issues its payload loads only after it has seen that store.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ void wait_memory() { __builtin_amdgcn_s_waitcnt(0); }
 
-// Claim a slot for writing; returns its index or -1 when the ring is full.
-__device__ int ring_claim(Control *ctl, StealSlot *slots, int nslots, unsigned long long *pos_out) {
-    int idx = -1;
-    unsigned long long pos = 0;
-    if (lane_id() == 0) {
-        pos = load_agent(&ctl->q_tail);
-        for (int attempt = 0; attempt < 8; ++attempt) {
-            StealSlot &sl = slots[pos % static_cast<unsigned long long>(nslots)];
-            const unsigned long long seq = load_agent(&sl.seq);
-            if (seq == pos) {
-                if (__hip_atomic_compare_exchange_strong(&ctl->q_tail, &pos, pos + 1, __ATOMIC_RELAXED,
-                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    idx = static_cast<int>(pos % static_cast<unsigned long long>(nslots));
-                    break;
-                }
-                // pos now holds the current tail; retry
-            } else if (seq < pos) {
-                break;  // full
-            } else {
-                pos = load_agent(&ctl->q_tail);
+// Claim one waiting wavefront; returns its id or -1.
+__device__ int32_t claim_idle(const SearchArgs &a, uint32_t start) {
+    const uint32_t lane = lane_id();
+    const uint32_t nwords = (static_cast<uint32_t>(a.steal_slots) + 63u) / 64u;
+    for (uint32_t base = 0; base < nwords; base += kWave) {
+        const uint32_t w = (start + base + lane) % nwords;
+        unsigned long long bits = 0;
+        if (base + lane < nwords) bits = load_agent(&a.idle_bits[w]);
+        uint64_t any = ballot(bits != 0ull);
+        while (any) {
+            const uint32_t src = static_cast<uint32_t>(__builtin_ctzll(any));
+            any &= any - 1;
+            const uint32_t word = read_lane(w, src);
+            const unsigned long long seen = read_lane64(bits, src);
+            int32_t id = -1;
+            if (lane == 0) {
+                const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(seen));
+                const unsigned long long mask = 1ull << b;
+                const unsigned long long old = __hip_atomic_fetch_and(&a.idle_bits[word], ~mask, __ATOMIC_RELAXED,
+                                                                      __HIP_MEMORY_SCOPE_AGENT);
+                if (old & mask) id = static_cast<int32_t>(word * 64u + b);
             }
+            id = static_cast<int32_t>(read_lane(static_cast<uint32_t>(id), 0));
+            if (id >= 0) return id;
         }
     }
-    *pos_out = read_lane64(pos, 0);
-    return static_cast<int>(read_lane(static_cast<uint32_t>(idx), 0));
-}
-
-__device__ void ring_publish(StealSlot *slots, int idx, unsigned long long pos) {
-    wait_memory();
-    if (lane_id() == 0) store_agent(&slots[idx].seq, pos + 1);
-}
-
-// Take a published slot; returns its index or -1 when the ring is empty.
-__device__ int ring_take(Control *ctl, StealSlot *slots, int nslots, unsigned long long *pos_out) {
-    int idx = -1;
-    unsigned long long pos = 0;
-    if (lane_id() == 0) {
-        pos = load_agent(&ctl->q_head);
-        for (int attempt = 0; attempt < 8; ++attempt) {
-            StealSlot &sl = slots[pos % static_cast<unsigned long long>(nslots)];
-            const unsigned long long seq = load_agent(&sl.seq);
-            if (seq == pos + 1) {
-                if (__hip_atomic_compare_exchange_strong(&ctl->q_head, &pos, pos + 1, __ATOMIC_RELAXED,
-                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    idx = static_cast<int>(pos % static_cast<unsigned long long>(nslots));
-                    break;
-                }
-            } else if (seq < pos + 1) {
-                break;  // empty
-            } else {
-                pos = load_agent(&ctl->q_head);
-            }
-        }
-    }
-    *pos_out = read_lane64(pos, 0);
-    return static_cast<int>(read_lane(static_cast<uint32_t>(idx), 0));
-}
-
-__device__ void ring_release(StealSlot *slots, int nslots, int idx, unsigned long long pos) {
-    wait_memory();
-    if (lane_id() == 0) store_agent(&slots[idx].seq, pos + static_cast<unsigned long long>(nslots));
+    return -1;
 }
 
 // Inclusive prefix sum over the wavefront.
@@ -409,12 +409,13 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     return x;
 }
 
-// Dynamic balancing (Sec. 4.3): give the upper half of the unscattered tasks of
-// the shallowest non-leaf level with at least `threshold` of them to an idle
-// wavefront.  The donor keeps the lower half by moving that level's end.
-// Returns true if a donation was published.
+// Dynamic balancing (Sec. 4.3): when wavefronts wait for work, give one of
+// them the upper half of the unscattered tasks of this wavefront's
+// shallowest non-leaf level holding at least `threshold` of them ("split the
+// stack in half").  The donor keeps the lower half by moving that level's end.
+// Returns true if work was handed over.
 template <int K>
-__device__ __forceinline__ bool donate(WaveStack<K> &S, const SearchArgs &a, int base, int l, uint32_t lane) {
+__device__ bool donate(WaveStack<K> &S, const SearchArgs &a, int base, int l, uint32_t lane) {
     const int k = a.plan.k;
     const int top = l < k - 2 ? l : k - 2;
     for (int L = base; L <= top; ++L) {
@@ -428,6 +429,10 @@ __device__ __forceinline__ bool donate(WaveStack<K> &S, const SearchArgs &a, int
         const uint32_t incl = wave_incl_scan(rem);
         const uint32_t total = read_lane(incl, 63);
         if (total < static_cast<uint32_t>(a.steal_threshold)) continue;
+        Control *ctl = a.ctl;
+        const int32_t thief = claim_idle(a, (blockIdx.x * 37u) & 0xffffu);
+        if (thief < 0) return false;
+        if (lane == 0) atomicAdd(&ctl->idle_count, -1);
         // split at h: the donor keeps tasks [0, h), the thief takes [h, total)
         const uint32_t h = total / 2;
         const uint32_t excl = incl - rem;
@@ -435,35 +440,29 @@ __device__ __forceinline__ bool donate(WaveStack<K> &S, const SearchArgs &a, int
         const uint32_t p = static_cast<uint32_t>(__builtin_ctzll(hit));
         const uint32_t excl_p = read_lane(excl, p);
         const uint32_t pj = (p == ci ? cjo : 0u) + (h - excl_p);
-        Control *ctl = a.ctl;
-        lane0_add(&ctl->busy, 1);  // counted before it becomes visible
-        unsigned long long pos;
-        const int idx = ring_claim(ctl, a.steal, a.steal_slots, &pos);
-        if (idx < 0) {
-            lane0_add(&ctl->busy, -1);
-            return false;
-        }
-        StealSlot &sl = a.steal[idx];
-        const bool mine = lane >= p && lane <= ei && S.cj[L][lane] != 0xffu;
+        Mailbox &mb = a.mail[thief];
+        const bool mine = lane >= p && lane <= ei && (S.cl[L][lane] & 0xffu) != 0xffu;
         const uint64_t lanes = ballot(mine);
         if (mine) {
             uint32_t q = lane;
             for (int i = L - 1; i >= 0; --i) {
-                store_agent(&sl.rows[lane * kMaxK + i], S.v[i][q]);
-                q = S.pid[i][q];
+                store_agent(&mb.rows[lane * kMaxK + i], S.v[i][q]);
+                q = ent_pid(S, i, q);
             }
         }
         if (lane == 0) {
-            store_agent(&sl.lanes, static_cast<unsigned long long>(lanes));
-            store_agent(&sl.depth, L);
-            store_agent(&sl.pi, static_cast<int32_t>(p));
-            store_agent(&sl.pj, static_cast<int32_t>(pj));
-            store_agent(&sl.ei, static_cast<int32_t>(ei));
-            store_agent(&sl.ej, static_cast<int32_t>(ej));
+            store_agent(&mb.lanes, static_cast<unsigned long long>(lanes));
+            store_agent(&mb.depth, L);
+            store_agent(&mb.pi, static_cast<int32_t>(p));
+            store_agent(&mb.pj, static_cast<int32_t>(pj));
+            store_agent(&mb.ei, static_cast<int32_t>(ei));
+            store_agent(&mb.ej, static_cast<int32_t>(ej));
+            atomicAdd(&ctl->busy, 1);  // the thief is busy from the hand-over on
             S.end_i[L] = p;
             S.end_j[L] = pj;
         }
-        ring_publish(a.steal, idx, pos);
+        wait_memory();
+        if (lane == 0) store_agent(&mb.status, static_cast<unsigned int>(kMailFull));
         return true;
     }
     return false;
@@ -475,18 +474,40 @@ enum Mode { kCount = 0, kEnumerate = 1, kExpand = 2 };
 // donation once the pool is empty), load it as the bottom of its stack, and run
 // Alg. 2's Search iteratively until the stack is empty.  kExpand stops at the
 // pool level and appends the valid extensions to the next pool instead (one
-// breadth-first step of the initialisation); it never steals.
+// breadth-first step of the initialisation); donations then split the long
+// lists of hub rows at that level.
+// Expansion output is staged in LDS and written out kStageRows rows at a time:
+// one atomic and coalesced stores per flush instead of per scatter round.
+constexpr int kStageRows = 128;
+constexpr int kStageWidth = 8;  // pool rows up to this many positions are staged
+
+__device__ __forceinline__ void flush_stage(int32_t *stage, uint32_t &staged, int width, const SearchArgs &a) {
+    if (staged == 0) return;
+    const unsigned long long b0 = lane0_atomic_add(&a.ctl->out_rows, staged);
+    const unsigned long long n_ok = b0 >= a.out_cap ? 0ull
+                                    : (a.out_cap - b0 < staged ? a.out_cap - b0 : static_cast<unsigned long long>(staged));
+    const uint32_t ints = static_cast<uint32_t>(n_ok) * static_cast<uint32_t>(width);
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t t = lane_id(); t < ints; t += kWave) a.out[b0 * width + t] = stage[t];
+    __builtin_amdgcn_wave_barrier();
+    staged = 0;
+}
+
 template <int K, int MODE>
-__global__ __launch_bounds__(kBlock, 5) void search_kernel(SearchArgs a) {
+__global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
     __shared__ WaveStack<K> stacks[kWavesPerBlock];
+    __shared__ int32_t stage_all[kWavesPerBlock][MODE == kExpand ? kStageRows * kStageWidth : 1];
     WaveStack<K> &S = stacks[threadIdx.x / kWave];
+    int32_t *stage = stage_all[threadIdx.x / kWave];
+    uint32_t staged = 0;
     const uint32_t lane = lane_id();
     const int k = a.plan.k;
     const int d = a.plan.depth;
     Control *ctl = a.ctl;
-    const bool stealing = MODE != kExpand && a.steal != nullptr;
+    const bool stealing = a.mail != nullptr;
+    const uint32_t wave_id = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
 
-    uint64_t my_tasks = 0;
+    uint64_t my_tasks = 0, my_scanned = 0, my_lookups = 0;
     uint32_t my_probes = 0;
     uint64_t my_probes_total = 0;
     uint64_t w_groups = 0, w_active = 0, w_issued = 0, w_count = 0, w_steals = 0;
@@ -512,13 +533,13 @@ __global__ __launch_bounds__(kBlock, 5) void search_kernel(SearchArgs a) {
                         v = a.pool[(r0 + lane) * static_cast<unsigned long long>(d) + i];
                         vi = a.vinfo[v];
                     }
-                    S.v[i][lane] = v;
-                    S.st[i][lane] = vi.x;
-                    S.dg[i][lane] = vi_deg(vi);
-                    S.pid[i][lane] = static_cast<uint8_t>(lane);
+                    push_entry(S, i, lane, v, vi, lane);
                 }
                 const uint64_t F0 = ballot(mine);
-                my_tasks += generate_tasks(S, a.plan, d, F0, lane);
+                const Gen g = generate_tasks(S, a, d, F0, lane);
+                my_tasks += g.tasks;
+                my_scanned += g.scanned;
+                my_lookups += g.lookups;
                 w_groups += __popcll(F0);
                 open_level(S, d, lane);
                 have = true;
@@ -529,63 +550,67 @@ __global__ __launch_bounds__(kBlock, 5) void search_kernel(SearchArgs a) {
         if (!have) {
             if (!stealing) break;
             // idle: wait for a donation until nobody holds work or the search aborts
-            lane0_add(&ctl->busy, -1);
-            lane0_add(&ctl->idle, 1);
-            int idx = -1;
-            unsigned long long pos = 0;
-            uint32_t nap = 1;  // exponential back-off keeps idle polling off the memory system
-            for (;;) {
-                for (uint32_t z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(32);
-                nap = nap < 64u ? nap * 2u : 64u;
-                if (deadline && wall_clock64() > deadline) set_abort(ctl, kAbortTime);
-                unsigned int ab = 0;
-                int busy = 0;
-                unsigned long long queued = 0;
-                if (lane == 0) {
-                    ab = load_agent(&ctl->abort);
-                    busy = load_agent(&ctl->busy);
-                    queued = load_agent(&ctl->q_tail) - load_agent(&ctl->q_head);
-                }
-                if (read_lane(ab, 0) != kAbortNone) break;
-                if (read_lane(static_cast<uint32_t>(busy), 0) == 0) break;
-                if (read_lane64(queued, 0) == 0) continue;
-                idx = ring_take(ctl, a.steal, a.steal_slots, &pos);
-                if (idx >= 0) break;
-                nap = 1;
+            Mailbox &mb = a.mail[wave_id];
+            if (lane == 0) store_agent(&mb.status, static_cast<unsigned int>(kMailWaiting));
+            wait_memory();
+            if (lane == 0) {
+                atomicAdd(&ctl->busy, -1);
+                atomicAdd(&ctl->idle_count, 1);
+                __hip_atomic_fetch_or(&a.idle_bits[wave_id / 64u], 1ull << (wave_id % 64u), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
             }
-            if (idx < 0) break;
-            lane0_add(&ctl->idle, -1);
+            bool got = false;
+            uint32_t nap = 1;  // exponential back-off on the wavefront's own mailbox
+            for (uint32_t iter = 0;; ++iter) {
+                for (uint32_t z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(16);
+                nap = nap < 32u ? nap * 2u : 32u;
+                unsigned int stt = 0;
+                if (lane == 0) stt = load_agent(&mb.status);
+                if (read_lane(stt, 0) == kMailFull) {
+                    got = true;
+                    break;
+                }
+                if ((iter & 7u) == 7u) {
+                    if (deadline && wall_clock64() > deadline) set_abort(ctl, kAbortTime);
+                    unsigned int ab = 0;
+                    int busy = 0;
+                    if (lane == 0) {
+                        ab = load_agent(&ctl->abort);
+                        busy = load_agent(&ctl->busy);
+                    }
+                    if (read_lane(ab, 0) != kAbortNone) break;
+                    if (read_lane(static_cast<uint32_t>(busy), 0) == 0) break;
+                }
+            }
+            if (!got) break;
             // the donated work: parent rows at level L-1 and a task range at level L
-            StealSlot &sl = a.steal[idx];
-            const int L = load_agent(&sl.depth);
-            const uint64_t lanes = load_agent(&sl.lanes);
+            const int L = load_agent(&mb.depth);
+            const uint64_t lanes = load_agent(&mb.lanes);
             const bool mine = (lanes >> lane) & 1ull;
             for (int i = 0; i < L; ++i) {
                 int32_t v = 0;
                 VInfo vi = make_uint2(0u, 0u);
                 if (mine) {
-                    v = load_agent(&sl.rows[lane * kMaxK + i]);
+                    v = load_agent(&mb.rows[lane * kMaxK + i]);
                     vi = a.vinfo[v];
                 }
-                S.v[i][lane] = v;
-                S.st[i][lane] = vi.x;
-                S.dg[i][lane] = vi_deg(vi);
-                S.pid[i][lane] = static_cast<uint8_t>(lane);
+                push_entry(S, i, lane, v, vi, lane);
             }
-            generate_tasks(S, a.plan, L, lanes, lane);  // already counted by the donor
+            generate_tasks(S, a, L, lanes, lane);  // already counted by the donor
             if (lane == 0) {
-                S.cur_i[L] = static_cast<uint32_t>(load_agent(&sl.pi));
-                S.cur_j[L] = static_cast<uint32_t>(load_agent(&sl.pj));
-                S.end_i[L] = static_cast<uint32_t>(load_agent(&sl.ei));
-                S.end_j[L] = static_cast<uint32_t>(load_agent(&sl.ej));
+                S.cur_i[L] = static_cast<uint32_t>(load_agent(&mb.pi));
+                S.cur_j[L] = static_cast<uint32_t>(load_agent(&mb.pj));
+                S.end_i[L] = static_cast<uint32_t>(load_agent(&mb.ei));
+                S.end_j[L] = static_cast<uint32_t>(load_agent(&mb.ej));
             }
-            ring_release(a.steal, a.steal_slots, idx, pos);
+            wait_memory();
+            if (lane == 0) store_agent(&mb.status, static_cast<unsigned int>(kMailEmpty));
             base = L;
             ++w_steals;
         }
         int l = base;
         while (l >= base) {
-            const Round r = scatter(S, a.col, l, lane);
+            const Round r = scatter(S, a.lcol, l, lane);
             if (r.ntask == 0) {
                 --l;
                 continue;
@@ -597,12 +622,23 @@ __global__ __launch_bounds__(kBlock, 5) void search_kernel(SearchArgs a) {
             const uint64_t m = ballot(ok);
             if (MODE == kExpand) {
                 if (m) {
-                    const unsigned long long b0 = lane0_atomic_add(&ctl->out_rows, __popcll(m));
-                    const unsigned long long slot = b0 + popc_below(m);
-                    if (ok && slot < a.out_cap) {
-                        int32_t *row = a.out + slot * static_cast<unsigned long long>(d + 1);
-                        for (int i = 0; i < d; ++i) row[i] = S.v[i][r.owner];
-                        row[d] = r.v;
+                    const uint32_t nv = static_cast<uint32_t>(__popcll(m));
+                    if (d + 1 <= kStageWidth) {
+                        if (staged + nv > static_cast<uint32_t>(kStageRows)) flush_stage(stage, staged, d + 1, a);
+                        if (ok) {
+                            int32_t *row = stage + (staged + popc_below(m)) * static_cast<uint32_t>(d + 1);
+                            for (int i = 0; i < d; ++i) row[i] = S.v[i][r.owner];
+                            row[d] = r.v;
+                        }
+                        staged += nv;
+                    } else {
+                        const unsigned long long b0 = lane0_atomic_add(&ctl->out_rows, nv);
+                        const unsigned long long slot = b0 + popc_below(m);
+                        if (ok && slot < a.out_cap) {
+                            int32_t *row = a.out + slot * static_cast<unsigned long long>(d + 1);
+                            for (int i = 0; i < d; ++i) row[i] = S.v[i][r.owner];
+                            row[d] = r.v;
+                        }
                     }
                 }
             } else if (l == k - 1) {
@@ -615,17 +651,17 @@ __global__ __launch_bounds__(kBlock, 5) void search_kernel(SearchArgs a) {
                         uint32_t q = r.owner;
                         for (int i = l - 1; i >= 0; --i) {
                             row[a.plan.phi[i]] = S.v[i][q];
-                            q = S.pid[i][q];
+                            q = ent_pid(S, i, q);
                         }
                     }
                 }
                 w_count += __popcll(m);
             } else if (m) {
-                S.v[l][lane] = r.v;
-                S.st[l][lane] = vi.x;
-                S.dg[l][lane] = vi_deg(vi);
-                S.pid[l][lane] = static_cast<uint8_t>(r.owner);
-                my_tasks += generate_tasks(S, a.plan, l + 1, m, lane);
+                push_entry(S, l, lane, r.v, vi, r.owner);
+                const Gen g = generate_tasks(S, a, l + 1, m, lane);
+                my_tasks += g.tasks;
+                my_scanned += g.scanned;
+                my_lookups += g.lookups;
                 w_groups += __popcll(m);
                 open_level(S, l + 1, lane);
                 ++l;
@@ -641,15 +677,10 @@ __global__ __launch_bounds__(kBlock, 5) void search_kernel(SearchArgs a) {
                     if (deadline && wall_clock64() > deadline) set_abort(ctl, kAbortTime);
                     if (load_abort(ctl) != kAbortNone) stop = true;
                     if (stealing && !stop && (rounds & 127u) == 0) {  // idle wavefronts exist only once the pool is empty
-                        int idle = 0;
-                        unsigned long long queued = 0;
-                        if (lane == 0) {
-                            idle = load_agent(&ctl->idle);
-                            queued = load_agent(&ctl->q_tail) - load_agent(&ctl->q_head);
-                        }
-                        idle = static_cast<int>(read_lane(static_cast<uint32_t>(idle), 0));
-                        queued = read_lane64(queued, 0);
-                        if (idle > 0 && static_cast<unsigned long long>(idle) > queued) donate(S, a, base, l, lane);
+                        int waiting = 0;
+                        if (lane == 0) waiting = load_agent(&ctl->idle_count);
+                        if (static_cast<int>(read_lane(static_cast<uint32_t>(waiting), 0)) > 0)
+                            donate(S, a, base, l, lane);
                     }
                 }
                 my_probes_total += my_probes;
@@ -658,13 +689,18 @@ __global__ __launch_bounds__(kBlock, 5) void search_kernel(SearchArgs a) {
             }
         }
     }
+    if (MODE == kExpand) flush_stage(stage, staged, d + 1, a);
     my_probes_total += my_probes;
     const uint64_t tasks = wave_sum64(my_tasks);
+    const uint64_t scanned = wave_sum64(my_scanned);
+    const uint64_t lookups = wave_sum64(my_lookups);
     const uint64_t probes = wave_sum64(my_probes_total);
     if (lane == 0) {
         if (w_count) atomicAdd(&ctl->count, w_count);
         atomicAdd(&ctl->groups, w_groups);
         atomicAdd(&ctl->tasks, tasks);
+        atomicAdd(&ctl->scanned, scanned);
+        atomicAdd(&ctl->lookups, lookups);
         atomicAdd(&ctl->lanes_active, w_active);
         atomicAdd(&ctl->lanes_issued, w_issued);
         atomicAdd(&ctl->probes, probes);
@@ -672,9 +708,10 @@ __global__ __launch_bounds__(kBlock, 5) void search_kernel(SearchArgs a) {
     }
 }
 
-__global__ void steal_init_kernel(StealSlot *slots, int32_t n) {
+__global__ void steal_init_kernel(Mailbox *mail, unsigned long long *idle_bits, int32_t n) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) slots[i].seq = static_cast<unsigned long long>(i);
+    if (i < n) mail[i].status = kMailEmpty;
+    if (i < (n + 63) / 64) idle_bits[i] = 0ull;
 }
 
 // Candidates of the first query vertex: label and degree filter over all of V(G).
@@ -700,10 +737,12 @@ __global__ __launch_bounds__(256) void root_scan_kernel(const VInfo *__restrict_
     }
 }
 
-// Upper bound on the size of the next pool level: sum over rows of |C^L|.
+// Upper bound on the size of the next pool level: sum over rows of the smallest
+// candidate slice among the row's backward neighbours (the slice GenerateTask scans).
 __global__ __launch_bounds__(256) void measure_kernel(SearchArgs a) {
     const int d = a.plan.depth;
     const uint32_t bw = a.plan.bwd[d];
+    const uint32_t lab = a.loff_stride > 1 ? static_cast<uint32_t>(a.plan.lab[d]) : 0u;
     uint64_t sum = 0;
     const unsigned long long stride = static_cast<unsigned long long>(gridDim.x) * blockDim.x;
     for (unsigned long long r = static_cast<unsigned long long>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -711,8 +750,11 @@ __global__ __launch_bounds__(256) void measure_kernel(SearchArgs a) {
         uint32_t best = 0xffffffffu;
         for (int i = 0; i < d; ++i) {
             if ((bw >> i) & 1u) {
-                const uint32_t dg = vi_deg(a.vinfo[a.pool[r * static_cast<unsigned long long>(d) + i]]);
-                best = dg < best ? dg : best;
+                const uint32_t *o = a.loff +
+                    static_cast<unsigned long long>(a.pool[r * static_cast<unsigned long long>(d) + i]) *
+                        a.loff_stride + lab;
+                const uint32_t n = o[1] - o[0];
+                best = n < best ? n : best;
             }
         }
         sum += best;
@@ -733,7 +775,9 @@ hipError_t launch_persistent(const SearchArgs &a, int num_cu, int waves_per_cu, 
         int want = (waves_per_cu + kWavesPerBlock - 1) / kWavesPerBlock;
         if (want < per_cu) per_cu = want;
     }
-    const int blocks = num_cu * per_cu;
+    int blocks = num_cu * per_cu;
+    if (a.mail && blocks * kWavesPerBlock > a.steal_slots) blocks = a.steal_slots / kWavesPerBlock;  // one mailbox each
+    if (blocks < 1) blocks = 1;
     if (grid_waves) *grid_waves = blocks * kWavesPerBlock;
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
@@ -778,9 +822,9 @@ hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int wa
     return launch_levels<kCount>(a.plan.k, a, num_cu, waves_per_cu, s, grid_waves_out);
 }
 
-hipError_t launch_steal_init(StealSlot *slots, int32_t n, hipStream_t s) {
+hipError_t launch_steal_init(Mailbox *mail, unsigned long long *idle_bits, int32_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(steal_init_kernel, dim3((n + 255) / 256), dim3(256), 0, s, slots, n);
+    hipLaunchKernelGGL(steal_init_kernel, dim3((n + 255) / 256), dim3(256), 0, s, mail, idle_bits, n);
     return hipGetLastError();
 }
 
