@@ -279,7 +279,8 @@ def main() -> int:
         "config": {"workload": w.name, "graph_vertices": w.graph.n, "graph_edges": w.graph.num_edges,
                    "queries": len(w.queries), "query_sizes": sorted({q.k for q in w.queries}),
                    "cap": cap, "time_limit_s": limit, "order": "RI heuristic",
-                   "tau": args.tau if args.tau else 1000000, "work_stealing": not args.disable_stealing},
+                   "tau": args.tau if args.tau else "64 rows per resident wavefront",
+                   "work_stealing": not args.disable_stealing},
         "intersected_edges_per_s": tasks / wall,
         "scanned_candidates_per_s": sum(r.scanned for r in flat) / wall,
         "query_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),

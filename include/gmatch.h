@@ -52,8 +52,10 @@ typedef struct gm_engine gm_engine;
 typedef struct {
     /* Initial task pool threshold tau (Sec. 4.3, "Initialization Phase"): the
      * breadth-first expansion stops at the first level holding >= tau partial
-     * matches.  0 = default 1,000,000.  Negative = no expansion: the pool is the
-     * candidate set of the first query vertex (the BFS-disabled mode of Sec. 6.2). */
+     * matches.  0 = default: 64 rows (one full batch) for every wavefront the
+     * search keeps resident, about 2.5e5 on MI355X (the paper's own setting is
+     * 1e6).  Negative = no expansion: the pool is the candidate set of the first
+     * query vertex (the BFS-disabled mode of Sec. 6.2). */
     int64_t tau;
     /* Largest pool the expansion may build, in rows; 0 = default 64 * tau. */
     int64_t pool_row_limit;

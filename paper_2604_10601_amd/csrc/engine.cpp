@@ -195,7 +195,12 @@ void free_graph(gm_engine *e) {
     e->label_id.clear();
 }
 
-int64_t option_tau(const gm_options &o) { return o.tau == 0 ? 1000000 : o.tau; }
+// tau (Sec. 4.3): the option, or by default one full batch of 64 pool rows for
+// every wavefront the search launch keeps resident (about 2.5e5 on MI355X).
+int64_t option_tau(const gm_engine *e, int32_t k) {
+    if (e->opt.tau != 0) return e->opt.tau;
+    return 64LL * gm::search_waves(k, e->num_cu, e->opt.waves_per_cu);
+}
 
 gm_status check_graph(gm_engine *e, int32_t n, const int64_t *row_ptr, const int32_t *col, bool symmetric) {
     if (row_ptr[0] != 0) return e->fail(GM_ERR_GRAPH, "row_ptr[0] must be 0");
@@ -371,7 +376,7 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
     }
 
     // Initialisation phase (Sec. 4.3): breadth-first levels until >= tau rows.
-    const int64_t tau = option_tau(e->opt);
+    const int64_t tau = option_tau(e, q->k);
     const int64_t row_limit = e->opt.pool_row_limit > 0 ? e->opt.pool_row_limit : 64 * std::max<int64_t>(tau, 1);
     bool aborted = false;
     while (tau > 0 && pool_rows > 0 && pool_rows < static_cast<uint64_t>(tau) && depth < q->k - 1) {

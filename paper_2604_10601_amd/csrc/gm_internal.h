@@ -106,6 +106,8 @@ hipError_t launch_measure(const SearchArgs &a, int num_cu, hipStream_t s);
 hipError_t launch_expand(const SearchArgs &a, int num_cu, hipStream_t s);
 hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int waves_per_cu, hipStream_t s,
                          int *grid_waves_out);
+// Wavefronts a depth-first search launch for a query of `levels` positions keeps resident.
+int search_waves(int levels, int num_cu, int waves_per_cu);
 hipError_t launch_steal_init(Mailbox *mail, unsigned long long *idle_bits, int32_t n, hipStream_t s);
 
 }  // namespace gm

@@ -80,31 +80,61 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
     return x;
 }
 
-// Is v in the ascending list col[lo, lo + n)?  Adds the 4-byte reads made to probes.
-__device__ __forceinline__ bool list_contains(const int32_t *__restrict__ col, uint32_t lo, uint32_t n, int32_t v,
-                                              uint32_t lin, uint32_t &probes) {
-    while (n > lin) {
-        uint32_t h = n >> 1;
-        int32_t x = col[lo + h];
-        ++probes;
-        if (x == v) return true;
-        if (x < v) {
-            lo += h + 1;
-            n -= h + 1;
-        } else {
-            n = h;
+// Membership of v in up to kLists ascending lists col[lo[s], lo[s] + n[s]) at
+// once (n[s] == 0 marks an unused slot).  The lists are bisected in lockstep,
+// so one round trip serves every list: a candidate with several backward
+// neighbours waits for the longest search, not for the sum of them.  Each
+// range is narrowed until at most kTail entries remain, and those tails are
+// read with independent loads (indices clamped into the list).  Returns true
+// iff v is in every used list; adds the 4-byte reads made to probes.
+constexpr int kLists = 4;
+constexpr uint32_t kTail = 4;
+
+__device__ __forceinline__ bool in_all_lists(const int32_t *__restrict__ col, uint32_t (&lo)[kLists],
+                                             uint32_t (&n)[kLists], int32_t v, uint32_t &probes) {
+    bool found[kLists];
+#pragma unroll
+    for (int s = 0; s < kLists; ++s) found[s] = n[s] == 0u;
+    for (;;) {
+        bool more = false;
+#pragma unroll
+        for (int s = 0; s < kLists; ++s) more |= !found[s] && n[s] > kTail;
+        if (!more) break;
+        int32_t x[kLists];
+        uint32_t h[kLists];
+#pragma unroll
+        for (int s = 0; s < kLists; ++s) {
+            h[s] = n[s] >> 1;
+            const bool act = !found[s] && n[s] > kTail;
+            x[s] = act ? col[lo[s] + h[s]] : 0;
+            probes += act;
+        }
+#pragma unroll
+        for (int s = 0; s < kLists; ++s) {
+            if (found[s] || n[s] <= kTail) continue;
+            if (x[s] == v) {
+                found[s] = true;
+            } else if (x[s] < v) {
+                lo[s] += h[s] + 1u;
+                n[s] -= h[s] + 1u;
+            } else {
+                n[s] = h[s];
+            }
         }
     }
-    if (n == 0) return false;
-    // n <= kLinear: independent loads, indices clamped into the list
-    bool f = false;
+    bool all = true;
 #pragma unroll
-    for (uint32_t i = 0; i < kLinear; ++i) {
-        uint32_t idx = lo + (i < n ? i : n - 1);
-        f |= (col[idx] == v);
+    for (int s = 0; s < kLists; ++s) {
+        if (found[s]) continue;
+        bool f = false;
+        if (n[s] != 0u) {
+#pragma unroll
+            for (uint32_t i = 0; i < kTail; ++i) f |= col[lo[s] + (i < n[s] ? i : n[s] - 1u)] == v;
+            probes += n[s];
+        }
+        all &= f;
     }
-    probes += n;
-    return f;
+    return all;
 }
 
 // Per-wavefront stack in LDS (Sec. 5.1: S is |V(Q)| x warp width), 20 bytes per
@@ -298,8 +328,14 @@ __device__ __forceinline__ bool process(WaveStack<K> &S, const SearchArgs &a, in
     ok = ok && vi_lab(vi) == static_cast<uint32_t>(a.plan.lab[l]) &&
          vi_deg(vi) >= static_cast<uint32_t>(a.plan.qdeg[l]);
     if (ok) {
+        // One walk down the chain: injectivity at every level; the neighbour
+        // lists of the other backward neighbours are collected (kLists at a
+        // time, the slot index being the same in every lane) and tested together.
         const uint32_t bw = a.plan.bwd[l];
         const uint32_t js = S.cl[l][r.owner] & 0xffu;
+        uint32_t lo[kLists] = {0u, 0u, 0u, 0u};
+        uint32_t n[kLists] = {0u, 0u, 0u, 0u};
+        int used = 0;
         uint32_t q = r.owner;
         for (int i = l - 1; i >= 0; --i) {
             const int32_t w = S.v[i][q];
@@ -307,14 +343,25 @@ __device__ __forceinline__ bool process(WaveStack<K> &S, const SearchArgs &a, in
                 ok = false;
                 break;
             }
-            if (((bw >> i) & 1u) && static_cast<uint32_t>(i) != js) {
-                if (!list_contains(a.col, S.st[i][q], ent_deg(S, i, q), r.v, a.linear_probe, probes)) {
-                    ok = false;
-                    break;
+            if ((bw >> i) & 1u) {
+                const uint32_t st = S.st[i][q];
+                const uint32_t len = static_cast<uint32_t>(i) == js ? 0u : ent_deg(S, i, q);
+                if (used == 0) { lo[0] = st; n[0] = len; }
+                else if (used == 1) { lo[1] = st; n[1] = len; }
+                else if (used == 2) { lo[2] = st; n[2] = len; }
+                else { lo[3] = st; n[3] = len; }
+                if (++used == kLists) {
+                    if (!in_all_lists(a.col, lo, n, r.v, probes)) {
+                        ok = false;
+                        break;
+                    }
+                    used = 0;
+                    n[0] = n[1] = n[2] = n[3] = 0u;
                 }
             }
             q = ent_pid(S, i, q);
         }
+        if (ok && used > 0) ok = in_all_lists(a.col, lo, n, r.v, probes);
     }
     return ok;
 }
@@ -814,6 +861,22 @@ hipError_t launch_measure(const SearchArgs &a, int num_cu, hipStream_t s) {
 
 hipError_t launch_expand(const SearchArgs &a, int num_cu, hipStream_t s) {
     return launch_levels<kExpand>(a.plan.depth + 1, a, num_cu, 0, s, nullptr);
+}
+
+int search_waves(int levels, int num_cu, int waves_per_cu) {
+    auto occ = [&](auto kern) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        if (waves_per_cu > 0) {
+            const int want = (waves_per_cu + kWavesPerBlock - 1) / kWavesPerBlock;
+            if (want < per_cu) per_cu = want;
+        }
+        return num_cu * per_cu * kWavesPerBlock;
+    };
+    if (levels <= 8) return occ(search_kernel<8, kCount>);
+    if (levels <= 16) return occ(search_kernel<16, kCount>);
+    return occ(search_kernel<32, kCount>);
 }
 
 hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int waves_per_cu, hipStream_t s,
