@@ -312,12 +312,15 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
     HIP_TRY(e, hipMemsetAsync(e->d_ctl, 0, sizeof(Control), e->stream));
     st = ensure_buffer(e, &e->d_pool[0], &e->pool_cap[0], static_cast<size_t>(e->n));
     if (st) return st;
-    HIP_TRY(e, gm::launch_root_scan(e->d_vinfo, e->n, plan.lab[0], plan.qdeg[0], e->d_pool[0], 0, e->d_ctl,
-                                    e->num_cu, e->stream));
+    // the root scan also bounds the next level: each root's label slice for position 1
+    const int32_t lab1 = q->k >= 2 ? (e->loff_stride > 1 ? plan.lab[1] : 0) : -1;
+    HIP_TRY(e, gm::launch_root_scan(e->d_vinfo, e->n, plan.lab[0], plan.qdeg[0], e->d_pool[0], e->d_loff,
+                                    e->loff_stride, lab1, e->d_ctl, e->num_cu, e->stream));
     Control c{};
     st = read_ctl(e, &c);
     if (st) return st;
     uint64_t pool_rows = c.out_rows;
+    uint64_t bound = c.measure;  // upper bound on the rows of the next level
     int cur = 0;
     int32_t depth = 1;
 
@@ -383,18 +386,15 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
         a.plan.depth = depth;
         a.pool = e->d_pool[cur];
         a.pool_rows = pool_rows;
-        HIP_TRY(e, hipMemsetAsync(&e->d_ctl->measure, 0, sizeof(unsigned long long), e->stream));
-        HIP_TRY(e, gm::launch_measure(a, e->num_cu, e->stream));
-        st = read_ctl(e, &c);
-        if (st) return st;
-        const uint64_t bound = c.measure;
         if (bound > static_cast<uint64_t>(row_limit)) break;
         st = ensure_buffer(e, &e->d_pool[cur ^ 1], &e->pool_cap[cur ^ 1], bound * static_cast<size_t>(depth + 1));
         if (st) return st;
         HIP_TRY(e, hipMemsetAsync(&e->d_ctl->pool_next, 0, sizeof(unsigned long long), e->stream));
         HIP_TRY(e, hipMemsetAsync(&e->d_ctl->out_rows, 0, sizeof(unsigned long long), e->stream));
+        HIP_TRY(e, hipMemsetAsync(&e->d_ctl->measure, 0, sizeof(unsigned long long), e->stream));
         a.out = e->d_pool[cur ^ 1];
         a.out_cap = bound;
+        a.measure_next = depth + 1 < q->k - 1 ? 1 : 0;  // bound of the level after this one
         st = reset_stealing(e, a);
         if (st) return st;
         HIP_TRY(e, gm::launch_expand(a, e->num_cu, e->stream));
@@ -405,6 +405,7 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
             break;
         }
         pool_rows = c.out_rows;
+        bound = c.measure;
         cur ^= 1;
         ++depth;
     }

@@ -43,7 +43,7 @@ struct alignas(128) Control {
     int idle_count;                  // wavefronts whose bit is set in the idle bitmap
     int pad_idle[31];
     // written once per launch or read by the host only
-    unsigned long long measure;      // expansion bound: sum of |C^L| over pool rows
+    unsigned long long measure;      // bound on the next pool level (sum of smallest label slices)
     unsigned long long groups;
     unsigned long long tasks;
     unsigned long long lanes_active;
@@ -94,15 +94,17 @@ struct SearchArgs {
     unsigned long long *idle_bits; // bit w set: wavefront w waits for work
     int32_t steal_slots;       // number of mailboxes (>= wavefronts launched)
     int32_t steal_threshold;
-    int32_t linear_probe;      // lists this short are scanned, longer ones bisected
-    int32_t pad0;
+    int32_t linear_probe;      // unused
+    int32_t measure_next;      // expansion: add the next level's size bound to ctl->measure
     Plan plan;
 };
 
 // Launchers implemented in kernels.hip.  All return hipSuccess or the launch error.
+// measure_lab >= 0: also add up the candidates' label slices for position 1
+// (label id measure_lab) into ctl->measure, the bound of the next pool level.
 hipError_t launch_root_scan(const VInfo *vinfo, int32_t n, int32_t lab0, int32_t qdeg0, int32_t *pool,
-                            int count_only, Control *ctl, int num_cu, hipStream_t s);
-hipError_t launch_measure(const SearchArgs &a, int num_cu, hipStream_t s);
+                            const uint32_t *loff, int32_t loff_stride, int32_t measure_lab, Control *ctl, int num_cu,
+                            hipStream_t s);
 hipError_t launch_expand(const SearchArgs &a, int num_cu, hipStream_t s);
 hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int waves_per_cu, hipStream_t s,
                          int *grid_waves_out);

@@ -523,6 +523,25 @@ enum Mode { kCount = 0, kEnumerate = 1, kExpand = 2 };
 // pool level and appends the valid extensions to the next pool instead (one
 // breadth-first step of the initialisation); donations then split the long
 // lists of hub rows at that level.
+// Size bound of the level after an expansion, for one new row (positions 0..d,
+// position d being the row's candidate): its smallest label slice for position
+// d + 1 among that position's backward neighbours.
+template <int K>
+__device__ __forceinline__ uint32_t next_level_bound(const WaveStack<K> &S, const SearchArgs &a, int d,
+                                                     const Round &r) {
+    const uint32_t bw = a.plan.bwd[d + 1];
+    const uint32_t lab = a.loff_stride > 1 ? static_cast<uint32_t>(a.plan.lab[d + 1]) : 0u;
+    uint32_t best = 0xffffffffu;
+    for (int i = 0; i <= d; ++i) {
+        if (!((bw >> i) & 1u)) continue;
+        const int32_t w = i == d ? r.v : S.v[i][r.owner];
+        const uint32_t *o = a.loff + static_cast<unsigned long long>(w) * a.loff_stride + lab;
+        const uint32_t n = o[1] - o[0];
+        best = n < best ? n : best;
+    }
+    return best;
+}
+
 // Expansion output is staged in LDS and written out kStageRows rows at a time:
 // one atomic and coalesced stores per flush instead of per scatter round.
 constexpr int kStageRows = 128;
@@ -554,7 +573,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
     const bool stealing = a.mail != nullptr;
     const uint32_t wave_id = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
 
-    uint64_t my_tasks = 0, my_scanned = 0, my_lookups = 0;
+    uint64_t my_tasks = 0, my_scanned = 0, my_lookups = 0, my_bound = 0;
     uint32_t my_probes = 0;
     uint64_t my_probes_total = 0;
     uint64_t w_groups = 0, w_active = 0, w_issued = 0, w_count = 0, w_steals = 0;
@@ -676,6 +695,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
                             int32_t *row = stage + (staged + popc_below(m)) * static_cast<uint32_t>(d + 1);
                             for (int i = 0; i < d; ++i) row[i] = S.v[i][r.owner];
                             row[d] = r.v;
+                            if (a.measure_next) my_bound += next_level_bound(S, a, d, r);
                         }
                         staged += nv;
                     } else {
@@ -686,6 +706,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
                             for (int i = 0; i < d; ++i) row[i] = S.v[i][r.owner];
                             row[d] = r.v;
                         }
+                        if (ok && a.measure_next) my_bound += next_level_bound(S, a, d, r);
                     }
                 }
             } else if (l == k - 1) {
@@ -736,7 +757,13 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
             }
         }
     }
-    if (MODE == kExpand) flush_stage(stage, staged, d + 1, a);
+    if (MODE == kExpand) {
+        flush_stage(stage, staged, d + 1, a);
+        if (a.measure_next) {
+            const uint64_t b = wave_sum64(my_bound);
+            if (lane == 0 && b) atomicAdd(&ctl->measure, static_cast<unsigned long long>(b));
+        }
+    }
     my_probes_total += my_probes;
     const uint64_t tasks = wave_sum64(my_tasks);
     const uint64_t scanned = wave_sum64(my_scanned);
@@ -762,12 +789,17 @@ __global__ void steal_init_kernel(Mailbox *mail, unsigned long long *idle_bits, 
 }
 
 // Candidates of the first query vertex: label and degree filter over all of V(G).
+// With measure_lab >= 0 it also adds up each candidate's label slice for the
+// second position (its only backward neighbour is the first), the size bound of
+// the next pool level.
 __global__ __launch_bounds__(256) void root_scan_kernel(const VInfo *__restrict__ vinfo, int32_t n, int32_t lab0,
-                                                        int32_t qdeg0, int32_t *__restrict__ pool, int count_only,
-                                                        Control *ctl) {
+                                                        int32_t qdeg0, int32_t *__restrict__ pool,
+                                                        const uint32_t *__restrict__ loff, int32_t loff_stride,
+                                                        int32_t measure_lab, Control *ctl) {
     const uint32_t lane = lane_id();
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->t0 = wall_clock64();
     const long long stride = static_cast<long long>(gridDim.x) * blockDim.x;
+    uint64_t bound = 0;
     for (long long base = static_cast<long long>(blockIdx.x) * blockDim.x + (threadIdx.x & ~(kWave - 1)); base < n;
          base += stride) {
         const long long v = base + lane;
@@ -779,37 +811,20 @@ __global__ __launch_bounds__(256) void root_scan_kernel(const VInfo *__restrict_
         const uint64_t m = ballot(ok);
         if (m) {
             const unsigned long long b = lane0_atomic_add(&ctl->out_rows, __popcll(m));
-            if (ok && !count_only) pool[b + popc_below(m)] = static_cast<int32_t>(v);
-        }
-    }
-}
-
-// Upper bound on the size of the next pool level: sum over rows of the smallest
-// candidate slice among the row's backward neighbours (the slice GenerateTask scans).
-__global__ __launch_bounds__(256) void measure_kernel(SearchArgs a) {
-    const int d = a.plan.depth;
-    const uint32_t bw = a.plan.bwd[d];
-    const uint32_t lab = a.loff_stride > 1 ? static_cast<uint32_t>(a.plan.lab[d]) : 0u;
-    uint64_t sum = 0;
-    const unsigned long long stride = static_cast<unsigned long long>(gridDim.x) * blockDim.x;
-    for (unsigned long long r = static_cast<unsigned long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-         r < a.pool_rows; r += stride) {
-        uint32_t best = 0xffffffffu;
-        for (int i = 0; i < d; ++i) {
-            if ((bw >> i) & 1u) {
-                const uint32_t *o = a.loff +
-                    static_cast<unsigned long long>(a.pool[r * static_cast<unsigned long long>(d) + i]) *
-                        a.loff_stride + lab;
-                const uint32_t n = o[1] - o[0];
-                best = n < best ? n : best;
+            if (ok) {
+                pool[b + popc_below(m)] = static_cast<int32_t>(v);
+                if (measure_lab >= 0) {
+                    const uint32_t *o = loff + static_cast<unsigned long long>(v) * loff_stride + measure_lab;
+                    bound += o[1] - o[0];
+                }
             }
         }
-        sum += best;
     }
-    sum = wave_sum64(sum);
-    if (lane_id() == 0 && sum) atomicAdd(&a.ctl->measure, static_cast<unsigned long long>(sum));
+    if (measure_lab >= 0) {
+        bound = wave_sum64(bound);
+        if (lane == 0 && bound) atomicAdd(&ctl->measure, static_cast<unsigned long long>(bound));
+    }
 }
-
 
 template <int K, int MODE>
 hipError_t launch_persistent(const SearchArgs &a, int num_cu, int waves_per_cu, hipStream_t s, int *grid_waves) {
@@ -842,20 +857,13 @@ hipError_t launch_levels(int levels, const SearchArgs &a, int num_cu, int waves_
 }  // namespace
 
 hipError_t launch_root_scan(const VInfo *vinfo, int32_t n, int32_t lab0, int32_t qdeg0, int32_t *pool,
-                            int count_only, Control *ctl, int num_cu, hipStream_t s) {
+                            const uint32_t *loff, int32_t loff_stride, int32_t measure_lab, Control *ctl, int num_cu,
+                            hipStream_t s) {
     if (n <= 0) return hipSuccess;
     long long blocks = (static_cast<long long>(n) + 255) / 256;
     if (blocks > num_cu * 8LL) blocks = num_cu * 8LL;
     hipLaunchKernelGGL(root_scan_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, vinfo, n, lab0,
-                       qdeg0, pool, count_only, ctl);
-    return hipGetLastError();
-}
-
-hipError_t launch_measure(const SearchArgs &a, int num_cu, hipStream_t s) {
-    if (a.pool_rows == 0) return hipSuccess;
-    unsigned long long blocks = (a.pool_rows + 255) / 256;
-    if (blocks > static_cast<unsigned long long>(num_cu) * 8ull) blocks = static_cast<unsigned long long>(num_cu) * 8ull;
-    hipLaunchKernelGGL(measure_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, a);
+                       qdeg0, pool, loff, loff_stride, measure_lab, ctl);
     return hipGetLastError();
 }
 
