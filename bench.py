@@ -64,7 +64,7 @@ def read_traffic() -> dict | None:
         return None
 
 
-def make_workload(name: str, num_queries: int):
+def make_workload(name: str, num_queries: int, stride: int = 1):
     from paper_2604_10601_amd import workloads as wl
     if name == "medium":
         w = wl.medium_rmat20()
@@ -74,6 +74,7 @@ def make_workload(name: str, num_queries: int):
         w = wl.large_rmat24()
     else:
         raise SystemExit(f"unknown workload {name}")
+    w.queries = w.queries[::max(1, stride)]
     if num_queries > 0:
         w.queries = w.queries[:num_queries]
     return w
@@ -171,6 +172,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="medium", choices=["medium", "small", "large"])
     ap.add_argument("--queries", type=int, default=0, help="use only the first N queries (0 = all)")
+    ap.add_argument("--query-stride", type=int, default=1, help="use every S-th query")
+    ap.add_argument("--time-limit", type=float, default=-1.0, help="override the workload's per-query limit")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle time budget for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tau", type=int, default=0)
@@ -217,7 +220,9 @@ def main() -> int:
     import paper_2604_10601_amd as gm
 
     t = time.time()
-    w = make_workload(args.workload, args.queries)
+    w = make_workload(args.workload, args.queries, args.query_stride)
+    if args.time_limit >= 0:
+        w.time_limit_s = args.time_limit
     log(f"workload {w.name}: n={w.graph.n} |E|={w.graph.num_edges} queries={len(w.queries)} "
         f"({time.time() - t:.1f} s to generate)")
     e = gm.Engine(device=0, tau=args.tau, waves_per_cu=args.waves_per_cu,

@@ -137,32 +137,51 @@ __device__ __forceinline__ bool in_all_lists(const int32_t *__restrict__ col, ui
     return all;
 }
 
-// Per-wavefront stack in LDS (Sec. 5.1: S is |V(Q)| x warp width), 20 bytes per
-// (level, lane).
-template <int K>
+// Per-wavefront stack in LDS (Sec. 5.1: S is |V(Q)| x warp width): 20 bytes per
+// (level, lane) plus 16 bytes per level, for exactly k levels (the launch sizes
+// the dynamic LDS from the query), so small queries leave room for more
+// wavefronts per CU.  Element (level i, lane q) of an array is at [i * 64 + q].
 struct WaveStack {
-    int32_t v[K][kWave];     // data vertex of the task at (level, lane)
-    uint32_t st[K][kWave];   // start of N(v) in col[] (ids ascending)
-    uint32_t dp[K][kWave];   // |N(v)| << 8 | lane of the parent entry at level - 1
-    uint32_t cs[K][kWave];   // parent lane's local candidate slice: start in lcol[]
-    uint32_t cl[K][kWave];   //   ... length << 8 | level of its source list (0xff = no list)
-    uint32_t cur_j[K];       // scatter cursor: offset in the current parent's slice
-    uint32_t cur_i[K];       // scatter cursor: current parent lane (64 = level exhausted)
-    uint32_t end_j[K];       // end of the level's task range: offset in parent end_i's slice
-    uint32_t end_i[K];       //   ... parent lane (64 = no bound: the whole pool)
-    uint8_t own[kWave];      // scatter scratch: parent starting at each slot
+    int32_t *v;       // data vertex of the task at (level, lane)
+    uint32_t *st;     // start of N(v) in col[] (ids ascending)
+    uint32_t *dp;     // |N(v)| << 8 | lane of the parent entry at level - 1
+    uint32_t *cs;     // parent lane's local candidate slice: start in lcol[]
+    uint32_t *cl;     //   ... length << 8 | level of its source list (0xff = no list)
+    uint32_t *cur_j;  // per level: scatter cursor, offset in the current parent's slice
+    uint32_t *cur_i;  //   ... current parent lane (64 = level exhausted)
+    uint32_t *end_j;  // per level: end of the task range, offset in parent end_i's slice
+    uint32_t *end_i;  //   ... parent lane (64 = no bound: the whole pool)
+    uint8_t *own;     // scatter scratch: parent starting at each slot
 };
 
-template <int K>
-__device__ __forceinline__ uint32_t ent_deg(const WaveStack<K> &S, int i, uint32_t q) { return S.dp[i][q] >> 8; }
-template <int K>
-__device__ __forceinline__ uint32_t ent_pid(const WaveStack<K> &S, int i, uint32_t q) { return S.dp[i][q] & 0xffu; }
+__host__ __device__ constexpr size_t stack_bytes(int levels) {
+    return static_cast<size_t>(levels) * (kWave * 20u + 16u) + kWave;
+}
 
-template <int K>
-__device__ __forceinline__ void push_entry(WaveStack<K> &S, int i, uint32_t lane, int32_t v, VInfo vi, uint32_t pid) {
-    S.v[i][lane] = v;
-    S.st[i][lane] = vi.x;
-    S.dp[i][lane] = (vi_deg(vi) << 8) | pid;
+__device__ __forceinline__ WaveStack carve_stack(uint8_t *base, int levels) {
+    WaveStack S;
+    const size_t plane = static_cast<size_t>(levels) * kWave * 4u;
+    S.v = reinterpret_cast<int32_t *>(base);
+    S.st = reinterpret_cast<uint32_t *>(base + plane);
+    S.dp = reinterpret_cast<uint32_t *>(base + 2 * plane);
+    S.cs = reinterpret_cast<uint32_t *>(base + 3 * plane);
+    S.cl = reinterpret_cast<uint32_t *>(base + 4 * plane);
+    uint32_t *lv = reinterpret_cast<uint32_t *>(base + 5 * plane);
+    S.cur_j = lv;
+    S.cur_i = lv + levels;
+    S.end_j = lv + 2 * levels;
+    S.end_i = lv + 3 * levels;
+    S.own = reinterpret_cast<uint8_t *>(lv + 4 * levels);
+    return S;
+}
+
+__device__ __forceinline__ uint32_t ent_deg(const WaveStack &S, int i, uint32_t q) { return S.dp[(i) * kWave + (q)] >> 8; }
+__device__ __forceinline__ uint32_t ent_pid(const WaveStack &S, int i, uint32_t q) { return S.dp[(i) * kWave + (q)] & 0xffu; }
+
+__device__ __forceinline__ void push_entry(WaveStack &S, int i, uint32_t lane, int32_t v, VInfo vi, uint32_t pid) {
+    S.v[(i) * kWave + (lane)] = v;
+    S.st[(i) * kWave + (lane)] = vi.x;
+    S.dp[(i) * kWave + (lane)] = (vi_deg(vi) << 8) | pid;
 }
 
 struct Gen {
@@ -178,8 +197,7 @@ struct Gen {
 // lists only the slice of candidates labelled L(phi[l]) can pass the label
 // check, so the smallest such slice is scanned instead (earliest position on
 // ties); it yields exactly the same valid extensions.
-template <int K>
-__device__ __forceinline__ Gen generate_tasks(WaveStack<K> &S, const SearchArgs &a, int l, uint64_t F,
+__device__ __forceinline__ Gen generate_tasks(WaveStack &S, const SearchArgs &a, int l, uint64_t F,
                                               uint32_t lane) {
     Gen g{0u, 0u, 0u};
     uint32_t cs = 0, cl = 0xffu;
@@ -196,12 +214,12 @@ __device__ __forceinline__ Gen generate_tasks(WaveStack<K> &S, const SearchArgs 
                 best_full = d < best_full ? d : best_full;
                 uint32_t sa, sn;
                 if (sliced) {
-                    const uint32_t *o = a.loff + static_cast<unsigned long long>(S.v[i][q]) * a.loff_stride + lab;
+                    const uint32_t *o = a.loff + static_cast<unsigned long long>(S.v[(i) * kWave + (q)]) * a.loff_stride + lab;
                     sa = o[0];
                     sn = o[1] - sa;
                     ++g.lookups;
                 } else {
-                    sa = S.st[i][q];
+                    sa = S.st[(i) * kWave + (q)];
                     sn = d;
                 }
                 if (sn <= best_n) {
@@ -217,13 +235,12 @@ __device__ __forceinline__ Gen generate_tasks(WaveStack<K> &S, const SearchArgs 
         cs = best_a;
         cl = (best_n << 8) | best_j;
     }
-    S.cs[l][lane] = cs;
-    S.cl[l][lane] = cl;
+    S.cs[(l) * kWave + (lane)] = cs;
+    S.cl[(l) * kWave + (lane)] = cl;
     return g;
 }
 
-template <int K>
-__device__ __forceinline__ void open_level(WaveStack<K> &S, int l, uint32_t lane) {
+__device__ __forceinline__ void open_level(WaveStack &S, int l, uint32_t lane) {
     if (lane == 0) {
         S.cur_i[l] = 0;
         S.cur_j[l] = 0;
@@ -234,11 +251,10 @@ __device__ __forceinline__ void open_level(WaveStack<K> &S, int l, uint32_t lane
 
 // Unscattered tasks of this lane's task group at level l, given the level's
 // cursor (ci, cjo) and end (ei, ej).  Also returns the group's slice.
-template <int K>
-__device__ __forceinline__ uint32_t remaining(const WaveStack<K> &S, int l, uint32_t lane, uint32_t ci, uint32_t cjo,
+__device__ __forceinline__ uint32_t remaining(const WaveStack &S, int l, uint32_t lane, uint32_t ci, uint32_t cjo,
                                               uint32_t ei, uint32_t ej, uint32_t &cst, uint32_t &cln) {
-    const uint32_t cl = S.cl[l][lane];
-    cst = S.cs[l][lane];
+    const uint32_t cl = S.cl[(l) * kWave + (lane)];
+    cst = S.cs[(l) * kWave + (lane)];
     cln = cl >> 8;
     if (lane < ci || lane > ei) return 0u;
     const uint32_t lo = lane == ci ? cjo : 0u;
@@ -254,8 +270,7 @@ struct Round {
 
 // ScatterTask (Alg. 2) for the whole wavefront: hand the next <= 64 tasks of
 // level l to lanes 0..ntask-1 and advance the level's cursor.
-template <int K>
-__device__ __forceinline__ Round scatter(WaveStack<K> &S, const int32_t *__restrict__ lcol, int l, uint32_t lane) {
+__device__ __forceinline__ Round scatter(WaveStack &S, const int32_t *__restrict__ lcol, int l, uint32_t lane) {
     Round r;
     const uint32_t ci = __builtin_amdgcn_readfirstlane(S.cur_i[l]);
     const uint32_t cjo = __builtin_amdgcn_readfirstlane(S.cur_j[l]);
@@ -319,8 +334,7 @@ __device__ __forceinline__ Round scatter(WaveStack<K> &S, const int32_t *__restr
 // Process (Alg. 2): label and degree filters, then one walk down the parent
 // chain checking injectivity and membership in every backward neighbour's list
 // other than the one the candidate came from.
-template <int K>
-__device__ __forceinline__ bool process(WaveStack<K> &S, const SearchArgs &a, int l, const Round &r, uint32_t lane,
+__device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, int l, const Round &r, uint32_t lane,
                                         VInfo &vi, uint32_t &probes) {
     bool ok = lane < r.ntask;
     vi = make_uint2(0u, 0u);
@@ -332,19 +346,19 @@ __device__ __forceinline__ bool process(WaveStack<K> &S, const SearchArgs &a, in
         // lists of the other backward neighbours are collected (kLists at a
         // time, the slot index being the same in every lane) and tested together.
         const uint32_t bw = a.plan.bwd[l];
-        const uint32_t js = S.cl[l][r.owner] & 0xffu;
+        const uint32_t js = S.cl[(l) * kWave + (r.owner)] & 0xffu;
         uint32_t lo[kLists] = {0u, 0u, 0u, 0u};
         uint32_t n[kLists] = {0u, 0u, 0u, 0u};
         int used = 0;
         uint32_t q = r.owner;
         for (int i = l - 1; i >= 0; --i) {
-            const int32_t w = S.v[i][q];
+            const int32_t w = S.v[(i) * kWave + (q)];
             if (w == r.v) {
                 ok = false;
                 break;
             }
             if ((bw >> i) & 1u) {
-                const uint32_t st = S.st[i][q];
+                const uint32_t st = S.st[(i) * kWave + (q)];
                 const uint32_t len = static_cast<uint32_t>(i) == js ? 0u : ent_deg(S, i, q);
                 if (used == 0) { lo[0] = st; n[0] = len; }
                 else if (used == 1) { lo[1] = st; n[1] = len; }
@@ -461,8 +475,7 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 // shallowest non-leaf level holding at least `threshold` of them ("split the
 // stack in half").  The donor keeps the lower half by moving that level's end.
 // Returns true if work was handed over.
-template <int K>
-__device__ bool donate(WaveStack<K> &S, const SearchArgs &a, int base, int l, uint32_t lane) {
+__device__ bool donate(WaveStack &S, const SearchArgs &a, int base, int l, uint32_t lane) {
     const int k = a.plan.k;
     const int top = l < k - 2 ? l : k - 2;
     for (int L = base; L <= top; ++L) {
@@ -488,12 +501,12 @@ __device__ bool donate(WaveStack<K> &S, const SearchArgs &a, int base, int l, ui
         const uint32_t excl_p = read_lane(excl, p);
         const uint32_t pj = (p == ci ? cjo : 0u) + (h - excl_p);
         Mailbox &mb = a.mail[thief];
-        const bool mine = lane >= p && lane <= ei && (S.cl[L][lane] & 0xffu) != 0xffu;
+        const bool mine = lane >= p && lane <= ei && (S.cl[(L) * kWave + (lane)] & 0xffu) != 0xffu;
         const uint64_t lanes = ballot(mine);
         if (mine) {
             uint32_t q = lane;
             for (int i = L - 1; i >= 0; --i) {
-                store_agent(&mb.rows[lane * kMaxK + i], S.v[i][q]);
+                store_agent(&mb.rows[lane * kMaxK + i], S.v[(i) * kWave + (q)]);
                 q = ent_pid(S, i, q);
             }
         }
@@ -526,15 +539,14 @@ enum Mode { kCount = 0, kEnumerate = 1, kExpand = 2 };
 // Size bound of the level after an expansion, for one new row (positions 0..d,
 // position d being the row's candidate): its smallest label slice for position
 // d + 1 among that position's backward neighbours.
-template <int K>
-__device__ __forceinline__ uint32_t next_level_bound(const WaveStack<K> &S, const SearchArgs &a, int d,
+__device__ __forceinline__ uint32_t next_level_bound(const WaveStack &S, const SearchArgs &a, int d,
                                                      const Round &r) {
     const uint32_t bw = a.plan.bwd[d + 1];
     const uint32_t lab = a.loff_stride > 1 ? static_cast<uint32_t>(a.plan.lab[d + 1]) : 0u;
     uint32_t best = 0xffffffffu;
     for (int i = 0; i <= d; ++i) {
         if (!((bw >> i) & 1u)) continue;
-        const int32_t w = i == d ? r.v : S.v[i][r.owner];
+        const int32_t w = i == d ? r.v : S.v[(i) * kWave + (r.owner)];
         const uint32_t *o = a.loff + static_cast<unsigned long long>(w) * a.loff_stride + lab;
         const uint32_t n = o[1] - o[0];
         best = n < best ? n : best;
@@ -559,12 +571,18 @@ __device__ __forceinline__ void flush_stage(int32_t *stage, uint32_t &staged, in
     staged = 0;
 }
 
-template <int K, int MODE>
+// LDS of one wavefront for a query of `levels` positions (stack, plus the output
+// staging buffer of an expansion).
+__host__ __device__ constexpr size_t wave_lds_bytes(int levels, bool expand) {
+    return stack_bytes(levels) + (expand ? static_cast<size_t>(kStageRows) * kStageWidth * 4u : 0u);
+}
+
+template <int MODE>
 __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
-    __shared__ WaveStack<K> stacks[kWavesPerBlock];
-    __shared__ int32_t stage_all[kWavesPerBlock][MODE == kExpand ? kStageRows * kStageWidth : 1];
-    WaveStack<K> &S = stacks[threadIdx.x / kWave];
-    int32_t *stage = stage_all[threadIdx.x / kWave];
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    uint8_t *mine = lds + (threadIdx.x / kWave) * wave_lds_bytes(a.plan.k, MODE == kExpand);
+    WaveStack S = carve_stack(mine, a.plan.k);
+    int32_t *stage = reinterpret_cast<int32_t *>(mine + stack_bytes(a.plan.k));
     uint32_t staged = 0;
     const uint32_t lane = lane_id();
     const int k = a.plan.k;
@@ -693,7 +711,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
                         if (staged + nv > static_cast<uint32_t>(kStageRows)) flush_stage(stage, staged, d + 1, a);
                         if (ok) {
                             int32_t *row = stage + (staged + popc_below(m)) * static_cast<uint32_t>(d + 1);
-                            for (int i = 0; i < d; ++i) row[i] = S.v[i][r.owner];
+                            for (int i = 0; i < d; ++i) row[i] = S.v[(i) * kWave + (r.owner)];
                             row[d] = r.v;
                             if (a.measure_next) my_bound += next_level_bound(S, a, d, r);
                         }
@@ -703,7 +721,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
                         const unsigned long long slot = b0 + popc_below(m);
                         if (ok && slot < a.out_cap) {
                             int32_t *row = a.out + slot * static_cast<unsigned long long>(d + 1);
-                            for (int i = 0; i < d; ++i) row[i] = S.v[i][r.owner];
+                            for (int i = 0; i < d; ++i) row[i] = S.v[(i) * kWave + (r.owner)];
                             row[d] = r.v;
                         }
                         if (ok && a.measure_next) my_bound += next_level_bound(S, a, d, r);
@@ -718,7 +736,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
                         row[a.plan.phi[l]] = r.v;
                         uint32_t q = r.owner;
                         for (int i = l - 1; i >= 0; --i) {
-                            row[a.plan.phi[i]] = S.v[i][q];
+                            row[a.plan.phi[i]] = S.v[(i) * kWave + (q)];
                             q = ent_pid(S, i, q);
                         }
                     }
@@ -826,32 +844,30 @@ __global__ __launch_bounds__(256) void root_scan_kernel(const VInfo *__restrict_
     }
 }
 
-template <int K, int MODE>
-hipError_t launch_persistent(const SearchArgs &a, int num_cu, int waves_per_cu, hipStream_t s, int *grid_waves) {
-    auto kern = search_kernel<K, MODE>;
+template <int MODE>
+int blocks_per_cu(int levels, int waves_per_cu) {
+    const size_t lds_bytes = wave_lds_bytes(levels, MODE == kExpand) * kWavesPerBlock;
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0);
-    if (e != hipSuccess) return e;
-    if (per_cu < 1) per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel<MODE>, kBlock, lds_bytes) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
     if (waves_per_cu > 0) {
-        int want = (waves_per_cu + kWavesPerBlock - 1) / kWavesPerBlock;
+        const int want = (waves_per_cu + kWavesPerBlock - 1) / kWavesPerBlock;
         if (want < per_cu) per_cu = want;
     }
-    int blocks = num_cu * per_cu;
-    if (a.mail && blocks * kWavesPerBlock > a.steal_slots) blocks = a.steal_slots / kWavesPerBlock;  // one mailbox each
-    if (blocks < 1) blocks = 1;
-    if (grid_waves) *grid_waves = blocks * kWavesPerBlock;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
+    return per_cu;
 }
 
 template <int MODE>
-hipError_t launch_levels(int levels, const SearchArgs &a, int num_cu, int waves_per_cu, hipStream_t s,
-                         int *grid_waves) {
-    if (levels <= 8) return launch_persistent<8, MODE>(a, num_cu, waves_per_cu, s, grid_waves);
-    if (levels <= 16) return launch_persistent<16, MODE>(a, num_cu, waves_per_cu, s, grid_waves);
-    if (levels <= kMaxK) return launch_persistent<32, MODE>(a, num_cu, waves_per_cu, s, grid_waves);
-    return hipErrorInvalidValue;
+hipError_t launch_persistent(const SearchArgs &a, int num_cu, int waves_per_cu, hipStream_t s, int *grid_waves) {
+    if (a.plan.k < 1 || a.plan.k > kMaxK) return hipErrorInvalidValue;
+    const size_t lds_bytes = wave_lds_bytes(a.plan.k, MODE == kExpand) * kWavesPerBlock;
+    int blocks = num_cu * blocks_per_cu<MODE>(a.plan.k, waves_per_cu);
+    if (a.mail && blocks * kWavesPerBlock > a.steal_slots) blocks = a.steal_slots / kWavesPerBlock;  // one mailbox each
+    if (blocks < 1) blocks = 1;
+    if (grid_waves) *grid_waves = blocks * kWavesPerBlock;
+    hipLaunchKernelGGL(search_kernel<MODE>, dim3(blocks), dim3(kBlock), lds_bytes, s, a);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -868,29 +884,17 @@ hipError_t launch_root_scan(const VInfo *vinfo, int32_t n, int32_t lab0, int32_t
 }
 
 hipError_t launch_expand(const SearchArgs &a, int num_cu, hipStream_t s) {
-    return launch_levels<kExpand>(a.plan.depth + 1, a, num_cu, 0, s, nullptr);
+    return launch_persistent<kExpand>(a, num_cu, 0, s, nullptr);
 }
 
 int search_waves(int levels, int num_cu, int waves_per_cu) {
-    auto occ = [&](auto kern) {
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0) != hipSuccess || per_cu < 1)
-            per_cu = 1;
-        if (waves_per_cu > 0) {
-            const int want = (waves_per_cu + kWavesPerBlock - 1) / kWavesPerBlock;
-            if (want < per_cu) per_cu = want;
-        }
-        return num_cu * per_cu * kWavesPerBlock;
-    };
-    if (levels <= 8) return occ(search_kernel<8, kCount>);
-    if (levels <= 16) return occ(search_kernel<16, kCount>);
-    return occ(search_kernel<32, kCount>);
+    return num_cu * blocks_per_cu<kCount>(levels, waves_per_cu) * kWavesPerBlock;
 }
 
 hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int waves_per_cu, hipStream_t s,
                          int *grid_waves_out) {
-    if (enumerate) return launch_levels<kEnumerate>(a.plan.k, a, num_cu, waves_per_cu, s, grid_waves_out);
-    return launch_levels<kCount>(a.plan.k, a, num_cu, waves_per_cu, s, grid_waves_out);
+    if (enumerate) return launch_persistent<kEnumerate>(a, num_cu, waves_per_cu, s, grid_waves_out);
+    return launch_persistent<kCount>(a, num_cu, waves_per_cu, s, grid_waves_out);
 }
 
 hipError_t launch_steal_init(Mailbox *mail, unsigned long long *idle_bits, int32_t n, hipStream_t s) {
