@@ -179,6 +179,7 @@ def main() -> int:
     ap.add_argument("--tau", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--disable-stealing", action="store_true")
+    ap.add_argument("--stack-layout", type=int, default=0, help="0 auto, 1 full, 2 slim")
     ap.add_argument("--steal-threshold", type=int, default=0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB device-to-device (counter calibration)")
@@ -226,7 +227,8 @@ def main() -> int:
     log(f"workload {w.name}: n={w.graph.n} |E|={w.graph.num_edges} queries={len(w.queries)} "
         f"({time.time() - t:.1f} s to generate)")
     e = gm.Engine(device=0, tau=args.tau, waves_per_cu=args.waves_per_cu,
-                  disable_stealing=args.disable_stealing, steal_threshold=args.steal_threshold)
+                  disable_stealing=args.disable_stealing, steal_threshold=args.steal_threshold,
+                  stack_layout=args.stack_layout)
     e.load(w.graph)
     qids = [e.add(q) for q in w.queries]
     phis = [e.get_order(qid) for qid in qids]

@@ -69,9 +69,11 @@ typedef struct {
     int32_t waves_per_cu;
     /* 1 = skip the symmetry check of gm_load_graph (trusted input). */
     int32_t skip_symmetry_check;
-    /* Below this neighbour-list length a membership test scans the list with
-     * independent loads instead of bisecting it; 0 = default 8, max 16. */
-    int32_t linear_probe_len;
+    /* Per-wavefront stack layout in LDS: 1 = full (20 B per level and lane;
+     * entries cache their neighbour-list range), 2 = slim (13 B; membership
+     * tests bisect label slices, whose bounds cost one load), 0 = default
+     * (slim: it keeps more wavefronts per CU and bisects shorter ranges). */
+    int32_t stack_layout;
     /* 1 = do not build label-partitioned neighbour lists (every task group then
      * scans its whole list and the label filter rejects the rest). */
     int32_t disable_label_index;

@@ -39,7 +39,7 @@ class Options(ctypes.Structure):
         ("steal_threshold", ctypes.c_int32),
         ("waves_per_cu", ctypes.c_int32),
         ("skip_symmetry_check", ctypes.c_int32),
-        ("linear_probe_len", ctypes.c_int32),
+        ("stack_layout", ctypes.c_int32),
         ("disable_label_index", ctypes.c_int32),
         ("reserved", ctypes.c_int32 * 6),
     ]
@@ -140,7 +140,7 @@ class Engine:
 
     def __init__(self, device: int = 0, tau: int = 0, pool_row_limit: int = 0, disable_stealing: bool = False,
                  steal_threshold: int = 0, waves_per_cu: int = 0, skip_symmetry_check: bool = False,
-                 linear_probe_len: int = 0, disable_label_index: bool = False):
+                 stack_layout: int = 0, disable_label_index: bool = False):
         self._lib = load_library()
         opt = Options()
         opt.tau = tau
@@ -149,7 +149,7 @@ class Engine:
         opt.steal_threshold = steal_threshold
         opt.waves_per_cu = waves_per_cu
         opt.skip_symmetry_check = int(skip_symmetry_check)
-        opt.linear_probe_len = linear_probe_len
+        opt.stack_layout = stack_layout
         opt.disable_label_index = int(disable_label_index)
         h = ctypes.c_void_p()
         st = self._lib.gm_create(device, ctypes.byref(opt), ctypes.byref(h))

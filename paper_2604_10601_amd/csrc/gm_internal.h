@@ -94,7 +94,7 @@ struct SearchArgs {
     unsigned long long *idle_bits; // bit w set: wavefront w waits for work
     int32_t steal_slots;       // number of mailboxes (>= wavefronts launched)
     int32_t steal_threshold;
-    int32_t linear_probe;      // unused
+    int32_t slim;              // 1: slim stack layout (membership tests on label slices)
     int32_t measure_next;      // expansion: add the next level's size bound to ctl->measure
     Plan plan;
 };
@@ -109,7 +109,7 @@ hipError_t launch_expand(const SearchArgs &a, int num_cu, hipStream_t s);
 hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int waves_per_cu, hipStream_t s,
                          int *grid_waves_out);
 // Wavefronts a depth-first search launch for a query of `levels` positions keeps resident.
-int search_waves(int levels, int num_cu, int waves_per_cu);
+int search_waves(int levels, int num_cu, int waves_per_cu, bool slim);
 hipError_t launch_steal_init(Mailbox *mail, unsigned long long *idle_bits, int32_t n, hipStream_t s);
 
 }  // namespace gm

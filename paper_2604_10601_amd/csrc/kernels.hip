@@ -137,14 +137,20 @@ __device__ __forceinline__ bool in_all_lists(const int32_t *__restrict__ col, ui
     return all;
 }
 
-// Per-wavefront stack in LDS (Sec. 5.1: S is |V(Q)| x warp width): 20 bytes per
-// (level, lane) plus 16 bytes per level, for exactly k levels (the launch sizes
-// the dynamic LDS from the query), so small queries leave room for more
-// wavefronts per CU.  Element (level i, lane q) of an array is at [i * 64 + q].
+// Per-wavefront stack in LDS (Sec. 5.1: S is |V(Q)| x warp width) for exactly k
+// levels (the launch sizes the dynamic LDS from the query).  Element (level i,
+// lane q) of a plane is at [i * 64 + q].  Two layouts:
+//   full (20 B per (level, lane)): the entry caches its vertex's id-sorted list
+//     start and degree, so membership tests bisect N(w) with no extra load;
+//   slim (13 B): the entry keeps only its vertex and parent lane; membership
+//     tests bisect the label slice of N(w) in lcol (ids ascending within a
+//     label), whose bounds cost one 8-byte load per list but which is shorter
+//     than N(w).  Deep queries fit about twice as many wavefronts per CU.
 struct WaveStack {
     int32_t *v;       // data vertex of the task at (level, lane)
-    uint32_t *st;     // start of N(v) in col[] (ids ascending)
-    uint32_t *dp;     // |N(v)| << 8 | lane of the parent entry at level - 1
+    uint32_t *st;     // full: start of N(v) in col[] (ids ascending)
+    uint32_t *dp;     // full: |N(v)| << 8 | lane of the parent entry at level - 1
+    uint8_t *pid;     // slim: lane of the parent entry at level - 1
     uint32_t *cs;     // parent lane's local candidate slice: start in lcol[]
     uint32_t *cl;     //   ... length << 8 | level of its source list (0xff = no list)
     uint32_t *cur_j;  // per level: scatter cursor, offset in the current parent's slice
@@ -154,19 +160,31 @@ struct WaveStack {
     uint8_t *own;     // scatter scratch: parent starting at each slot
 };
 
-__host__ __device__ constexpr size_t stack_bytes(int levels) {
-    return static_cast<size_t>(levels) * (kWave * 20u + 16u) + kWave;
+__host__ __device__ constexpr size_t stack_bytes(int levels, bool slim) {
+    return static_cast<size_t>(levels) * (kWave * (slim ? 13u : 20u) + 16u) + kWave;
 }
 
+template <bool SLIM>
 __device__ __forceinline__ WaveStack carve_stack(uint8_t *base, int levels) {
     WaveStack S;
     const size_t plane = static_cast<size_t>(levels) * kWave * 4u;
-    S.v = reinterpret_cast<int32_t *>(base);
-    S.st = reinterpret_cast<uint32_t *>(base + plane);
-    S.dp = reinterpret_cast<uint32_t *>(base + 2 * plane);
-    S.cs = reinterpret_cast<uint32_t *>(base + 3 * plane);
-    S.cl = reinterpret_cast<uint32_t *>(base + 4 * plane);
-    uint32_t *lv = reinterpret_cast<uint32_t *>(base + 5 * plane);
+    uint8_t *p = base;
+    S.v = reinterpret_cast<int32_t *>(p);
+    p += plane;
+    if (SLIM) {
+        S.st = nullptr;
+        S.dp = nullptr;
+        S.pid = p;
+        p += static_cast<size_t>(levels) * kWave;
+    } else {
+        S.st = reinterpret_cast<uint32_t *>(p);
+        S.dp = reinterpret_cast<uint32_t *>(p + plane);
+        S.pid = nullptr;
+        p += 2 * plane;
+    }
+    S.cs = reinterpret_cast<uint32_t *>(p);
+    S.cl = reinterpret_cast<uint32_t *>(p + plane);
+    uint32_t *lv = reinterpret_cast<uint32_t *>(p + 2 * plane);
     S.cur_j = lv;
     S.cur_i = lv + levels;
     S.end_j = lv + 2 * levels;
@@ -175,13 +193,23 @@ __device__ __forceinline__ WaveStack carve_stack(uint8_t *base, int levels) {
     return S;
 }
 
-__device__ __forceinline__ uint32_t ent_deg(const WaveStack &S, int i, uint32_t q) { return S.dp[(i) * kWave + (q)] >> 8; }
-__device__ __forceinline__ uint32_t ent_pid(const WaveStack &S, int i, uint32_t q) { return S.dp[(i) * kWave + (q)] & 0xffu; }
+__device__ __forceinline__ uint32_t ent_deg(const WaveStack &S, int i, uint32_t q) { return S.dp[i * kWave + q] >> 8; }
 
+template <bool SLIM>
+__device__ __forceinline__ uint32_t ent_pid(const WaveStack &S, int i, uint32_t q) {
+    if (SLIM) return S.pid[i * kWave + q];
+    return S.dp[i * kWave + q] & 0xffu;
+}
+
+template <bool SLIM>
 __device__ __forceinline__ void push_entry(WaveStack &S, int i, uint32_t lane, int32_t v, VInfo vi, uint32_t pid) {
-    S.v[(i) * kWave + (lane)] = v;
-    S.st[(i) * kWave + (lane)] = vi.x;
-    S.dp[(i) * kWave + (lane)] = (vi_deg(vi) << 8) | pid;
+    S.v[i * kWave + lane] = v;
+    if (SLIM) {
+        S.pid[i * kWave + lane] = static_cast<uint8_t>(pid);
+    } else {
+        S.st[i * kWave + lane] = vi.x;
+        S.dp[i * kWave + lane] = (vi_deg(vi) << 8) | pid;
+    }
 }
 
 struct Gen {
@@ -197,6 +225,7 @@ struct Gen {
 // lists only the slice of candidates labelled L(phi[l]) can pass the label
 // check, so the smallest such slice is scanned instead (earliest position on
 // ties); it yields exactly the same valid extensions.
+template <bool SLIM>
 __device__ __forceinline__ Gen generate_tasks(WaveStack &S, const SearchArgs &a, int l, uint64_t F,
                                               uint32_t lane) {
     Gen g{0u, 0u, 0u};
@@ -204,39 +233,49 @@ __device__ __forceinline__ Gen generate_tasks(WaveStack &S, const SearchArgs &a,
     if ((F >> lane) & 1ull) {
         const uint32_t bw = a.plan.bwd[l];
         const int lowest = __builtin_ctz(bw);
-        const bool sliced = a.loff_stride > 1;
+        const int stride = a.loff_stride;
+        const bool sliced = stride > 1;
         const uint32_t lab = sliced ? static_cast<uint32_t>(a.plan.lab[l]) : 0u;
         uint32_t q = lane;
         uint32_t best_full = 0xffffffffu, best_n = 0xffffffffu, best_a = 0, best_j = 0;
         for (int i = l - 1; i >= lowest; --i) {
             if ((bw >> i) & 1u) {
-                const uint32_t d = ent_deg(S, i, q);
-                best_full = d < best_full ? d : best_full;
-                uint32_t sa, sn;
-                if (sliced) {
-                    const uint32_t *o = a.loff + static_cast<unsigned long long>(S.v[(i) * kWave + (q)]) * a.loff_stride + lab;
-                    sa = o[0];
-                    sn = o[1] - sa;
+                uint32_t d, sa, sn;
+                if (SLIM) {
+                    const uint32_t *o = a.loff + static_cast<unsigned long long>(S.v[i * kWave + q]) * stride;
+                    const uint32_t row0 = o[0];
+                    d = o[stride - 1 + (sliced ? 0 : 1)] - row0;  // whole list: first to last bound
+                    sa = o[lab];
+                    sn = o[lab + 1] - sa;
                     ++g.lookups;
                 } else {
-                    sa = S.st[(i) * kWave + (q)];
-                    sn = d;
+                    d = ent_deg(S, i, q);
+                    if (sliced) {
+                        const uint32_t *o = a.loff + static_cast<unsigned long long>(S.v[i * kWave + q]) * stride + lab;
+                        sa = o[0];
+                        sn = o[1] - sa;
+                        ++g.lookups;
+                    } else {
+                        sa = S.st[i * kWave + q];
+                        sn = d;
+                    }
                 }
+                best_full = d < best_full ? d : best_full;
                 if (sn <= best_n) {
                     best_n = sn;
                     best_a = sa;
                     best_j = static_cast<uint32_t>(i);
                 }
             }
-            q = ent_pid(S, i, q);
+            q = ent_pid<SLIM>(S, i, q);
         }
         g.tasks = best_full;
         g.scanned = best_n;
         cs = best_a;
         cl = (best_n << 8) | best_j;
     }
-    S.cs[(l) * kWave + (lane)] = cs;
-    S.cl[(l) * kWave + (lane)] = cl;
+    S.cs[l * kWave + lane] = cs;
+    S.cl[l * kWave + lane] = cl;
     return g;
 }
 
@@ -331,41 +370,75 @@ __device__ __forceinline__ Round scatter(WaveStack &S, const int32_t *__restrict
     return r;
 }
 
+// Test the collected lists (lo[t], n[t]); n[t] == 0 marks an unused slot.  In
+// the slim layout lo[t] holds the list's vertex w and n[t] = 1 until the bounds
+// of w's slice with the candidate's label are read here, for all slots at once;
+// an empty slice means v is not a neighbour of w.
+template <bool SLIM>
+__device__ __forceinline__ bool test_lists(const SearchArgs &a, uint32_t lab, uint32_t (&lo)[kLists],
+                                           uint32_t (&n)[kLists], int32_t v, uint32_t &probes, uint32_t &lookups) {
+    if (SLIM) {
+        uint32_t b0[kLists], b1[kLists];
+#pragma unroll
+        for (int t = 0; t < kLists; ++t) {
+            const bool use = n[t] != 0u;
+            const uint32_t *o = a.loff + static_cast<unsigned long long>(use ? lo[t] : 0u) * a.loff_stride + lab;
+            b0[t] = use ? o[0] : 0u;
+            b1[t] = use ? o[1] : 0u;
+            lookups += use ? 1u : 0u;
+        }
+        bool empty = false;
+#pragma unroll
+        for (int t = 0; t < kLists; ++t) {
+            if (n[t] != 0u) {
+                empty |= b1[t] == b0[t];
+                lo[t] = b0[t];
+                n[t] = b1[t] - b0[t];
+            }
+        }
+        if (empty) return false;
+        return in_all_lists(a.lcol, lo, n, v, probes);
+    }
+    return in_all_lists(a.col, lo, n, v, probes);
+}
+
 // Process (Alg. 2): label and degree filters, then one walk down the parent
 // chain checking injectivity and membership in every backward neighbour's list
-// other than the one the candidate came from.
+// other than the one the candidate came from.  The lists are collected during
+// the walk (kLists at a time, the slot index being the same in every lane) and
+// tested together.
+template <bool SLIM>
 __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, int l, const Round &r, uint32_t lane,
-                                        VInfo &vi, uint32_t &probes) {
+                                        VInfo &vi, uint32_t &probes, uint32_t &lookups) {
     bool ok = lane < r.ntask;
     vi = make_uint2(0u, 0u);
     if (ok) vi = a.vinfo[r.v];
     ok = ok && vi_lab(vi) == static_cast<uint32_t>(a.plan.lab[l]) &&
          vi_deg(vi) >= static_cast<uint32_t>(a.plan.qdeg[l]);
     if (ok) {
-        // One walk down the chain: injectivity at every level; the neighbour
-        // lists of the other backward neighbours are collected (kLists at a
-        // time, the slot index being the same in every lane) and tested together.
         const uint32_t bw = a.plan.bwd[l];
-        const uint32_t js = S.cl[(l) * kWave + (r.owner)] & 0xffu;
+        const uint32_t js = S.cl[l * kWave + r.owner] & 0xffu;
+        const uint32_t lab = a.loff_stride > 1 ? static_cast<uint32_t>(a.plan.lab[l]) : 0u;
         uint32_t lo[kLists] = {0u, 0u, 0u, 0u};
         uint32_t n[kLists] = {0u, 0u, 0u, 0u};
         int used = 0;
         uint32_t q = r.owner;
         for (int i = l - 1; i >= 0; --i) {
-            const int32_t w = S.v[(i) * kWave + (q)];
+            const int32_t w = S.v[i * kWave + q];
             if (w == r.v) {
                 ok = false;
                 break;
             }
             if ((bw >> i) & 1u) {
-                const uint32_t st = S.st[(i) * kWave + (q)];
-                const uint32_t len = static_cast<uint32_t>(i) == js ? 0u : ent_deg(S, i, q);
+                const bool skip = static_cast<uint32_t>(i) == js;
+                const uint32_t st = SLIM ? static_cast<uint32_t>(w) : S.st[i * kWave + q];
+                const uint32_t len = skip ? 0u : (SLIM ? 1u : ent_deg(S, i, q));
                 if (used == 0) { lo[0] = st; n[0] = len; }
                 else if (used == 1) { lo[1] = st; n[1] = len; }
                 else if (used == 2) { lo[2] = st; n[2] = len; }
                 else { lo[3] = st; n[3] = len; }
                 if (++used == kLists) {
-                    if (!in_all_lists(a.col, lo, n, r.v, probes)) {
+                    if (!test_lists<SLIM>(a, lab, lo, n, r.v, probes, lookups)) {
                         ok = false;
                         break;
                     }
@@ -373,9 +446,9 @@ __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, int l
                     n[0] = n[1] = n[2] = n[3] = 0u;
                 }
             }
-            q = ent_pid(S, i, q);
+            q = ent_pid<SLIM>(S, i, q);
         }
-        if (ok && used > 0) ok = in_all_lists(a.col, lo, n, r.v, probes);
+        if (ok && used > 0) ok = test_lists<SLIM>(a, lab, lo, n, r.v, probes, lookups);
     }
     return ok;
 }
@@ -475,6 +548,7 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 // shallowest non-leaf level holding at least `threshold` of them ("split the
 // stack in half").  The donor keeps the lower half by moving that level's end.
 // Returns true if work was handed over.
+template <bool SLIM>
 __device__ bool donate(WaveStack &S, const SearchArgs &a, int base, int l, uint32_t lane) {
     const int k = a.plan.k;
     const int top = l < k - 2 ? l : k - 2;
@@ -507,7 +581,7 @@ __device__ bool donate(WaveStack &S, const SearchArgs &a, int base, int l, uint3
             uint32_t q = lane;
             for (int i = L - 1; i >= 0; --i) {
                 store_agent(&mb.rows[lane * kMaxK + i], S.v[(i) * kWave + (q)]);
-                q = ent_pid(S, i, q);
+                q = ent_pid<SLIM>(S, i, q);
             }
         }
         if (lane == 0) {
@@ -573,16 +647,16 @@ __device__ __forceinline__ void flush_stage(int32_t *stage, uint32_t &staged, in
 
 // LDS of one wavefront for a query of `levels` positions (stack, plus the output
 // staging buffer of an expansion).
-__host__ __device__ constexpr size_t wave_lds_bytes(int levels, bool expand) {
-    return stack_bytes(levels) + (expand ? static_cast<size_t>(kStageRows) * kStageWidth * 4u : 0u);
+__host__ __device__ constexpr size_t wave_lds_bytes(int levels, bool expand, bool slim) {
+    return stack_bytes(levels, slim) + (expand ? static_cast<size_t>(kStageRows) * kStageWidth * 4u : 0u);
 }
 
-template <int MODE>
+template <int MODE, bool SLIM>
 __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    uint8_t *mine = lds + (threadIdx.x / kWave) * wave_lds_bytes(a.plan.k, MODE == kExpand);
-    WaveStack S = carve_stack(mine, a.plan.k);
-    int32_t *stage = reinterpret_cast<int32_t *>(mine + stack_bytes(a.plan.k));
+    uint8_t *mine = lds + (threadIdx.x / kWave) * wave_lds_bytes(a.plan.k, MODE == kExpand, SLIM);
+    WaveStack S = carve_stack<SLIM>(mine, a.plan.k);
+    int32_t *stage = reinterpret_cast<int32_t *>(mine + stack_bytes(a.plan.k, SLIM));
     uint32_t staged = 0;
     const uint32_t lane = lane_id();
     const int k = a.plan.k;
@@ -592,7 +666,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
     const uint32_t wave_id = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
 
     uint64_t my_tasks = 0, my_scanned = 0, my_lookups = 0, my_bound = 0;
-    uint32_t my_probes = 0;
+    uint32_t my_probes = 0, my_plookups = 0;
     uint64_t my_probes_total = 0;
     uint64_t w_groups = 0, w_active = 0, w_issued = 0, w_count = 0, w_steals = 0;
     uint32_t rounds = 0;
@@ -617,10 +691,10 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
                         v = a.pool[(r0 + lane) * static_cast<unsigned long long>(d) + i];
                         vi = a.vinfo[v];
                     }
-                    push_entry(S, i, lane, v, vi, lane);
+                    push_entry<SLIM>(S, i, lane, v, vi, lane);
                 }
                 const uint64_t F0 = ballot(mine);
-                const Gen g = generate_tasks(S, a, d, F0, lane);
+                const Gen g = generate_tasks<SLIM>(S, a, d, F0, lane);
                 my_tasks += g.tasks;
                 my_scanned += g.scanned;
                 my_lookups += g.lookups;
@@ -678,9 +752,9 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
                     v = load_agent(&mb.rows[lane * kMaxK + i]);
                     vi = a.vinfo[v];
                 }
-                push_entry(S, i, lane, v, vi, lane);
+                push_entry<SLIM>(S, i, lane, v, vi, lane);
             }
-            generate_tasks(S, a, L, lanes, lane);  // already counted by the donor
+            generate_tasks<SLIM>(S, a, L, lanes, lane);  // already counted by the donor
             if (lane == 0) {
                 S.cur_i[L] = static_cast<uint32_t>(load_agent(&mb.pi));
                 S.cur_j[L] = static_cast<uint32_t>(load_agent(&mb.pj));
@@ -702,7 +776,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
             w_active += r.ntask;
             w_issued += kWave;
             VInfo vi;
-            const bool ok = process(S, a, l, r, lane, vi, my_probes);
+            const bool ok = process<SLIM>(S, a, l, r, lane, vi, my_probes, my_plookups);
             const uint64_t m = ballot(ok);
             if (MODE == kExpand) {
                 if (m) {
@@ -737,14 +811,14 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
                         uint32_t q = r.owner;
                         for (int i = l - 1; i >= 0; --i) {
                             row[a.plan.phi[i]] = S.v[(i) * kWave + (q)];
-                            q = ent_pid(S, i, q);
+                            q = ent_pid<SLIM>(S, i, q);
                         }
                     }
                 }
                 w_count += __popcll(m);
             } else if (m) {
-                push_entry(S, l, lane, r.v, vi, r.owner);
-                const Gen g = generate_tasks(S, a, l + 1, m, lane);
+                push_entry<SLIM>(S, l, lane, r.v, vi, r.owner);
+                const Gen g = generate_tasks<SLIM>(S, a, l + 1, m, lane);
                 my_tasks += g.tasks;
                 my_scanned += g.scanned;
                 my_lookups += g.lookups;
@@ -766,11 +840,13 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
                         int waiting = 0;
                         if (lane == 0) waiting = load_agent(&ctl->idle_count);
                         if (static_cast<int>(read_lane(static_cast<uint32_t>(waiting), 0)) > 0)
-                            donate(S, a, base, l, lane);
+                            donate<SLIM>(S, a, base, l, lane);
                     }
                 }
                 my_probes_total += my_probes;
                 my_probes = 0;
+                my_lookups += my_plookups;
+                my_plookups = 0;
                 if (stop) break;
             }
         }
@@ -783,6 +859,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
         }
     }
     my_probes_total += my_probes;
+    my_lookups += my_plookups;
     const uint64_t tasks = wave_sum64(my_tasks);
     const uint64_t scanned = wave_sum64(my_scanned);
     const uint64_t lookups = wave_sum64(my_lookups);
@@ -844,11 +921,12 @@ __global__ __launch_bounds__(256) void root_scan_kernel(const VInfo *__restrict_
     }
 }
 
-template <int MODE>
+template <int MODE, bool SLIM>
 int blocks_per_cu(int levels, int waves_per_cu) {
-    const size_t lds_bytes = wave_lds_bytes(levels, MODE == kExpand) * kWavesPerBlock;
+    const size_t lds_bytes = wave_lds_bytes(levels, MODE == kExpand, SLIM) * kWavesPerBlock;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel<MODE>, kBlock, lds_bytes) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel<MODE, SLIM>, kBlock, lds_bytes) !=
+            hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     if (waves_per_cu > 0) {
@@ -858,15 +936,15 @@ int blocks_per_cu(int levels, int waves_per_cu) {
     return per_cu;
 }
 
-template <int MODE>
+template <int MODE, bool SLIM>
 hipError_t launch_persistent(const SearchArgs &a, int num_cu, int waves_per_cu, hipStream_t s, int *grid_waves) {
     if (a.plan.k < 1 || a.plan.k > kMaxK) return hipErrorInvalidValue;
-    const size_t lds_bytes = wave_lds_bytes(a.plan.k, MODE == kExpand) * kWavesPerBlock;
-    int blocks = num_cu * blocks_per_cu<MODE>(a.plan.k, waves_per_cu);
+    const size_t lds_bytes = wave_lds_bytes(a.plan.k, MODE == kExpand, SLIM) * kWavesPerBlock;
+    int blocks = num_cu * blocks_per_cu<MODE, SLIM>(a.plan.k, waves_per_cu);
     if (a.mail && blocks * kWavesPerBlock > a.steal_slots) blocks = a.steal_slots / kWavesPerBlock;  // one mailbox each
     if (blocks < 1) blocks = 1;
     if (grid_waves) *grid_waves = blocks * kWavesPerBlock;
-    hipLaunchKernelGGL(search_kernel<MODE>, dim3(blocks), dim3(kBlock), lds_bytes, s, a);
+    hipLaunchKernelGGL((search_kernel<MODE, SLIM>), dim3(blocks), dim3(kBlock), lds_bytes, s, a);
     return hipGetLastError();
 }
 
@@ -884,17 +962,24 @@ hipError_t launch_root_scan(const VInfo *vinfo, int32_t n, int32_t lab0, int32_t
 }
 
 hipError_t launch_expand(const SearchArgs &a, int num_cu, hipStream_t s) {
-    return launch_persistent<kExpand>(a, num_cu, 0, s, nullptr);
+    if (a.slim) return launch_persistent<kExpand, true>(a, num_cu, 0, s, nullptr);
+    return launch_persistent<kExpand, false>(a, num_cu, 0, s, nullptr);
 }
 
-int search_waves(int levels, int num_cu, int waves_per_cu) {
-    return num_cu * blocks_per_cu<kCount>(levels, waves_per_cu) * kWavesPerBlock;
+int search_waves(int levels, int num_cu, int waves_per_cu, bool slim) {
+    const int per_cu = slim ? blocks_per_cu<kCount, true>(levels, waves_per_cu)
+                            : blocks_per_cu<kCount, false>(levels, waves_per_cu);
+    return num_cu * per_cu * kWavesPerBlock;
 }
 
 hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int waves_per_cu, hipStream_t s,
                          int *grid_waves_out) {
-    if (enumerate) return launch_persistent<kEnumerate>(a, num_cu, waves_per_cu, s, grid_waves_out);
-    return launch_persistent<kCount>(a, num_cu, waves_per_cu, s, grid_waves_out);
+    if (a.slim) {
+        if (enumerate) return launch_persistent<kEnumerate, true>(a, num_cu, waves_per_cu, s, grid_waves_out);
+        return launch_persistent<kCount, true>(a, num_cu, waves_per_cu, s, grid_waves_out);
+    }
+    if (enumerate) return launch_persistent<kEnumerate, false>(a, num_cu, waves_per_cu, s, grid_waves_out);
+    return launch_persistent<kCount, false>(a, num_cu, waves_per_cu, s, grid_waves_out);
 }
 
 hipError_t launch_steal_init(Mailbox *mail, unsigned long long *idle_bits, int32_t n, hipStream_t s) {

@@ -36,13 +36,13 @@ def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gmatch.h"\n'
                    'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(gm_options), sizeof(gm_result),'
-                   ' offsetof(gm_result, kernel_ms), offsetof(gm_options, linear_probe_len),'
+                   ' offsetof(gm_result, kernel_ms), offsetof(gm_options, stack_layout),'
                    ' offsetof(gm_result, rows));return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
     vals = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     assert vals == [ctypes.sizeof(gm.Options), ctypes.sizeof(gm._CResult), gm._CResult.kernel_ms.offset,
-                    gm.Options.linear_probe_len.offset, gm._CResult.rows.offset]
+                    gm.Options.stack_layout.offset, gm._CResult.rows.offset]
 
 
 @pytest.fixture()
@@ -126,7 +126,7 @@ def test_host_engine_refuses_to_search(host_engine):
 
 def test_bad_options():
     with pytest.raises(gm.GmError) as ei:
-        gm.Engine(device=-1, linear_probe_len=99)
+        gm.Engine(device=-1, stack_layout=7)
     assert ei.value.status == gm.GM_ERR_ARG
     with pytest.raises(gm.GmError) as ei:
         gm.Engine(device=-2)
