@@ -72,6 +72,8 @@ def make_workload(name: str, num_queries: int, stride: int = 1):
         w = wl.small_er()
     elif name == "large":
         w = wl.large_rmat24()
+    elif name == "batch":
+        w = wl.batch_rmat20()
     else:
         raise SystemExit(f"unknown workload {name}")
     w.queries = w.queries[::max(1, stride)]
@@ -127,9 +129,10 @@ def _csvs(root: str, suffix: str):
 def kernel_key(name: str) -> str:
     """Short name of a dispatched kernel: search kernels by mode, copies, others by function name."""
     import re
-    m = re.search(r"search_kernel<(\d+), (\d+)>", name)
+    m = re.search(r"search_kernel<(\d+), (true|false)>", name)
     if m:
-        return {"0": "search", "1": "enumerate", "2": "expand"}[m.group(2)] + f"<K={m.group(1)}>"
+        return {"0": "search", "1": "enumerate", "2": "expand"}[m.group(1)] + (
+            "<slim>" if m.group(2) == "true" else "<full>")
     if "copyBuffer" in name:
         return "copy"
     base = name[:-1].rsplit("(", 1)[0] if name.endswith(")") else name
@@ -170,7 +173,11 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="medium", choices=["medium", "small", "large"])
+    ap.add_argument("--workload", default="medium", choices=["medium", "small", "large", "batch"],
+                    help="batch = 10,000 mixed-size queries in shared launches (autotuned)")
+    ap.add_argument("--no-tune", action="store_true", help="batch workload: keep the default launch settings")
+    ap.add_argument("--alone-sample", type=int, default=10,
+                    help="batch workload: time every N-th query alone as the one-at-a-time reference")
     ap.add_argument("--queries", type=int, default=0, help="use only the first N queries (0 = all)")
     ap.add_argument("--query-stride", type=int, default=1, help="use every S-th query")
     ap.add_argument("--time-limit", type=float, default=-1.0, help="override the workload's per-query limit")
@@ -219,6 +226,9 @@ def main() -> int:
         return 2
 
     import paper_2604_10601_amd as gm
+
+    if args.workload == "batch":
+        return bench_batch(args, gm)
 
     t = time.time()
     w = make_workload(args.workload, args.queries, args.query_stride)
@@ -309,12 +319,106 @@ def main() -> int:
             "algorithmic_bytes_per_launch": b_alg / max(1, launches),
         },
     }
+    # the same queries in shared persistent launches (gm_count_batch), one call
+    e.count_batch(qids, cap=cap, time_limit_s=limit)
+    t0 = time.perf_counter()
+    bres, binfo = e.count_batch(qids, cap=cap, time_limit_s=limit)
+    bwall = time.perf_counter() - t0
+    out["batched"] = {"value": binfo.count / bwall, "unit": "embeddings/s", "ms": bwall * 1000.0,
+                      "kernel_ms": binfo.kernel_ms, "launches": binfo.launches,
+                      "same_counts": all((a.count, a.outcome) == (b.count, b.outcome)
+                                         for a, b in zip(steps[-1], bres))}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w, phis, args.cpu_seconds, cap, per_query_s=10.0)
     e.close()
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib << 20)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_batch(args, gm) -> int:
+    """Many uneven queries in shared persistent launches (gm_count_batch), after the
+    autotuner picked the launch settings on a sample; the reference is the same
+    engine counting a sample of the queries one at a time."""
+    t = time.time()
+    w = make_workload("batch", args.queries, args.query_stride)
+    if args.time_limit >= 0:
+        w.time_limit_s = args.time_limit
+    log(f"workload {w.name}: n={w.graph.n} |E|={w.graph.num_edges} queries={len(w.queries)} "
+        f"({time.time() - t:.1f} s to generate)")
+    e = gm.Engine(device=0, waves_per_cu=args.waves_per_cu, disable_stealing=args.disable_stealing,
+                  steal_threshold=args.steal_threshold, stack_layout=args.stack_layout)
+    e.load(w.graph)
+    qids = [e.add(q) for q in w.queries]
+    cap, limit = w.cap, w.time_limit_s
+    tuning = None
+    if not args.no_tune:
+        sample = qids[::20]
+        t = time.time()
+        tuning = e.tune_batch(sample, cap=cap, time_limit_s=limit).as_dict()
+        log(f"autotuner on {len(sample)} queries ({time.time() - t:.1f} s): {tuning}")
+    for i in range(args.warmup):
+        e.count_batch(qids, cap=cap, time_limit_s=limit)
+    infos, results = [], []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        res, info = e.count_batch(qids, cap=cap, time_limit_s=limit)
+        infos.append(info)
+        results.append(res)
+        log(f"step {i}: {info.count} embeddings in {info.total_ms:.1f} ms ({info.launches} launches)")
+    wall = time.perf_counter() - t0
+    last = results[-1]
+    # one query at a time on a sample, the plain reference
+    sample = list(range(0, len(qids), max(1, args.alone_sample)))
+    t0 = time.perf_counter()
+    alone = [e.count(qids[i], cap=cap, time_limit_s=limit) for i in sample]
+    alone_wall = time.perf_counter() - t0
+    same = all((a.count, a.outcome) == (last[i].count, last[i].outcome)
+               for i, a in zip(sample, alone) if a.outcome != gm.GM_TIMEOUT and last[i].outcome != gm.GM_TIMEOUT)
+    embeddings = sum(i.count for i in infos)
+    kernel_s = sum(i.kernel_ms for i in infos) / 1000.0
+    launches = sum(i.launches for i in infos)
+    b_alg = sum(algorithmic_bytes(r.pool_rows, 1, r.kernel_scanned, r.kernel_lookups, r.kernel_probes)
+                for res in results for r in res)
+    achieved = b_alg / kernel_s / 1e9 if kernel_s > 0 else 0.0
+    alone_lat = np.array([a.search_ms for a in alone])
+    out = {
+        "metric": "embeddings/s",
+        "value": embeddings / wall,
+        "unit": "embeddings/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1000.0 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "graph_vertices": w.graph.n, "graph_edges": w.graph.num_edges,
+                   "queries": len(w.queries), "query_sizes": [min(q.k for q in w.queries),
+                                                              max(q.k for q in w.queries)],
+                   "cap": cap, "time_limit_s": limit, "order": "RI heuristic", "launch": "gm_count_batch"},
+        "queries_per_s": len(qids) * args.steps / wall,
+        "outcomes_per_step": {"done": sum(r.outcome == gm.GM_DONE for r in last),
+                              "capped": sum(r.outcome == gm.GM_CAPPED for r in last),
+                              "timeout": sum(r.outcome == gm.GM_TIMEOUT for r in last)},
+        "tuning": tuning,
+        "one_at_a_time": {"sample": f"every {max(1, args.alone_sample)}-th query ({len(sample)} queries)",
+                          "queries_per_s": len(sample) / alone_wall,
+                          "embeddings_per_s": sum(a.count for a in alone) / alone_wall,
+                          "latency_ms": {"p50": float(np.percentile(alone_lat, 50)),
+                                         "p99": float(np.percentile(alone_lat, 99))},
+                          "same_counts_as_batched": same},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "search_kernel (persistent depth-first search, shared by the batch)",
+                     "launches": launches, "avg_launch_ms": kernel_s * 1000.0 / max(1, launches),
+                     "algorithmic_bytes_per_launch": b_alg / max(1, launches)},
+    }
+    e.close()
     print(json.dumps(out), flush=True)
     return 0
 

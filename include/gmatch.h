@@ -77,7 +77,15 @@ typedef struct {
     /* 1 = do not build label-partitioned neighbour lists (every task group then
      * scans its whole list and the label filter rejects the rest). */
     int32_t disable_label_index;
-    int32_t reserved[6];
+    /* gm_count_batch: 0 = one persistent launch per stack-depth class (queries
+     * whose stacks allow the same number of resident wavefronts share a launch),
+     * 1 = a single launch sized for the largest query of the batch. */
+    int32_t batch_single_launch;
+    /* gm_count_batch: work-item streams per launch, i.e. queries in flight at
+     * once.  Every wavefront serves its home stream's queries in order and
+     * helps the next stream once its own runs dry.  0 = default 64. */
+    int32_t batch_streams;
+    int32_t reserved[4];
 } gm_options;
 
 /* Result of one count or enumerate call. */
@@ -156,6 +164,67 @@ gm_status gm_count(gm_engine *engine, int32_t qid, uint64_t cap, double time_lim
  * gm_count's rules with this cap and out->rows equals min(count, cap). */
 gm_status gm_enumerate(gm_engine *engine, int32_t qid, int32_t *rows, uint64_t cap, double time_limit_s,
                        gm_result *out);
+
+/* Summary of one gm_count_batch call. */
+typedef struct {
+    double total_ms;     /* host wall time of the call */
+    double kernel_ms;    /* device time of its persistent search launches (HIP events), summed */
+    int32_t launches;    /* search launches made */
+    int32_t grid_waves;  /* wavefronts of the largest launch */
+    uint64_t count;      /* sums over the queries of the per-query fields */
+    uint64_t tasks;
+    uint64_t scanned;
+    uint64_t lookups;
+    uint64_t probes;
+    uint64_t groups;
+    uint64_t steals;
+    uint64_t reserved[4];
+} gm_batch_info;
+
+/* Count several queries in shared persistent launches (Alg. 2 for many
+ * queries at once; Sec. 4.3's persistent wavefronts and work stealing carry
+ * over unchanged).  qids[nq] may repeat a query.  Each query's first-vertex
+ * candidates (label and degree filter, Sec. 6.1) form its share of the pool,
+ * 64 per work item, with no breadth-first expansion; idle wavefronts take work
+ * from busy ones regardless of query, so a heavy query spreads over the GPU.
+ * out[i] follows gm_count's rules for qids[i] with the same cap and time
+ * limit: the same exact count when the search finishes, min(count, cap) with
+ * GM_CAPPED, or a lower bound with GM_TIMEOUT.  Each query's time limit runs
+ * from the moment its first work item is taken on the device, so waiting
+ * behind other queries of the batch does not count.  out[i].search_ms is the
+ * call's wall time, out[i].kernel_ms and grid_waves describe the launch that
+ * held the query, pool_depth is 1 and pool_rows its candidate count; the
+ * kernel_* counters equal the totals (there is no expansion launch).  info
+ * may be NULL.  nq = 0 is allowed and does nothing. */
+gm_status gm_count_batch(gm_engine *engine, int32_t nq, const int32_t *qids, uint64_t cap, double time_limit_s,
+                         gm_result *out, gm_batch_info *info);
+
+/* Settings chosen by gm_tune_batch. */
+typedef struct {
+    int32_t waves_per_cu;        /* resident wavefronts per CU (0 = as many as fit) */
+    int32_t steal_threshold;     /* smallest level a busy wavefront splits for an idle one */
+    int32_t stack_layout;        /* 1 = full, 2 = slim (LDS bytes per stack entry) */
+    int32_t batch_single_launch; /* as in gm_options */
+    int32_t batch_streams;       /* as in gm_options */
+    int32_t trials;              /* settings measured */
+    double best_ms;              /* device time of the chosen setting on the sample */
+    double default_ms;           /* device time of the engine's settings before tuning */
+} gm_tuning;
+
+/* Autotuner of the batched launch: runs gm_count_batch on the sample qids[nq]
+ * and tunes one setting at a time, each over a fixed list, keeping the best
+ * value before moving on: streams (queries in flight) over 1, 16, 64, 256;
+ * wavefronts per CU over as-many-as-fit, 12, 8; stack layout (LDS bytes per
+ * wavefront) slim, full; steal threshold 32, 128, 512; launch grouping.  The
+ * measure is the device time of the batch's launches.  The result stays in
+ * the engine's options and is reported in *out.  Every setting must give the
+ * same count for each query that finishes under both; a difference returns
+ * GM_ERR_STATE (an engine defect) and restores the options. */
+gm_status gm_tune_batch(gm_engine *engine, int32_t nq, const int32_t *qids, uint64_t cap, double time_limit_s,
+                        gm_tuning *out);
+
+/* Copy the engine's current options (after gm_tune_batch, its choices). */
+gm_status gm_get_options(const gm_engine *engine, gm_options *out);
 
 /* Forget a query; its id is not reused. */
 gm_status gm_free_query(gm_engine *engine, int32_t qid);

@@ -22,7 +22,8 @@ GM_ERR_NOMEM, GM_ERR_DEVICE, GM_ERR_BUFFER, GM_ERR_STATE = -5, -6, -7, -8
 GM_DONE, GM_CAPPED, GM_TIMEOUT = 0, 1, 2
 
 ABI_FUNCTIONS = ("gm_create", "gm_destroy", "gm_load_graph", "gm_load_query", "gm_set_order",
-                 "gm_get_order", "gm_count", "gm_enumerate", "gm_free_query", "gm_last_error")
+                 "gm_get_order", "gm_count", "gm_enumerate", "gm_count_batch", "gm_tune_batch",
+                 "gm_get_options", "gm_free_query", "gm_last_error")
 
 
 class GmError(RuntimeError):
@@ -41,8 +42,46 @@ class Options(ctypes.Structure):
         ("skip_symmetry_check", ctypes.c_int32),
         ("stack_layout", ctypes.c_int32),
         ("disable_label_index", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("batch_single_launch", ctypes.c_int32),
+        ("batch_streams", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [
+        ("total_ms", ctypes.c_double),
+        ("kernel_ms", ctypes.c_double),
+        ("launches", ctypes.c_int32),
+        ("grid_waves", ctypes.c_int32),
+        ("count", ctypes.c_uint64),
+        ("tasks", ctypes.c_uint64),
+        ("scanned", ctypes.c_uint64),
+        ("lookups", ctypes.c_uint64),
+        ("probes", ctypes.c_uint64),
+        ("groups", ctypes.c_uint64),
+        ("steals", ctypes.c_uint64),
+        ("reserved", ctypes.c_uint64 * 4),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("waves_per_cu", ctypes.c_int32),
+        ("steal_threshold", ctypes.c_int32),
+        ("stack_layout", ctypes.c_int32),
+        ("batch_single_launch", ctypes.c_int32),
+        ("batch_streams", ctypes.c_int32),
+        ("trials", ctypes.c_int32),
+        ("best_ms", ctypes.c_double),
+        ("default_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class _CResult(ctypes.Structure):
@@ -121,11 +160,14 @@ def load_library():
     lib.gm_get_order.argtypes = [p, i32, p]
     lib.gm_count.argtypes = [p, i32, u64, dbl, ctypes.POINTER(_CResult)]
     lib.gm_enumerate.argtypes = [p, i32, p, u64, dbl, ctypes.POINTER(_CResult)]
+    lib.gm_count_batch.argtypes = [p, i32, p, u64, dbl, p, ctypes.POINTER(BatchInfo)]
+    lib.gm_tune_batch.argtypes = [p, i32, p, u64, dbl, ctypes.POINTER(Tuning)]
+    lib.gm_get_options.argtypes = [p, ctypes.POINTER(Options)]
     lib.gm_free_query.argtypes = [p, i32]
     lib.gm_last_error.argtypes = [p]
     lib.gm_last_error.restype = ctypes.c_char_p
     for name in ("gm_create", "gm_load_graph", "gm_load_query", "gm_set_order", "gm_get_order", "gm_count",
-                 "gm_enumerate", "gm_free_query"):
+                 "gm_enumerate", "gm_count_batch", "gm_tune_batch", "gm_get_options", "gm_free_query"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -140,7 +182,8 @@ class Engine:
 
     def __init__(self, device: int = 0, tau: int = 0, pool_row_limit: int = 0, disable_stealing: bool = False,
                  steal_threshold: int = 0, waves_per_cu: int = 0, skip_symmetry_check: bool = False,
-                 stack_layout: int = 0, disable_label_index: bool = False):
+                 stack_layout: int = 0, disable_label_index: bool = False, batch_single_launch: bool = False,
+                 batch_streams: int = 0):
         self._lib = load_library()
         opt = Options()
         opt.tau = tau
@@ -151,6 +194,8 @@ class Engine:
         opt.skip_symmetry_check = int(skip_symmetry_check)
         opt.stack_layout = stack_layout
         opt.disable_label_index = int(disable_label_index)
+        opt.batch_single_launch = int(batch_single_launch)
+        opt.batch_streams = batch_streams
         h = ctypes.c_void_p()
         st = self._lib.gm_create(device, ctypes.byref(opt), ctypes.byref(h))
         if st != GM_OK:
@@ -222,6 +267,28 @@ class Engine:
         self._check(self._lib.gm_enumerate(self._h, qid, _ptr(rows), int(cap), float(time_limit_s),
                                            ctypes.byref(r)))
         return self._result(r, rows[: int(r.rows)])
+
+    def count_batch(self, qids: Sequence[int], cap: int = 0, time_limit_s: float = 0.0):
+        """Counts of several queries in shared launches: (list of Result, BatchInfo)."""
+        ids = np.ascontiguousarray(qids, dtype=np.int32)
+        res = (_CResult * max(len(ids), 1))()
+        info = BatchInfo()
+        self._check(self._lib.gm_count_batch(self._h, len(ids), _ptr(ids), int(cap), float(time_limit_s),
+                                             ctypes.cast(res, ctypes.c_void_p), ctypes.byref(info)))
+        return [self._result(res[i]) for i in range(len(ids))], info
+
+    def tune_batch(self, qids: Sequence[int], cap: int = 0, time_limit_s: float = 0.0) -> Tuning:
+        """Autotune the batched launch on a sample; the engine keeps the best setting."""
+        ids = np.ascontiguousarray(qids, dtype=np.int32)
+        t = Tuning()
+        self._check(self._lib.gm_tune_batch(self._h, len(ids), _ptr(ids), int(cap), float(time_limit_s),
+                                            ctypes.byref(t)))
+        return t
+
+    def options(self) -> Options:
+        o = Options()
+        self._check(self._lib.gm_get_options(self._h, ctypes.byref(o)))
+        return o
 
     def free_query(self, qid: int) -> None:
         self._check(self._lib.gm_free_query(self._h, qid))

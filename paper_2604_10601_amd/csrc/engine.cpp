@@ -121,6 +121,11 @@ struct gm_engine {
     uint32_t *d_loff = nullptr;    // label slice bounds
     int32_t loff_stride = 1;
     std::unordered_map<int32_t, int32_t> label_id;  // G's label value -> compact id
+    // vertices grouped by label, by degree descending within a label: the
+    // candidates of a first query vertex are a prefix of its label's bucket
+    int32_t *d_bylabel = nullptr;
+    std::vector<int64_t> lab_start;       // [labels + 1] bucket bounds
+    std::vector<uint32_t> bylabel_deg;    // degree of each bucket entry (host copy)
 
     std::vector<QueryRec> queries;
 
@@ -128,6 +133,15 @@ struct gm_engine {
     size_t pool_cap[2] = {0, 0};  // in int32
     int32_t *d_rows = nullptr;
     size_t rows_cap = 0;           // in int32
+    Plan *d_plans = nullptr;       // per-query plans of a launch
+    size_t plans_cap = 0;
+    gm::QCtl *d_qctl = nullptr;    // per-query results of a launch
+    size_t qctl_cap = 0;
+    std::vector<Plan> h_plans;     // host copies (kept until the uploads complete)
+    std::vector<gm::QCtl> h_qctl;
+    gm::StreamCtl *d_streams = nullptr;  // work-item streams of a launch
+    size_t streams_cap = 0;
+    std::vector<gm::StreamCtl> h_streams;
     Control *d_ctl = nullptr;
     gm::Mailbox *d_mail = nullptr;
     unsigned long long *d_idle_bits = nullptr;
@@ -179,11 +193,51 @@ gm_status ensure_buffer(gm_engine *e, int32_t **buf, size_t *cap, size_t need_in
     return GM_OK;
 }
 
+// Room for ns work-item streams on the device.
+gm_status ensure_streams(gm_engine *e, size_t ns) {
+    if (ns <= e->streams_cap && e->d_streams) return GM_OK;
+    if (e->d_streams) hipFree(e->d_streams);
+    e->d_streams = nullptr;
+    e->streams_cap = 0;
+    const size_t want = std::max<size_t>(ns, 64);
+    if (hipMalloc(reinterpret_cast<void **>(&e->d_streams), want * sizeof(gm::StreamCtl)) != hipSuccess) {
+        e->d_streams = nullptr;
+        return e->fail(GM_ERR_NOMEM, "device allocation of work streams failed");
+    }
+    e->streams_cap = want;
+    return GM_OK;
+}
+
+// Room for nq plans and per-query result blocks on the device.
+gm_status ensure_query_slots(gm_engine *e, size_t nq) {
+    if (nq <= e->plans_cap && e->d_plans && e->d_qctl) return GM_OK;
+    if (e->d_plans) hipFree(e->d_plans);
+    if (e->d_qctl) hipFree(e->d_qctl);
+    e->d_plans = nullptr;
+    e->d_qctl = nullptr;
+    e->plans_cap = 0;
+    const size_t want = std::max<size_t>(nq, 64);
+    hipError_t h = hipMalloc(reinterpret_cast<void **>(&e->d_plans), want * sizeof(Plan));
+    if (h == hipSuccess) h = hipMalloc(reinterpret_cast<void **>(&e->d_qctl), want * sizeof(gm::QCtl));
+    if (h != hipSuccess) {
+        if (e->d_plans) hipFree(e->d_plans);
+        e->d_plans = nullptr;
+        e->d_qctl = nullptr;
+        return e->fail(GM_ERR_NOMEM, "device allocation of query plans failed");
+    }
+    e->plans_cap = want;
+    return GM_OK;
+}
+
 void free_graph(gm_engine *e) {
     if (e->d_vinfo) hipFree(e->d_vinfo);
     if (e->d_lcol && e->d_lcol != e->d_col) hipFree(e->d_lcol);
     if (e->d_col) hipFree(e->d_col);
     if (e->d_loff) hipFree(e->d_loff);
+    if (e->d_bylabel) hipFree(e->d_bylabel);
+    e->d_bylabel = nullptr;
+    e->lab_start.clear();
+    e->bylabel_deg.clear();
     e->d_vinfo = nullptr;
     e->d_col = nullptr;
     e->d_lcol = nullptr;
@@ -273,6 +327,86 @@ gm_status reset_stealing(gm_engine *e, const SearchArgs &a) {
     return GM_OK;
 }
 
+// Plan of a query along its order (a0): labels as G's compact ids (255 when
+// absent from G, which leaves no candidates), query degrees and backward masks.
+Plan make_plan(const gm_engine *e, const QueryRec &q, bool *label_missing) {
+    Plan plan{};
+    plan.k = q.k;
+    plan.depth = 1;
+    plan.flush = ~0ull;
+    *label_missing = false;
+    for (int32_t i = 0; i < q.k; ++i) {
+        const int32_t u = q.order[i];
+        plan.phi[i] = u;
+        auto it = e->label_id.find(q.labels[u]);
+        plan.lab[i] = it == e->label_id.end() ? 255 : it->second;
+        *label_missing |= it == e->label_id.end();
+        plan.qdeg[i] = popcount(q.adj[u]);
+        uint32_t b = 0;
+        for (int32_t j = 0; j < i; ++j)
+            if ((q.adj[u] >> q.order[j]) & 1u) b |= 1u << j;
+        plan.bwd[i] = b;
+    }
+    return plan;
+}
+
+// Local matches a wavefront keeps before adding them to the query's count: small
+// enough that the cap is seen soon after it is reached.
+unsigned long long flush_for_cap(const gm_engine *e, uint64_t cap) {
+    if (!cap) return ~0ull;
+    const unsigned long long per = cap / (static_cast<unsigned long long>(e->num_cu) * 64ull);
+    return std::max<unsigned long long>(1, std::min<unsigned long long>(4096, per));
+}
+
+// Mailboxes and idle bitmap for work stealing (allocated on first use).
+gm_status attach_stealing(gm_engine *e, SearchArgs &a) {
+    a.mail = nullptr;
+    a.idle_bits = nullptr;
+    a.steal_slots = 0;
+    a.steal_threshold = e->opt.steal_threshold > 0 ? e->opt.steal_threshold : 128;
+    if (e->opt.disable_stealing) return GM_OK;
+    if (!e->d_mail) {
+        // one mailbox per wavefront that can be resident (at most 32 per CU)
+        const int32_t slots = e->num_cu * 32;
+        hipError_t h = hipMalloc(reinterpret_cast<void **>(&e->d_mail), sizeof(gm::Mailbox) * slots);
+        if (h == hipSuccess)
+            h = hipMalloc(reinterpret_cast<void **>(&e->d_idle_bits), sizeof(unsigned long long) * ((slots + 63) / 64));
+        if (h != hipSuccess) {
+            if (e->d_mail) hipFree(e->d_mail);
+            e->d_mail = nullptr;
+            e->d_idle_bits = nullptr;
+            return e->fail(GM_ERR_NOMEM, "work-stealing mailbox allocation failed");
+        }
+        e->steal_slots = slots;
+    }
+    a.mail = e->d_mail;
+    a.idle_bits = e->d_idle_bits;
+    a.steal_slots = e->steal_slots;
+    return GM_OK;
+}
+
+SearchArgs graph_args(const gm_engine *e) {
+    SearchArgs a{};
+    a.vinfo = e->d_vinfo;
+    a.col = e->d_col;
+    a.lcol = e->d_lcol;
+    a.loff = e->d_loff;
+    a.loff_stride = e->loff_stride;
+    a.ctl = e->d_ctl;
+    a.plans = e->d_plans;
+    a.qctl = e->d_qctl;
+    a.streams = e->d_streams;
+    return a;
+}
+
+unsigned long long items_of(unsigned long long rows) { return (rows + gm::kWave - 1) / gm::kWave; }
+
+// A query is finished when every work item of it was claimed (its stream's
+// counter passed them) and every unit of its work (item or donation) ran to its end.
+bool query_finished(const Plan &p, const gm::QCtl &qc, const gm::StreamCtl &sc) {
+    return qc.live == 0 && sc.next >= p.item_end;
+}
+
 // One search (Alg. 2): root candidates, breadth-first pool to tau, then the
 // persistent depth-first kernel.  rows != null selects enumeration.
 gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_s, int32_t *rows,
@@ -285,26 +419,16 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
     std::memset(out, 0, sizeof(*out));
     HIP_TRY(e, hipSetDevice(e->device));
 
-    Plan plan{};
-    plan.k = q->k;
     bool label_missing = false;
-    for (int32_t i = 0; i < q->k; ++i) {
-        const int32_t u = q->order[i];
-        plan.phi[i] = u;
-        auto it = e->label_id.find(q->labels[u]);
-        plan.lab[i] = it == e->label_id.end() ? 255 : it->second;
-        label_missing |= it == e->label_id.end();
-        plan.qdeg[i] = popcount(q->adj[u]);
-        uint32_t b = 0;
-        for (int32_t j = 0; j < i; ++j)
-            if ((q->adj[u] >> q->order[j]) & 1u) b |= 1u << j;
-        plan.bwd[i] = b;
-    }
+    const Plan base_plan = make_plan(e, *q, &label_missing);
     const bool enumerate = rows != nullptr;
     if (label_missing || e->n == 0) {
         out->outcome = GM_DONE;
         return GM_OK;
     }
+    st = ensure_query_slots(e, 1);
+    if (!st) st = ensure_streams(e, 1);
+    if (st) return st;
 
     const auto t_start = std::chrono::steady_clock::now();
     const long long budget_ticks =
@@ -316,11 +440,12 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
     };
 
     HIP_TRY(e, hipMemsetAsync(e->d_ctl, 0, sizeof(Control), e->stream));
+    HIP_TRY(e, hipMemsetAsync(e->d_qctl, 0, sizeof(gm::QCtl), e->stream));
     st = ensure_buffer(e, &e->d_pool[0], &e->pool_cap[0], static_cast<size_t>(e->n));
     if (st) return st;
     // the root scan also bounds the next level: each root's label slice for position 1
-    const int32_t lab1 = q->k >= 2 ? (e->loff_stride > 1 ? plan.lab[1] : 0) : -1;
-    HIP_TRY(e, gm::launch_root_scan(e->d_vinfo, e->n, plan.lab[0], plan.qdeg[0], e->d_pool[0], e->d_loff,
+    const int32_t lab1 = q->k >= 2 ? (e->loff_stride > 1 ? base_plan.lab[1] : 0) : -1;
+    HIP_TRY(e, gm::launch_root_scan(e->d_vinfo, e->n, base_plan.lab[0], base_plan.qdeg[0], e->d_pool[0], e->d_loff,
                                     e->loff_stride, lab1, e->d_ctl, e->num_cu, e->stream));
     Control c{};
     st = read_ctl(e, &c);
@@ -330,41 +455,14 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
     int cur = 0;
     int32_t depth = 1;
 
-    SearchArgs a{};
-    a.vinfo = e->d_vinfo;
-    a.col = e->d_col;
-    a.lcol = e->d_lcol;
-    a.loff = e->d_loff;
-    a.loff_stride = e->loff_stride;
-    a.ctl = e->d_ctl;
-    a.cap = cap;
-    a.flush = ~0ull;
+    SearchArgs a = graph_args(e);
+    a.nq = 1;
+    a.nstreams = 1;
+    a.levels = q->k;
     a.budget = static_cast<unsigned long long>(budget_ticks);
     a.slim = use_slim(e, q->k) ? 1 : 0;
-    a.mail = nullptr;
-    a.idle_bits = nullptr;
-    a.steal_slots = 0;
-    if (!e->opt.disable_stealing) {
-        if (!e->d_mail) {
-            // one mailbox per wavefront that can be resident (at most 32 per CU)
-            const int32_t slots = e->num_cu * 32;
-            hipError_t h = hipMalloc(reinterpret_cast<void **>(&e->d_mail), sizeof(gm::Mailbox) * slots);
-            if (h == hipSuccess)
-                h = hipMalloc(reinterpret_cast<void **>(&e->d_idle_bits), sizeof(unsigned long long) * ((slots + 63) / 64));
-            if (h != hipSuccess) {
-                if (e->d_mail) hipFree(e->d_mail);
-                e->d_mail = nullptr;
-                e->d_idle_bits = nullptr;
-                return e->fail(GM_ERR_NOMEM, "work-stealing mailbox allocation failed");
-            }
-            e->steal_slots = slots;
-        }
-        a.mail = e->d_mail;
-        a.idle_bits = e->d_idle_bits;
-        a.steal_slots = e->steal_slots;
-    }
-    a.steal_threshold = e->opt.steal_threshold > 0 ? e->opt.steal_threshold : 128;
-    a.plan = plan;
+    st = attach_stealing(e, a);
+    if (st) return st;
 
     if (q->k == 1) {
         // a single query vertex: its candidates are the matches
@@ -384,27 +482,54 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
         return GM_OK;
     }
 
+    // Plan 0 with the current pool level as its share (one query, items from 0).
+    auto upload_plan = [&](int32_t d, uint64_t nrows, unsigned long long flush) -> gm_status {
+        e->h_plans.assign(1, base_plan);
+        Plan &p = e->h_plans[0];
+        p.depth = d;
+        p.cap = cap;
+        p.flush = flush;
+        p.row0 = 0;
+        p.rows = nrows;
+        p.item0 = 0;
+        p.item_end = items_of(nrows);
+        e->h_streams.assign(1, gm::StreamCtl{});
+        e->h_streams[0].items = p.item_end;
+        e->h_streams[0].plan0 = 0;
+        e->h_streams[0].plan1 = 1;
+        HIP_TRY(e, hipMemcpyAsync(e->d_plans, &p, sizeof(Plan), hipMemcpyHostToDevice, e->stream));
+        HIP_TRY(e, hipMemcpyAsync(e->d_streams, e->h_streams.data(), sizeof(gm::StreamCtl), hipMemcpyHostToDevice,
+                                  e->stream));
+        HIP_TRY(e, hipMemsetAsync(&e->d_ctl->out_rows, 0, sizeof(unsigned long long), e->stream));
+        return GM_OK;
+    };
+    gm::QCtl qc{};
+    gm::StreamCtl sc{};
+    auto read_results = [&]() -> gm_status {
+        HIP_TRY(e, hipMemcpyAsync(&qc, e->d_qctl, sizeof(gm::QCtl), hipMemcpyDeviceToHost, e->stream));
+        HIP_TRY(e, hipMemcpyAsync(&sc, e->d_streams, sizeof(gm::StreamCtl), hipMemcpyDeviceToHost, e->stream));
+        return read_ctl(e, &c);
+    };
+
     // Initialisation phase (Sec. 4.3): breadth-first levels until >= tau rows.
     const int64_t tau = option_tau(e, q->k);
     const int64_t row_limit = e->opt.pool_row_limit > 0 ? e->opt.pool_row_limit : 64 * std::max<int64_t>(tau, 1);
     bool aborted = false;
     while (tau > 0 && pool_rows > 0 && pool_rows < static_cast<uint64_t>(tau) && depth < q->k - 1) {
-        a.plan.depth = depth;
-        a.pool = e->d_pool[cur];
-        a.pool_rows = pool_rows;
         if (bound > static_cast<uint64_t>(row_limit)) break;
         st = ensure_buffer(e, &e->d_pool[cur ^ 1], &e->pool_cap[cur ^ 1], bound * static_cast<size_t>(depth + 1));
         if (st) return st;
-        HIP_TRY(e, hipMemsetAsync(&e->d_ctl->pool_next, 0, sizeof(unsigned long long), e->stream));
-        HIP_TRY(e, hipMemsetAsync(&e->d_ctl->out_rows, 0, sizeof(unsigned long long), e->stream));
+        st = upload_plan(depth, pool_rows, ~0ull);
+        if (st) return st;
         HIP_TRY(e, hipMemsetAsync(&e->d_ctl->measure, 0, sizeof(unsigned long long), e->stream));
+        a.pool = e->d_pool[cur];
         a.out = e->d_pool[cur ^ 1];
         a.out_cap = bound;
         a.measure_next = depth + 1 < q->k - 1 ? 1 : 0;  // bound of the level after this one
         st = reset_stealing(e, a);
         if (st) return st;
         HIP_TRY(e, gm::launch_expand(a, e->num_cu, e->stream));
-        st = read_ctl(e, &c);
+        st = read_results();
         if (st) return st;
         if (c.abort != gm::kAbortNone || timed_out_host()) {
             aborted = true;
@@ -418,58 +543,54 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
 
     int grid_waves = 0;
     float kernel_ms = 0.f;
-    Control before = c;
+    gm::QCtl before = qc;
+    bool finished = !aborted;
     if (!aborted && pool_rows > 0) {
         if (enumerate) {
             st = ensure_buffer(e, &e->d_rows, &e->rows_cap, static_cast<size_t>(cap) * q->k);
             if (st) return st;
         }
-        a.plan.depth = depth;
+        st = upload_plan(depth, pool_rows, flush_for_cap(e, cap));
+        if (st) return st;
         a.pool = e->d_pool[cur];
-        a.pool_rows = pool_rows;
         a.out = enumerate ? e->d_rows : nullptr;
         a.out_cap = enumerate ? cap : 0;
-        if (cap) {
-            const unsigned long long per = cap / (static_cast<unsigned long long>(e->num_cu) * 64ull);
-            a.flush = std::max<unsigned long long>(1, std::min<unsigned long long>(4096, per));
-        }
-        HIP_TRY(e, hipMemsetAsync(&e->d_ctl->pool_next, 0, sizeof(unsigned long long), e->stream));
-        HIP_TRY(e, hipMemsetAsync(&e->d_ctl->out_rows, 0, sizeof(unsigned long long), e->stream));
+        a.measure_next = 0;
         st = reset_stealing(e, a);
         if (st) return st;
-        before = c;
         HIP_TRY(e, hipEventRecord(e->ev0, e->stream));
         HIP_TRY(e, gm::launch_search(a, enumerate, e->num_cu, e->opt.waves_per_cu, e->stream, &grid_waves));
         HIP_TRY(e, hipEventRecord(e->ev1, e->stream));
-        st = read_ctl(e, &c);
+        st = read_results();
         if (st) return st;
         HIP_TRY(e, hipEventElapsedTime(&kernel_ms, e->ev0, e->ev1));
+        finished = query_finished(e->h_plans[0], qc, sc);
     }
 
-    const uint64_t total = c.count;
+    const uint64_t total = qc.count;
     if (cap && total >= cap) {
         out->count = cap;
         out->outcome = GM_CAPPED;
     } else {
         out->count = total;
-        out->outcome = (aborted || c.abort == gm::kAbortTime) ? GM_TIMEOUT : GM_DONE;
+        out->outcome = finished ? GM_DONE : GM_TIMEOUT;
     }
     out->pool_rows = pool_rows;
     out->pool_depth = depth;
-    out->groups = c.groups;
-    out->tasks = c.tasks;
-    out->lanes_active = c.lanes_active;
-    out->lanes_issued = c.lanes_issued;
-    out->probes = c.probes;
-    out->steals = c.steals;
+    out->groups = qc.groups;
+    out->tasks = qc.tasks;
+    out->lanes_active = qc.lanes_active;
+    out->lanes_issued = qc.lanes_issued;
+    out->probes = qc.probes;
+    out->steals = qc.steals;
     out->kernel_ms = kernel_ms;
     out->grid_waves = grid_waves;
-    out->kernel_tasks = c.tasks - before.tasks;
-    out->kernel_probes = c.probes - before.probes;
-    out->kernel_groups = c.groups - before.groups;
-    out->scanned = c.scanned;
-    out->kernel_scanned = c.scanned - before.scanned;
-    out->kernel_lookups = c.lookups - before.lookups;
+    out->kernel_tasks = qc.tasks - before.tasks;
+    out->kernel_probes = qc.probes - before.probes;
+    out->kernel_groups = qc.groups - before.groups;
+    out->scanned = qc.scanned;
+    out->kernel_scanned = qc.scanned - before.scanned;
+    out->kernel_lookups = qc.lookups - before.lookups;
     if (enumerate) {
         const uint64_t nrows = std::min<uint64_t>(out->count, std::min<uint64_t>(c.out_rows, cap));
         if (nrows) {
@@ -481,6 +602,261 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
     }
     std::chrono::duration<double, std::milli> ms = std::chrono::steady_clock::now() - t_start;
     out->search_ms = ms.count();
+    return GM_OK;
+}
+
+// Wavefronts per CU a search launch for a query of k vertices keeps resident.
+int residency(const gm_engine *e, int32_t k) {
+    return gm::search_waves(k, e->num_cu, e->opt.waves_per_cu, use_slim(e, k));
+}
+
+// Work-item streams of a batched launch: the option, else 64 (queries in flight).
+int32_t batch_streams(const gm_engine *e) { return e->opt.batch_streams > 0 ? e->opt.batch_streams : 64; }
+
+// Several queries in shared persistent launches: every query's first-vertex
+// candidates (a prefix of its label's bucket, highest degree first) are its
+// pool share, and wavefronts move between queries as they claim work items or
+// take donations.  Queries are grouped by the residency their stack depth
+// allows (or all in one launch), each group one launch.
+gm_status run_batch(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t cap, double time_limit_s,
+                    gm_result *out, gm_batch_info *info) {
+    if (nq < 0) return e->fail(GM_ERR_ARG, "nq must be >= 0");
+    if (nq > 0 && (!qids || !out)) return e->fail(GM_ERR_ARG, "qids and out must not be null");
+    std::vector<const QueryRec *> recs(static_cast<size_t>(nq));
+    for (int32_t i = 0; i < nq; ++i) {
+        gm_status st = get_query(e, qids[i], &recs[i]);
+        if (st) return st;
+    }
+    gm_batch_info sum{};
+    if (nq == 0) {
+        if (info) *info = sum;
+        return GM_OK;
+    }
+    if (!e->has_graph) return e->fail(GM_ERR_STATE, "no data graph loaded");
+    if (e->device < 0) return e->fail(GM_ERR_DEVICE, "host-only engine (created with device -1) cannot search");
+    const auto t_start = std::chrono::steady_clock::now();
+    auto elapsed_s = [&]() {
+        std::chrono::duration<double> el = std::chrono::steady_clock::now() - t_start;
+        return el.count();
+    };
+    HIP_TRY(e, hipSetDevice(e->device));
+    std::memset(out, 0, sizeof(gm_result) * static_cast<size_t>(nq));
+
+    // each query's limit runs from its first work item on the device
+    unsigned long long budget_ticks = 0;
+    if (time_limit_s > 0)
+        budget_ticks = std::max<unsigned long long>(
+            1, static_cast<unsigned long long>(time_limit_s * 1000.0 * static_cast<double>(e->wall_khz)));
+    std::vector<Plan> plans(static_cast<size_t>(nq));
+    for (int32_t i = 0; i < nq; ++i) {
+        bool missing = false;
+        Plan p = make_plan(e, *recs[i], &missing);
+        p.cap = cap;
+        p.flush = flush_for_cap(e, cap);
+        p.depth = 1;
+        p.budget = budget_ticks;
+        if (!missing && e->n > 0) {
+            const int64_t b = e->lab_start[p.lab[0]], en = e->lab_start[p.lab[0] + 1];
+            const uint32_t need = static_cast<uint32_t>(p.qdeg[0]);
+            auto first = e->bylabel_deg.begin() + b;
+            auto it = std::partition_point(first, e->bylabel_deg.begin() + en, [need](uint32_t d) { return d >= need; });
+            p.row0 = static_cast<unsigned long long>(b);
+            p.rows = static_cast<unsigned long long>(it - first);
+        }
+        plans[i] = p;
+        out[i].pool_depth = 1;
+        out[i].pool_rows = p.rows;
+        out[i].outcome = GM_DONE;
+    }
+
+    // launch groups: larger residency (shallower stacks) first
+    std::vector<int32_t> idx(static_cast<size_t>(nq));
+    std::vector<int> key(static_cast<size_t>(nq));
+    for (int32_t i = 0; i < nq; ++i) {
+        idx[i] = i;
+        key[i] = e->opt.batch_single_launch ? 0 : residency(e, plans[i].k);
+    }
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return key[x] > key[y]; });
+
+    for (size_t g0 = 0; g0 < idx.size();) {
+        size_t g1 = g0;
+        int32_t levels = 0;
+        while (g1 < idx.size() && key[idx[g1]] == key[idx[g0]]) levels = std::max(levels, plans[idx[g1++]].k);
+        const int32_t g = static_cast<int32_t>(g1 - g0);
+        // streams: member j of the group goes to stream j mod ns; plans are laid
+        // out stream by stream, pos[] maps a plan back to its place in the batch
+        const int32_t ns = std::max(1, std::min(g, batch_streams(e)));
+        e->h_plans.clear();
+        e->h_streams.assign(static_cast<size_t>(ns), gm::StreamCtl{});
+        std::vector<int32_t> pos;
+        unsigned long long items = 0;
+        for (int32_t sidx = 0; sidx < ns; ++sidx) {
+            gm::StreamCtl &sc = e->h_streams[sidx];
+            sc.plan0 = static_cast<int32_t>(e->h_plans.size());
+            unsigned long long local = 0;
+            for (int32_t j = sidx; j < g; j += ns) {
+                Plan p = plans[idx[g0 + j]];
+                p.item0 = local;
+                local += items_of(p.rows);
+                p.item_end = local;
+                e->h_plans.push_back(p);
+                pos.push_back(idx[g0 + j]);
+            }
+            sc.plan1 = static_cast<int32_t>(e->h_plans.size());
+            sc.items = local;
+            items += local;
+        }
+        if (items == 0) {
+            g0 = g1;
+            continue;
+        }
+        gm_status st = ensure_query_slots(e, static_cast<size_t>(g));
+        if (!st) st = ensure_streams(e, static_cast<size_t>(ns));
+        if (st) return st;
+        HIP_TRY(e, hipMemsetAsync(e->d_ctl, 0, sizeof(Control), e->stream));
+        HIP_TRY(e, hipMemsetAsync(e->d_qctl, 0, sizeof(gm::QCtl) * static_cast<size_t>(g), e->stream));
+        HIP_TRY(e, hipMemcpyAsync(e->d_plans, e->h_plans.data(), sizeof(Plan) * static_cast<size_t>(g),
+                                  hipMemcpyHostToDevice, e->stream));
+        HIP_TRY(e, hipMemcpyAsync(e->d_streams, e->h_streams.data(), sizeof(gm::StreamCtl) * static_cast<size_t>(ns),
+                                  hipMemcpyHostToDevice, e->stream));
+        SearchArgs a = graph_args(e);
+        a.nq = g;
+        a.nstreams = ns;
+        a.levels = levels;
+        a.pool = e->d_bylabel;
+        a.slim = use_slim(e, levels) ? 1 : 0;
+        a.budget = 0;  // limits are per query (plan budgets)
+        st = attach_stealing(e, a);
+        if (st) return st;
+        st = reset_stealing(e, a);
+        if (st) return st;
+        int grid_waves = 0;
+        float kernel_ms = 0.f;
+        HIP_TRY(e, gm::launch_start_clock(e->d_ctl, e->stream));
+        HIP_TRY(e, hipEventRecord(e->ev0, e->stream));
+        HIP_TRY(e, gm::launch_search(a, false, e->num_cu, e->opt.waves_per_cu, e->stream, &grid_waves));
+        HIP_TRY(e, hipEventRecord(e->ev1, e->stream));
+        e->h_qctl.resize(static_cast<size_t>(g));
+        HIP_TRY(e, hipMemcpyAsync(e->h_qctl.data(), e->d_qctl, sizeof(gm::QCtl) * static_cast<size_t>(g),
+                                  hipMemcpyDeviceToHost, e->stream));
+        HIP_TRY(e, hipMemcpyAsync(e->h_streams.data(), e->d_streams, sizeof(gm::StreamCtl) * static_cast<size_t>(ns),
+                                  hipMemcpyDeviceToHost, e->stream));
+        Control c{};
+        st = read_ctl(e, &c);
+        if (st) return st;
+        HIP_TRY(e, hipEventElapsedTime(&kernel_ms, e->ev0, e->ev1));
+        sum.kernel_ms += kernel_ms;
+        sum.launches += 1;
+        sum.grid_waves = std::max(sum.grid_waves, grid_waves);
+        for (int32_t sidx = 0; sidx < ns; ++sidx) {
+            const gm::StreamCtl &sc = e->h_streams[sidx];
+            for (int32_t j = sc.plan0; j < sc.plan1; ++j) {
+                const Plan &p = e->h_plans[j];
+                const gm::QCtl &qc = e->h_qctl[j];
+                gm_result &r = out[pos[j]];
+                if (cap && qc.count >= cap) {
+                    r.count = cap;
+                    r.outcome = GM_CAPPED;
+                } else {
+                    r.count = qc.count;
+                    const bool done = p.rows == 0 || (qc.abort != gm::kAbortTime && query_finished(p, qc, sc));
+                    r.outcome = done ? GM_DONE : GM_TIMEOUT;
+                }
+                r.groups = r.kernel_groups = qc.groups;
+                r.tasks = r.kernel_tasks = qc.tasks;
+                r.lanes_active = qc.lanes_active;
+                r.lanes_issued = qc.lanes_issued;
+                r.probes = r.kernel_probes = qc.probes;
+                r.steals = qc.steals;
+                r.scanned = r.kernel_scanned = qc.scanned;
+                r.kernel_lookups = qc.lookups;
+                r.kernel_ms = kernel_ms;
+                r.grid_waves = grid_waves;
+                sum.lookups += qc.lookups;
+            }
+        }
+        g0 = g1;
+    }
+    const double total_ms = elapsed_s() * 1000.0;
+    for (int32_t i = 0; i < nq; ++i) {
+        out[i].search_ms = total_ms;
+        sum.count += out[i].count;
+        sum.tasks += out[i].tasks;
+        sum.scanned += out[i].scanned;
+        sum.probes += out[i].probes;
+        sum.groups += out[i].groups;
+        sum.steals += out[i].steals;
+    }
+    sum.total_ms = total_ms;
+    if (info) *info = sum;
+    return GM_OK;
+}
+
+// Autotuner of the batched launch: coordinate descent over the settings, each
+// knob over a fixed list with the others at their best so far; the measure is
+// the batch's device time, and counts must not depend on the setting.
+gm_status run_tune(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t cap, double time_limit_s,
+                   gm_tuning *out) {
+    const gm_options saved = e->opt;
+    std::vector<gm_result> ref(static_cast<size_t>(std::max(nq, 1))), res(ref.size());
+    gm_batch_info info{};
+    gm_status st = run_batch(e, nq, qids, cap, time_limit_s, ref.data(), &info);
+    if (st) return st;
+    gm_options best = saved;
+    best.steal_threshold = saved.steal_threshold > 0 ? saved.steal_threshold : 128;
+    best.stack_layout = saved.stack_layout == 1 ? 1 : 2;
+    best.batch_streams = batch_streams(e);
+    double best_ms = info.kernel_ms;
+    const double default_ms = info.kernel_ms;
+    int32_t trials = 1;
+    struct Knob {
+        int32_t gm_options::*field;
+        std::vector<int32_t> values;
+    };
+    const Knob knobs[] = {
+        {&gm_options::batch_streams, {1, 16, 64, 256}},
+        {&gm_options::waves_per_cu, {0, 12, 8}},
+        {&gm_options::stack_layout, {2, 1}},
+        {&gm_options::steal_threshold, {32, 128, 512}},
+        {&gm_options::batch_single_launch, {0, 1}},
+    };
+    for (const Knob &kb : knobs) {
+        const gm_options base = best;
+        for (int32_t v : kb.values) {
+            if (v == base.*kb.field) continue;  // measured already
+            e->opt = base;
+            e->opt.*kb.field = v;
+            st = run_batch(e, nq, qids, cap, time_limit_s, res.data(), &info);
+            if (st) {
+                e->opt = saved;
+                return st;
+            }
+            ++trials;
+            for (int32_t i = 0; i < nq; ++i) {
+                const bool both = ref[i].outcome != GM_TIMEOUT && res[i].outcome != GM_TIMEOUT;
+                if (both && (ref[i].count != res[i].count || ref[i].outcome != res[i].outcome)) {
+                    e->opt = saved;
+                    return e->fail(GM_ERR_STATE, "tuning: query " + std::to_string(qids[i]) +
+                                                     " counted differently under two settings");
+                }
+            }
+            if (info.kernel_ms < best_ms) {
+                best_ms = info.kernel_ms;
+                best = e->opt;
+            }
+        }
+    }
+    e->opt = best;
+    gm_tuning t{};
+    t.waves_per_cu = best.waves_per_cu;
+    t.steal_threshold = best.steal_threshold;
+    t.stack_layout = best.stack_layout;
+    t.batch_single_launch = best.batch_single_launch;
+    t.batch_streams = best.batch_streams;
+    t.trials = trials;
+    t.best_ms = best_ms;
+    t.default_ms = default_ms;
+    if (out) *out = t;
     return GM_OK;
 }
 
@@ -501,7 +877,7 @@ gm_status gm_create(int32_t device, const gm_options *opt, gm_engine **out) {
     gm_options o{};
     if (opt) o = *opt;
     if (o.stack_layout < 0 || o.stack_layout > 2 || o.steal_threshold < 0 || o.waves_per_cu < 0 ||
-        o.pool_row_limit < 0) {
+        o.pool_row_limit < 0 || o.batch_single_launch < 0 || o.batch_single_launch > 1 || o.batch_streams < 0) {
         g_create_error = "option out of range";
         return GM_ERR_ARG;
     }
@@ -548,6 +924,8 @@ void gm_destroy(gm_engine *e) {
         for (int i = 0; i < 2; ++i)
             if (e->d_pool[i]) hipFree(e->d_pool[i]);
         if (e->d_rows) hipFree(e->d_rows);
+        if (e->d_plans) hipFree(e->d_plans);
+        if (e->d_qctl) hipFree(e->d_qctl);
         if (e->d_ctl) hipFree(e->d_ctl);
         if (e->d_mail) hipFree(e->d_mail);
         if (e->d_idle_bits) hipFree(e->d_idle_bits);
@@ -613,6 +991,24 @@ gm_status gm_load_graph(gm_engine *e, int32_t n, const int64_t *row_ptr, const i
             }
         });
     }
+    // Vertices by label, highest degree first within a label (ties by id): the
+    // first query vertex's candidates are a prefix of its label's bucket, and
+    // hub roots, the heaviest work, are claimed first.
+    std::vector<int64_t> lab_start(static_cast<size_t>(labels_used) + 1, 0);
+    for (int32_t v = 0; v < n; ++v) ++lab_start[(vinfo[v].y & 0xffu) + 1];
+    for (int32_t c = 0; c < labels_used; ++c) lab_start[c + 1] += lab_start[c];
+    std::vector<int32_t> bylabel(static_cast<size_t>(n));
+    {
+        std::vector<int64_t> fill(lab_start.begin(), lab_start.end() - 1);
+        for (int32_t v = 0; v < n; ++v) bylabel[fill[vinfo[v].y & 0xffu]++] = v;
+    }
+    for (int32_t c = 0; c < labels_used; ++c)
+        std::sort(bylabel.begin() + lab_start[c], bylabel.begin() + lab_start[c + 1], [&](int32_t x, int32_t y) {
+            const uint32_t dx = vinfo[x].y >> 8, dy = vinfo[y].y >> 8;
+            return dx != dy ? dx > dy : x < y;
+        });
+    std::vector<uint32_t> bylabel_deg(static_cast<size_t>(n));
+    for (int32_t i = 0; i < n; ++i) bylabel_deg[i] = vinfo[bylabel[i]].y >> 8;
     if (e->device >= 0) {
         HIP_TRY(e, hipSetDevice(e->device));
         free_graph(e);
@@ -623,6 +1019,8 @@ gm_status gm_load_graph(gm_engine *e, int32_t n, const int64_t *row_ptr, const i
             h = hipMalloc(reinterpret_cast<void **>(&e->d_loff), std::max<size_t>(loff.size(), 1) * sizeof(uint32_t));
         if (h == hipSuccess && stride > 1)
             h = hipMalloc(reinterpret_cast<void **>(&e->d_lcol), std::max<uint64_t>(nnz, 1) * sizeof(int32_t));
+        if (h == hipSuccess)
+            h = hipMalloc(reinterpret_cast<void **>(&e->d_bylabel), std::max<size_t>(n, 1) * sizeof(int32_t));
         if (h != hipSuccess) {
             free_graph(e);
             return e->fail(GM_ERR_NOMEM, std::string("graph upload: ") + hipGetErrorString(h));
@@ -633,11 +1031,14 @@ gm_status gm_load_graph(gm_engine *e, int32_t n, const int64_t *row_ptr, const i
         if (nnz) HIP_TRY(e, hipMemcpy(e->d_col, col, nnz * sizeof(int32_t), hipMemcpyHostToDevice));
         HIP_TRY(e, hipMemcpy(e->d_loff, loff.data(), loff.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
         if (stride > 1 && nnz) HIP_TRY(e, hipMemcpy(e->d_lcol, lcol.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+        if (n) HIP_TRY(e, hipMemcpy(e->d_bylabel, bylabel.data(), static_cast<size_t>(n) * sizeof(int32_t), hipMemcpyHostToDevice));
     } else {
         free_graph(e);
         e->loff_stride = stride;
     }
     e->label_id = std::move(ids);
+    e->lab_start = std::move(lab_start);
+    e->bylabel_deg = std::move(bylabel_deg);
     e->n = n;
     e->nnz = nnz;
     e->has_graph = true;
@@ -721,6 +1122,29 @@ gm_status gm_enumerate(gm_engine *e, int32_t qid, int32_t *rows, uint64_t cap, d
     if (!out) return e->fail(GM_ERR_ARG, "out is null");
     if (!rows || cap == 0) return e->fail(GM_ERR_BUFFER, "enumerate needs a row buffer and cap >= 1");
     return run_search(e, qid, cap, time_limit_s, rows, out);
+}
+
+gm_status gm_count_batch(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t cap, double time_limit_s,
+                         gm_result *out, gm_batch_info *info) {
+    if (!e) return GM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(e->mu);
+    return run_batch(e, nq, qids, cap, time_limit_s, out, info);
+}
+
+gm_status gm_tune_batch(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t cap, double time_limit_s,
+                        gm_tuning *out) {
+    if (!e) return GM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (!out) return e->fail(GM_ERR_ARG, "out is null");
+    return run_tune(e, nq, qids, cap, time_limit_s, out);
+}
+
+gm_status gm_get_options(const gm_engine *e, gm_options *out) {
+    if (!e) return GM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (!out) return e->fail(GM_ERR_ARG, "out is null");
+    *out = e->opt;
+    return GM_OK;
 }
 
 gm_status gm_free_query(gm_engine *e, int32_t qid) {

@@ -1,6 +1,7 @@
 // Types shared by the host engine (engine.cpp) and the gfx950 kernels (kernels.hip).
 #pragma once
 
+#include <stddef.h>
 #include <stdint.h>
 
 #include <hip/hip_runtime.h>
@@ -17,7 +18,9 @@ using VInfo = uint2;
 __host__ __device__ inline uint32_t vi_deg(VInfo a) { return a.y >> 8; }
 __host__ __device__ inline uint32_t vi_lab(VInfo a) { return a.y & 0xffu; }
 
-// Query along the matching order: position i maps query vertex phi[i].
+// Query along the matching order: position i maps query vertex phi[i].  Plans
+// live in device memory (one per query of a launch); kernels read them through
+// the constant address space, so a wavefront's plan fields come from scalar loads.
 struct Plan {
     int32_t k;                // query size
     int32_t depth;            // matched positions per pool row (>= 1)
@@ -25,18 +28,50 @@ struct Plan {
     int32_t lab[kMaxK];       // compact label of phi[i] (255 = absent from G)
     int32_t qdeg[kMaxK];      // query degree of phi[i] (degree filter)
     uint32_t bwd[kMaxK];      // bit j set: phi[j] (j < i) is a backward neighbour of phi[i]
+    unsigned long long cap;   // 0 = none
+    unsigned long long flush; // local matches kept by a wavefront before an atomic flush
+    unsigned long long budget; // time limit of this query in device wall-clock ticks from
+                               // its first work item, 0 = none
+    // this query's share of the launch's pool: rows pool[row0 + r * depth ...],
+    // r < rows, claimed as work items item0 .. item_end - 1 of 64 rows each
+    unsigned long long row0;
+    unsigned long long rows;
+    unsigned long long item0;
+    unsigned long long item_end;
 };
 
-// Device-resident control block, cleared before every search.  Words that many
-// wavefronts hit with atomics or polls live on cache lines of their own (128 B).
-struct alignas(128) Control {
+// Per-query results of a launch.  The count (atomics from every wavefront on
+// the query) and the abort word (polled by them) sit on separate 128-byte
+// lines: sharing one line costs about half the throughput of a single query.
+struct alignas(128) QCtl {
     unsigned long long count;        // matches found (flushed by wavefronts)
-    unsigned long long pad_count[15];
-    unsigned long long pool_next;    // next unclaimed pool row
-    unsigned long long pad_pool[15];
+    unsigned long long pad0[15];
+    unsigned int abort;              // kAbortCap once the count reached the cap, kAbortTime
+                                     // once work remained past the query's time limit
+    unsigned int pad1;
+    unsigned long long t_start;      // device wall clock when its first work item was claimed
+    unsigned long long pad2[14];
+    unsigned long long groups;
+    unsigned long long tasks;
+    unsigned long long scanned;      // candidates read from label slices
+    unsigned long long lookups;      // label-slice bound lookups
+    unsigned long long probes;
+    unsigned long long lanes_active;
+    unsigned long long lanes_issued;
+    unsigned long long steals;
+    int live;                        // work units (items, donations) taken and not finished
+    int pad3[15];
+};
+
+static_assert(sizeof(QCtl) == 384 && offsetof(QCtl, abort) == 128 && offsetof(QCtl, groups) == 256,
+              "hot words of QCtl must sit on lines of their own");
+
+// Device-resident control block of a launch.  Words that many wavefronts hit
+// with atomics or polls live on cache lines of their own (128 B).
+struct alignas(128) Control {
     unsigned long long out_rows;     // rows appended (root scan, expansion, enumerate)
     unsigned long long pad_rows[15];
-    unsigned int abort;              // 0 running, 1 cap reached, 2 time limit
+    unsigned int abort;              // kAbortNone, or kAbortTime (stops the whole launch)
     unsigned int pad_abort[31];
     int busy;                        // wavefronts holding work (donations count from hand-over)
     int pad_busy[31];
@@ -44,16 +79,23 @@ struct alignas(128) Control {
     int pad_idle[31];
     // written once per launch or read by the host only
     unsigned long long measure;      // bound on the next pool level (sum of smallest label slices)
-    unsigned long long groups;
-    unsigned long long tasks;
-    unsigned long long lanes_active;
-    unsigned long long lanes_issued;
-    unsigned long long probes;
-    unsigned long long steals;
-    unsigned long long t0;           // device wall clock when the root scan started
-    unsigned long long scanned;      // candidates read from label slices
-    unsigned long long lookups;      // label-slice bound lookups
+    unsigned long long t0;           // device wall clock at the start of the search
+    unsigned long long pad_cold[14];
 };
+
+// A stream of work items: the items of queries plan0 .. plan1 - 1, one query
+// after the other (each plan's item0 / item_end count from the stream's start).
+// Every wavefront has a home stream and moves on to the next stream once its
+// own runs dry, so a launch holds as many queries in flight as it has streams.
+struct alignas(128) StreamCtl {
+    unsigned long long next;         // next unclaimed item of this stream
+    unsigned long long pad0[15];
+    unsigned long long items;        // items in the stream
+    int32_t plan0, plan1;            // its queries
+    unsigned long long pad1[14];
+};
+
+static_assert(sizeof(StreamCtl) == 256, "StreamCtl: claim counter on a line of its own");
 
 // Mailbox of one wavefront for dynamic balancing (Sec. 4.3): an idle wavefront
 // sets its bit in the idle bitmap and polls only its own mailbox; a busy one
@@ -65,7 +107,8 @@ struct alignas(128) Mailbox {
     unsigned int status;             // kMailEmpty / kMailWaiting / kMailFull
     int32_t depth, pi, pj, ei, ej;
     unsigned long long lanes;        // parent lanes present
-    int32_t pad[24];
+    int32_t qid;                     // query of the donated work
+    int32_t pad[23];
     int32_t rows[kWave * kMaxK];     // rows[q * kMaxK + i] = image of position i for parent lane q
 };
 
@@ -81,14 +124,16 @@ struct SearchArgs {
     const uint32_t *loff;      // label slice bounds: N(v) with label c is
                                // lcol[loff[v*stride + c] .. loff[v*stride + c + 1])
     int32_t loff_stride;       // labels + 1, or 1 when lists are not partitioned (c = 0)
-    int32_t pad_l;
-    const int32_t *pool;       // [pool_rows * depth]
-    unsigned long long pool_rows;
+    const Plan *plans;         // [nq] device copies of the query plans
+    QCtl *qctl;                // [nq] per-query results
+    int32_t nq;                // queries in this launch
+    int32_t levels;            // stack levels per wavefront: the largest k of the launch
+    const int32_t *pool;       // pool rows of every query (each plan gives its share)
+    StreamCtl *streams;        // [nstreams] work-item streams
+    int32_t nstreams;
     int32_t *out;              // expansion: next pool; enumerate: rows
     unsigned long long out_cap; // rows that fit in out
     Control *ctl;
-    unsigned long long cap;    // 0 = none
-    unsigned long long flush;  // local matches kept before an atomic flush
     unsigned long long budget; // time limit in device wall-clock ticks from ctl->t0, 0 = none
     Mailbox *mail;             // one per wavefront (work stealing), or null
     unsigned long long *idle_bits; // bit w set: wavefront w waits for work
@@ -96,7 +141,6 @@ struct SearchArgs {
     int32_t steal_threshold;
     int32_t slim;              // 1: slim stack layout (membership tests on label slices)
     int32_t measure_next;      // expansion: add the next level's size bound to ctl->measure
-    Plan plan;
 };
 
 // Launchers implemented in kernels.hip.  All return hipSuccess or the launch error.
@@ -108,6 +152,8 @@ hipError_t launch_root_scan(const VInfo *vinfo, int32_t n, int32_t lab0, int32_t
 hipError_t launch_expand(const SearchArgs &a, int num_cu, hipStream_t s);
 hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int waves_per_cu, hipStream_t s,
                          int *grid_waves_out);
+// Writes the device wall clock into ctl->t0 (start of a search's time budget).
+hipError_t launch_start_clock(Control *ctl, hipStream_t s);
 // Wavefronts a depth-first search launch for a query of `levels` positions keeps resident.
 int search_waves(int levels, int num_cu, int waves_per_cu, bool slim);
 hipError_t launch_steal_init(Mailbox *mail, unsigned long long *idle_bits, int32_t n, hipStream_t s);

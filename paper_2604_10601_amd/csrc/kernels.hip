@@ -41,9 +41,16 @@ namespace {
 
 constexpr int kWavesPerBlock = 1;
 constexpr int kBlock = kWave * kWavesPerBlock;
-constexpr int kLinear = 8;  // longest list tail scanned with independent loads
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
+
+// Plans are read through the constant address space: with a wave-uniform query
+// index every field is a scalar load, as if the plan were a kernel argument.
+typedef const __attribute__((address_space(4))) Plan *PlanPtr;
+
+__device__ __forceinline__ PlanPtr plan_at(const SearchArgs &a, int32_t q) {
+    return reinterpret_cast<PlanPtr>(reinterpret_cast<uintptr_t>(a.plans)) + q;
+}
 
 // Number of set bits of m below this lane.
 __device__ __forceinline__ uint32_t popc_below(uint64_t m) {
@@ -226,16 +233,16 @@ struct Gen {
 // check, so the smallest such slice is scanned instead (earliest position on
 // ties); it yields exactly the same valid extensions.
 template <bool SLIM>
-__device__ __forceinline__ Gen generate_tasks(WaveStack &S, const SearchArgs &a, int l, uint64_t F,
+__device__ __forceinline__ Gen generate_tasks(WaveStack &S, const SearchArgs &a, PlanPtr P, int l, uint64_t F,
                                               uint32_t lane) {
     Gen g{0u, 0u, 0u};
     uint32_t cs = 0, cl = 0xffu;
     if ((F >> lane) & 1ull) {
-        const uint32_t bw = a.plan.bwd[l];
+        const uint32_t bw = P->bwd[l];
         const int lowest = __builtin_ctz(bw);
         const int stride = a.loff_stride;
         const bool sliced = stride > 1;
-        const uint32_t lab = sliced ? static_cast<uint32_t>(a.plan.lab[l]) : 0u;
+        const uint32_t lab = sliced ? static_cast<uint32_t>(P->lab[l]) : 0u;
         uint32_t q = lane;
         uint32_t best_full = 0xffffffffu, best_n = 0xffffffffu, best_a = 0, best_j = 0;
         for (int i = l - 1; i >= lowest; --i) {
@@ -408,17 +415,16 @@ __device__ __forceinline__ bool test_lists(const SearchArgs &a, uint32_t lab, ui
 // the walk (kLists at a time, the slot index being the same in every lane) and
 // tested together.
 template <bool SLIM>
-__device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, int l, const Round &r, uint32_t lane,
-                                        VInfo &vi, uint32_t &probes, uint32_t &lookups) {
+__device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanPtr P, int l, const Round &r,
+                                        uint32_t lane, VInfo &vi, uint32_t &probes, uint32_t &lookups) {
     bool ok = lane < r.ntask;
     vi = make_uint2(0u, 0u);
     if (ok) vi = a.vinfo[r.v];
-    ok = ok && vi_lab(vi) == static_cast<uint32_t>(a.plan.lab[l]) &&
-         vi_deg(vi) >= static_cast<uint32_t>(a.plan.qdeg[l]);
+    ok = ok && vi_lab(vi) == static_cast<uint32_t>(P->lab[l]) && vi_deg(vi) >= static_cast<uint32_t>(P->qdeg[l]);
     if (ok) {
-        const uint32_t bw = a.plan.bwd[l];
+        const uint32_t bw = P->bwd[l];
         const uint32_t js = S.cl[l * kWave + r.owner] & 0xffu;
-        const uint32_t lab = a.loff_stride > 1 ? static_cast<uint32_t>(a.plan.lab[l]) : 0u;
+        const uint32_t lab = a.loff_stride > 1 ? static_cast<uint32_t>(P->lab[l]) : 0u;
         uint32_t lo[kLists] = {0u, 0u, 0u, 0u};
         uint32_t n[kLists] = {0u, 0u, 0u, 0u};
         int used = 0;
@@ -547,10 +553,11 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 // them the upper half of the unscattered tasks of this wavefront's
 // shallowest non-leaf level holding at least `threshold` of them ("split the
 // stack in half").  The donor keeps the lower half by moving that level's end.
-// Returns true if work was handed over.
+// The thief takes over one work unit of query cq.  Returns true if work was
+// handed over.
 template <bool SLIM>
-__device__ bool donate(WaveStack &S, const SearchArgs &a, int base, int l, uint32_t lane) {
-    const int k = a.plan.k;
+__device__ bool donate(WaveStack &S, const SearchArgs &a, PlanPtr P, int32_t cq, int base, int l, uint32_t lane) {
+    const int k = P->k;
     const int top = l < k - 2 ? l : k - 2;
     for (int L = base; L <= top; ++L) {
         const uint32_t ci = __builtin_amdgcn_readfirstlane(S.cur_i[L]);
@@ -591,7 +598,9 @@ __device__ bool donate(WaveStack &S, const SearchArgs &a, int base, int l, uint3
             store_agent(&mb.pj, static_cast<int32_t>(pj));
             store_agent(&mb.ei, static_cast<int32_t>(ei));
             store_agent(&mb.ej, static_cast<int32_t>(ej));
+            store_agent(&mb.qid, cq);
             atomicAdd(&ctl->busy, 1);  // the thief is busy from the hand-over on
+            atomicAdd(&a.qctl[cq].live, 1);
             S.end_i[L] = p;
             S.end_j[L] = pj;
         }
@@ -613,10 +622,10 @@ enum Mode { kCount = 0, kEnumerate = 1, kExpand = 2 };
 // Size bound of the level after an expansion, for one new row (positions 0..d,
 // position d being the row's candidate): its smallest label slice for position
 // d + 1 among that position's backward neighbours.
-__device__ __forceinline__ uint32_t next_level_bound(const WaveStack &S, const SearchArgs &a, int d,
+__device__ __forceinline__ uint32_t next_level_bound(const WaveStack &S, const SearchArgs &a, PlanPtr P, int d,
                                                      const Round &r) {
-    const uint32_t bw = a.plan.bwd[d + 1];
-    const uint32_t lab = a.loff_stride > 1 ? static_cast<uint32_t>(a.plan.lab[d + 1]) : 0u;
+    const uint32_t bw = P->bwd[d + 1];
+    const uint32_t lab = a.loff_stride > 1 ? static_cast<uint32_t>(P->lab[d + 1]) : 0u;
     uint32_t best = 0xffffffffu;
     for (int i = 0; i <= d; ++i) {
         if (!((bw >> i) & 1u)) continue;
@@ -651,59 +660,163 @@ __host__ __device__ constexpr size_t wave_lds_bytes(int levels, bool expand, boo
     return stack_bytes(levels, slim) + (expand ? static_cast<size_t>(kStageRows) * kStageWidth * 4u : 0u);
 }
 
+// Query that item t of a stream (queries p0 .. p1 - 1) belongs to: the current
+// one when t is in its range, else a bisection of the plans' first items.
+__device__ __forceinline__ int32_t find_query(const SearchArgs &a, PlanPtr P, int32_t cq, int32_t p0, int32_t p1,
+                                              unsigned long long t) {
+    if (cq >= p0 && cq < p1 && t >= P->item0 && t < P->item_end) return cq;
+    int32_t lo = p0, hi = p1 - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (plan_at(a, mid)->item0 <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Work counters of the query a wavefront is on; per-lane fields are summed over
+// the wavefront when flushed.
+struct Tally {
+    uint64_t tasks, scanned, lookups, probes;  // per lane
+    uint32_t probes_run, lookups_run;          // per lane, folded into the above every 32 rounds
+    uint64_t groups, active, issued, count, steals;  // wave-uniform
+};
+
+__device__ __forceinline__ void fold_run(Tally &t) {
+    t.probes += t.probes_run;
+    t.lookups += t.lookups_run;
+    t.probes_run = 0;
+    t.lookups_run = 0;
+}
+
+// Adds the wavefront's matches to query q's count; returns true once the count
+// has reached the query's cap (the caller can drop its remaining work at once).
+__device__ __forceinline__ bool count_flush(const SearchArgs &a, PlanPtr P, int32_t q, Tally &t) {
+    if (!t.count) return false;
+    const unsigned long long before = lane0_atomic_add(&a.qctl[q].count, t.count);
+    const bool capped = P->cap && before + t.count >= P->cap;
+    if (capped && lane_id() == 0) atomicCAS(&a.qctl[q].abort, kAbortNone, kAbortCap);
+    t.count = 0;
+    return capped;
+}
+
+// Adds the wavefront's counters to query q's slots and zeroes them.
+__device__ void tally_flush(const SearchArgs &a, PlanPtr P, int32_t q, Tally &t) {
+    (void)count_flush(a, P, q, t);
+    fold_run(t);
+    const uint64_t tasks = wave_sum64(t.tasks);
+    const uint64_t scanned = wave_sum64(t.scanned);
+    const uint64_t lookups = wave_sum64(t.lookups);
+    const uint64_t probes = wave_sum64(t.probes);
+    if (lane_id() == 0) {
+        QCtl &c = a.qctl[q];
+        if (t.groups) atomicAdd(&c.groups, t.groups);
+        if (tasks) atomicAdd(&c.tasks, tasks);
+        if (scanned) atomicAdd(&c.scanned, scanned);
+        if (lookups) atomicAdd(&c.lookups, lookups);
+        if (probes) atomicAdd(&c.probes, probes);
+        if (t.active) atomicAdd(&c.lanes_active, t.active);
+        if (t.issued) atomicAdd(&c.lanes_issued, t.issued);
+        if (t.steals) atomicAdd(&c.steals, t.steals);
+    }
+    t = Tally{};
+}
+
+__device__ __forceinline__ unsigned int load_word(unsigned int *p) {
+    unsigned int v = 0;
+    if (lane_id() == 0) v = load_agent(p);
+    return read_lane(v, 0);
+}
+
 template <int MODE, bool SLIM>
-__global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
+__global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    uint8_t *mine = lds + (threadIdx.x / kWave) * wave_lds_bytes(a.plan.k, MODE == kExpand, SLIM);
-    WaveStack S = carve_stack<SLIM>(mine, a.plan.k);
-    int32_t *stage = reinterpret_cast<int32_t *>(mine + stack_bytes(a.plan.k, SLIM));
+    const int levels = a.levels;
+    uint8_t *mine = lds + (threadIdx.x / kWave) * wave_lds_bytes(levels, MODE == kExpand, SLIM);
+    WaveStack S = carve_stack<SLIM>(mine, levels);
+    int32_t *stage = reinterpret_cast<int32_t *>(mine + stack_bytes(levels, SLIM));
     uint32_t staged = 0;
     const uint32_t lane = lane_id();
-    const int k = a.plan.k;
-    const int d = a.plan.depth;
     Control *ctl = a.ctl;
     const bool stealing = a.mail != nullptr;
     const uint32_t wave_id = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
 
-    uint64_t my_tasks = 0, my_scanned = 0, my_lookups = 0, my_bound = 0;
-    uint32_t my_probes = 0, my_plookups = 0;
-    uint64_t my_probes_total = 0;
-    uint64_t w_groups = 0, w_active = 0, w_issued = 0, w_count = 0, w_steals = 0;
+    int32_t cq = 0;  // query of the wavefront's current work (wave-uniform)
+    PlanPtr P = plan_at(a, 0);
+    int32_t sid = static_cast<int32_t>(wave_id % static_cast<uint32_t>(a.nstreams));  // home stream first
+    int32_t dry = 0;  // streams found exhausted
+    unsigned long long qstart = 0;  // start of that query's time budget
+    Tally t{};
+    uint64_t my_bound = 0;
     uint32_t rounds = 0;
     bool stop = false;
-    bool pool_left = true;
+    bool items_left = true;
     const unsigned long long deadline = a.budget ? a.ctl->t0 + a.budget : 0ull;
     if (stealing) lane0_add(&ctl->busy, 1);
 
     while (!stop) {
-        int base = d;
+        int base = 0;
         bool have = false;
-        if (pool_left) {
-            const unsigned long long r0 = lane0_atomic_add(&ctl->pool_next, kWave);
-            if (r0 < a.pool_rows) {
-                const unsigned long long left = a.pool_rows - r0;
-                const uint32_t nrows = left < kWave ? static_cast<uint32_t>(left) : kWave;
-                const bool mine = lane < nrows;
-                for (int i = 0; i < d; ++i) {
-                    int32_t v = 0;
-                    VInfo vi = make_uint2(0u, 0u);
-                    if (mine) {
-                        v = a.pool[(r0 + lane) * static_cast<unsigned long long>(d) + i];
-                        vi = a.vinfo[v];
-                    }
-                    push_entry<SLIM>(S, i, lane, v, vi, lane);
-                }
-                const uint64_t F0 = ballot(mine);
-                const Gen g = generate_tasks<SLIM>(S, a, d, F0, lane);
-                my_tasks += g.tasks;
-                my_scanned += g.scanned;
-                my_lookups += g.lookups;
-                w_groups += __popcll(F0);
-                open_level(S, d, lane);
-                have = true;
-            } else {
-                pool_left = false;
+        // a work item: 64 pool rows of one query, skipped once that query reached its cap
+        while (items_left) {
+            StreamCtl &sc = a.streams[sid];
+            const unsigned long long it = lane0_atomic_add(&sc.next, 1ull);
+            if (it >= sc.items) {  // this stream ran dry: help the next one
+                if (++dry >= a.nstreams) items_left = false;
+                sid = sid + 1 == a.nstreams ? 0 : sid + 1;
+                continue;
             }
+            const int32_t q = find_query(a, P, cq, sc.plan0, sc.plan1, it);
+            if (q != cq) {
+                tally_flush(a, P, cq, t);
+                cq = q;
+                P = plan_at(a, q);
+            }
+            if (load_word(&a.qctl[cq].abort) != kAbortNone) {
+                // capped or out of time: nobody needs the query's other items
+                if (lane == 0) atomicMax(&sc.next, static_cast<unsigned long long>(P->item_end));
+                continue;
+            }
+            if (P->budget) {  // the query's clock starts with its first claimed item
+                unsigned long long old = 0;
+                if (lane == 0) {
+                    const unsigned long long now = wall_clock64();
+                    old = atomicCAS(&a.qctl[cq].t_start, 0ull, now);
+                    if (old == 0ull) old = now;
+                }
+                qstart = read_lane64(old, 0);
+            }
+            const int d = P->depth;
+            const unsigned long long r0 = (it - P->item0) * kWave;
+            const unsigned long long left = P->rows - r0;
+            const uint32_t nrows = left < kWave ? static_cast<uint32_t>(left) : kWave;
+            const bool mine = lane < nrows;
+            const int32_t *src = a.pool + P->row0 + (r0 + lane) * static_cast<unsigned long long>(d);
+            for (int i = 0; i < d; ++i) {
+                int32_t v = 0;
+                VInfo vi = make_uint2(0u, 0u);
+                if (mine) {
+                    v = src[i];
+                    vi = a.vinfo[v];
+                }
+                push_entry<SLIM>(S, i, lane, v, vi, lane);
+            }
+            const uint64_t F0 = ballot(mine);
+            if (d >= P->k) {  // the rows are whole matches (a one-vertex query)
+                t.count += __popcll(F0);
+                (void)count_flush(a, P, cq, t);
+                continue;
+            }
+            lane0_add(&a.qctl[cq].live, 1);
+            const Gen g = generate_tasks<SLIM>(S, a, P, d, F0, lane);
+            t.tasks += g.tasks;
+            t.scanned += g.scanned;
+            t.lookups += g.lookups;
+            t.groups += __popcll(F0);
+            open_level(S, d, lane);
+            base = d;
+            have = true;
+            break;
         }
         if (!have) {
             if (!stealing) break;
@@ -722,9 +835,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
             for (uint32_t iter = 0;; ++iter) {
                 for (uint32_t z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(16);
                 nap = nap < 32u ? nap * 2u : 32u;
-                unsigned int stt = 0;
-                if (lane == 0) stt = load_agent(&mb.status);
-                if (read_lane(stt, 0) == kMailFull) {
+                if (load_word(&mb.status) == kMailFull) {
                     got = true;
                     break;
                 }
@@ -741,8 +852,21 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
                 }
             }
             if (!got) break;
-            // the donated work: parent rows at level L-1 and a task range at level L
-            const int L = load_agent(&mb.depth);
+            // the donated work: parent rows at level L-1 and a task range at level L of query qid
+            int32_t q = 0;
+            if (lane == 0) q = load_agent(&mb.qid);
+            q = static_cast<int32_t>(read_lane(static_cast<uint32_t>(q), 0));
+            if (q != cq) {
+                tally_flush(a, P, cq, t);
+                cq = q;
+                P = plan_at(a, q);
+            }
+            if (P->budget) {
+                unsigned long long ts = 0;
+                if (lane == 0) ts = load_agent(&a.qctl[cq].t_start);
+                qstart = read_lane64(ts, 0);
+            }
+            const int L = __builtin_amdgcn_readfirstlane(load_agent(&mb.depth));
             const uint64_t lanes = load_agent(&mb.lanes);
             const bool mine = (lanes >> lane) & 1ull;
             for (int i = 0; i < L; ++i) {
@@ -754,7 +878,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
                 }
                 push_entry<SLIM>(S, i, lane, v, vi, lane);
             }
-            generate_tasks<SLIM>(S, a, L, lanes, lane);  // already counted by the donor
+            generate_tasks<SLIM>(S, a, P, L, lanes, lane);  // already counted by the donor
             if (lane == 0) {
                 S.cur_i[L] = static_cast<uint32_t>(load_agent(&mb.pi));
                 S.cur_j[L] = static_cast<uint32_t>(load_agent(&mb.pj));
@@ -764,8 +888,15 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
             wait_memory();
             if (lane == 0) store_agent(&mb.status, static_cast<unsigned int>(kMailEmpty));
             base = L;
-            ++w_steals;
+            ++t.steals;
         }
+        // the unit's query, made provably wave-uniform so that every plan field
+        // in the loop below is a scalar load
+        cq = __builtin_amdgcn_readfirstlane(cq);
+        P = plan_at(a, cq);
+        const int k = P->k;
+        const int d = P->depth;
+        bool dropped = false;  // the query reached its cap or time limit: drop the rest of this unit
         int l = base;
         while (l >= base) {
             const Round r = scatter(S, a.lcol, l, lane);
@@ -773,10 +904,10 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
                 --l;
                 continue;
             }
-            w_active += r.ntask;
-            w_issued += kWave;
+            t.active += r.ntask;
+            t.issued += kWave;
             VInfo vi;
-            const bool ok = process<SLIM>(S, a, l, r, lane, vi, my_probes, my_plookups);
+            const bool ok = process<SLIM>(S, a, P, l, r, lane, vi, t.probes_run, t.lookups_run);
             const uint64_t m = ballot(ok);
             if (MODE == kExpand) {
                 if (m) {
@@ -787,7 +918,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
                             int32_t *row = stage + (staged + popc_below(m)) * static_cast<uint32_t>(d + 1);
                             for (int i = 0; i < d; ++i) row[i] = S.v[(i) * kWave + (r.owner)];
                             row[d] = r.v;
-                            if (a.measure_next) my_bound += next_level_bound(S, a, d, r);
+                            if (a.measure_next) my_bound += next_level_bound(S, a, P, d, r);
                         }
                         staged += nv;
                     } else {
@@ -798,7 +929,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
                             for (int i = 0; i < d; ++i) row[i] = S.v[(i) * kWave + (r.owner)];
                             row[d] = r.v;
                         }
-                        if (ok && a.measure_next) my_bound += next_level_bound(S, a, d, r);
+                        if (ok && a.measure_next) my_bound += next_level_bound(S, a, P, d, r);
                     }
                 }
             } else if (l == k - 1) {
@@ -807,74 +938,63 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
                     const unsigned long long slot = b0 + popc_below(m);
                     if (ok && slot < a.out_cap) {
                         int32_t *row = a.out + slot * static_cast<unsigned long long>(k);
-                        row[a.plan.phi[l]] = r.v;
+                        row[P->phi[l]] = r.v;
                         uint32_t q = r.owner;
                         for (int i = l - 1; i >= 0; --i) {
-                            row[a.plan.phi[i]] = S.v[(i) * kWave + (q)];
+                            row[P->phi[i]] = S.v[(i) * kWave + (q)];
                             q = ent_pid<SLIM>(S, i, q);
                         }
                     }
                 }
-                w_count += __popcll(m);
+                t.count += __popcll(m);
             } else if (m) {
                 push_entry<SLIM>(S, l, lane, r.v, vi, r.owner);
-                const Gen g = generate_tasks<SLIM>(S, a, l + 1, m, lane);
-                my_tasks += g.tasks;
-                my_scanned += g.scanned;
-                my_lookups += g.lookups;
-                w_groups += __popcll(m);
+                const Gen g = generate_tasks<SLIM>(S, a, P, l + 1, m, lane);
+                t.tasks += g.tasks;
+                t.scanned += g.scanned;
+                t.lookups += g.lookups;
+                t.groups += __popcll(m);
                 open_level(S, l + 1, lane);
                 ++l;
             }
             ++rounds;
-            if (w_count >= a.flush || (rounds & 31u) == 0) {
-                if (w_count) {
-                    const unsigned long long before = lane0_atomic_add(&ctl->count, w_count);
-                    if (a.cap && before + w_count >= a.cap) set_abort(ctl, kAbortCap);
-                    w_count = 0;
-                }
+            if (t.count >= P->flush || (rounds & 31u) == 0) {
+                if (count_flush(a, P, cq, t)) dropped = true;
                 if ((rounds & 31u) == 0) {
-                    if (deadline && wall_clock64() > deadline) set_abort(ctl, kAbortTime);
+                    if (deadline | P->budget) {
+                        const unsigned long long now = wall_clock64();
+                        if (deadline && now > deadline) set_abort(ctl, kAbortTime);
+                        if (P->budget && now > qstart + P->budget && lane == 0)
+                            atomicCAS(&a.qctl[cq].abort, kAbortNone, kAbortTime);
+                    }
                     if (load_abort(ctl) != kAbortNone) stop = true;
-                    if (stealing && !stop && (rounds & 127u) == 0) {  // idle wavefronts exist only once the pool is empty
+                    else if (!dropped && load_word(&a.qctl[cq].abort) != kAbortNone) dropped = true;
+                    if (stealing && !stop && !dropped && (rounds & 127u) == 0) {
                         int waiting = 0;
                         if (lane == 0) waiting = load_agent(&ctl->idle_count);
                         if (static_cast<int>(read_lane(static_cast<uint32_t>(waiting), 0)) > 0)
-                            donate<SLIM>(S, a, base, l, lane);
+                            donate<SLIM>(S, a, P, cq, base, l, lane);
                     }
+                    fold_run(t);
                 }
-                my_probes_total += my_probes;
-                my_probes = 0;
-                my_lookups += my_plookups;
-                my_plookups = 0;
-                if (stop) break;
+                if (stop || dropped) break;
             }
         }
+        // a unit that ran to its end is finished; one cut short by the time limit is not
+        if (!stop) lane0_add(&a.qctl[cq].live, -1);
     }
     if (MODE == kExpand) {
-        flush_stage(stage, staged, d + 1, a);
+        flush_stage(stage, staged, P->depth + 1, a);
         if (a.measure_next) {
             const uint64_t b = wave_sum64(my_bound);
             if (lane == 0 && b) atomicAdd(&ctl->measure, static_cast<unsigned long long>(b));
         }
     }
-    my_probes_total += my_probes;
-    my_lookups += my_plookups;
-    const uint64_t tasks = wave_sum64(my_tasks);
-    const uint64_t scanned = wave_sum64(my_scanned);
-    const uint64_t lookups = wave_sum64(my_lookups);
-    const uint64_t probes = wave_sum64(my_probes_total);
-    if (lane == 0) {
-        if (w_count) atomicAdd(&ctl->count, w_count);
-        atomicAdd(&ctl->groups, w_groups);
-        atomicAdd(&ctl->tasks, tasks);
-        atomicAdd(&ctl->scanned, scanned);
-        atomicAdd(&ctl->lookups, lookups);
-        atomicAdd(&ctl->lanes_active, w_active);
-        atomicAdd(&ctl->lanes_issued, w_issued);
-        atomicAdd(&ctl->probes, probes);
-        atomicAdd(&ctl->steals, w_steals);
-    }
+    tally_flush(a, P, cq, t);
+}
+
+__global__ void start_clock_kernel(Control *ctl) {
+    if (threadIdx.x == 0) ctl->t0 = wall_clock64();
 }
 
 __global__ void steal_init_kernel(Mailbox *mail, unsigned long long *idle_bits, int32_t n) {
@@ -938,9 +1058,10 @@ int blocks_per_cu(int levels, int waves_per_cu) {
 
 template <int MODE, bool SLIM>
 hipError_t launch_persistent(const SearchArgs &a, int num_cu, int waves_per_cu, hipStream_t s, int *grid_waves) {
-    if (a.plan.k < 1 || a.plan.k > kMaxK) return hipErrorInvalidValue;
-    const size_t lds_bytes = wave_lds_bytes(a.plan.k, MODE == kExpand, SLIM) * kWavesPerBlock;
-    int blocks = num_cu * blocks_per_cu<MODE, SLIM>(a.plan.k, waves_per_cu);
+    if (a.levels < 1 || a.levels > kMaxK || a.nq < 1 || !a.plans || !a.qctl || a.nstreams < 1 || !a.streams)
+        return hipErrorInvalidValue;
+    const size_t lds_bytes = wave_lds_bytes(a.levels, MODE == kExpand, SLIM) * kWavesPerBlock;
+    int blocks = num_cu * blocks_per_cu<MODE, SLIM>(a.levels, waves_per_cu);
     if (a.mail && blocks * kWavesPerBlock > a.steal_slots) blocks = a.steal_slots / kWavesPerBlock;  // one mailbox each
     if (blocks < 1) blocks = 1;
     if (grid_waves) *grid_waves = blocks * kWavesPerBlock;
@@ -980,6 +1101,11 @@ hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int wa
     }
     if (enumerate) return launch_persistent<kEnumerate, false>(a, num_cu, waves_per_cu, s, grid_waves_out);
     return launch_persistent<kCount, false>(a, num_cu, waves_per_cu, s, grid_waves_out);
+}
+
+hipError_t launch_start_clock(Control *ctl, hipStream_t s) {
+    hipLaunchKernelGGL(start_clock_kernel, dim3(1), dim3(kWave), 0, s, ctl);
+    return hipGetLastError();
 }
 
 hipError_t launch_steal_init(Mailbox *mail, unsigned long long *idle_bits, int32_t n, hipStream_t s) {

@@ -175,13 +175,15 @@ def induced_query(g: Graph, verts: Sequence[int]) -> Query:
     verts = np.asarray(verts, dtype=np.int64)
     k = len(verts)
     edges = []
-    for a in range(k):
+    for a in range(k - 1):
         lo, hi = g.row_ptr[verts[a]], g.row_ptr[verts[a] + 1]
         nb = g.col[lo:hi]
-        for b in range(a + 1, k):
-            p = np.searchsorted(nb, verts[b])
-            if p < nb.shape[0] and nb[p] == verts[b]:
-                edges.append((a, b))
+        if nb.shape[0] == 0:
+            continue
+        later = verts[a + 1:]
+        p = np.minimum(np.searchsorted(nb, later), nb.shape[0] - 1)
+        for b in np.flatnonzero(nb[p] == later):
+            edges.append((a, a + 1 + int(b)))
     e = np.asarray(edges, dtype=np.int32).reshape(-1, 2)
     return Query(k=k, edges=e, labels=g.labels[verts].astype(np.int32),
                  witness=verts.astype(np.int32))
@@ -289,3 +291,37 @@ def large_rmat24(per_class: int = 25) -> Workload:
     g = rmat24_graph()
     qs = extract_queries(g, [12, 16, 24, 32], per_class, per_class, seed=26)
     return Workload("rmat24_ef16_zipf8_q12-32", g, qs, cap=1_000_000_000, time_limit_s=60.0)
+
+
+_WALK_GRAPH: Optional[Graph] = None  # graph shared with forked query-drawing workers
+
+
+def _walk_queries(args) -> List[Query]:
+    sizes, seed = args
+    g = _WALK_GRAPH
+    rng = _rng(seed)
+    return [induced_query(g, random_walk_vertices(g, int(k), rng)) for k in sizes]
+
+
+def batch_rmat20(num_queries: int = 10_000, seed: int = 40, g: Optional[Graph] = None,
+                 workers: int = 8) -> Workload:
+    """The R-MAT scale-20 graph with num_queries random-walk queries whose sizes are
+    uniform in 4..32 (labels copied from G, so they follow G's label frequencies).
+    Per query: cap 1e6 embeddings, 1 s time limit.  Queries are drawn in chunks of
+    500, chunk c with seed 1000 * seed + c, so the set does not depend on `workers`."""
+    global _WALK_GRAPH
+    g = rmat20_graph() if g is None else g
+    sizes = _rng(seed).integers(4, 33, size=num_queries)
+    chunks = [(sizes[c:c + 500], 1000 * seed + c // 500) for c in range(0, num_queries, 500)]
+    _WALK_GRAPH = g
+    try:
+        if workers > 1 and len(chunks) > 1:
+            import multiprocessing as mp
+            with mp.get_context("fork").Pool(min(workers, len(chunks))) as pool:
+                parts = pool.map(_walk_queries, chunks)
+        else:
+            parts = [_walk_queries(c) for c in chunks]
+    finally:
+        _WALK_GRAPH = None
+    qs = [q for part in parts for q in part]
+    return Workload("rmat20_ef16_zipf16_q4-32_mixed", g, qs, cap=1_000_000, time_limit_s=1.0)

@@ -35,14 +35,16 @@ def test_library_exports_every_declared_function():
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gmatch.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(gm_options), sizeof(gm_result),'
-                   ' offsetof(gm_result, kernel_ms), offsetof(gm_options, stack_layout),'
-                   ' offsetof(gm_result, rows));return 0;}\n')
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gm_options),'
+                   ' sizeof(gm_result), offsetof(gm_result, kernel_ms), offsetof(gm_options, stack_layout),'
+                   ' offsetof(gm_result, rows), offsetof(gm_options, batch_single_launch),'
+                   ' sizeof(gm_batch_info), offsetof(gm_batch_info, count), sizeof(gm_tuning));return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
     vals = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     assert vals == [ctypes.sizeof(gm.Options), ctypes.sizeof(gm._CResult), gm._CResult.kernel_ms.offset,
-                    gm.Options.stack_layout.offset, gm._CResult.rows.offset]
+                    gm.Options.stack_layout.offset, gm._CResult.rows.offset, gm.Options.batch_single_launch.offset,
+                    ctypes.sizeof(gm.BatchInfo), gm.BatchInfo.count.offset, ctypes.sizeof(gm.Tuning)]
 
 
 @pytest.fixture()
@@ -122,12 +124,23 @@ def test_host_engine_refuses_to_search(host_engine):
     e.load(S.complete(4))
     expect(gm.GM_ERR_DEVICE, e.count, qid)
     expect(gm.GM_ERR_DEVICE, e.enumerate, qid, 10)
+    expect(gm.GM_ERR_DEVICE, e.count_batch, [qid, qid])
+    expect(gm.GM_ERR_STATE, e.count_batch, [qid, 999])
+    expect(gm.GM_ERR_DEVICE, e.tune_batch, [qid])
+    res, info = e.count_batch([])                                                # empty batch: nothing to do
+    assert res == [] and info.launches == 0
+    o = e.options()
+    assert (o.stack_layout, o.batch_single_launch) == (0, 0)
 
 
 def test_bad_options():
     with pytest.raises(gm.GmError) as ei:
         gm.Engine(device=-1, stack_layout=7)
     assert ei.value.status == gm.GM_ERR_ARG
+    opt = gm.Options()
+    opt.batch_single_launch = 2
+    h = ctypes.c_void_p()
+    assert gm.load_library().gm_create(-1, ctypes.byref(opt), ctypes.byref(h)) == gm.GM_ERR_ARG
     with pytest.raises(gm.GmError) as ei:
         gm.Engine(device=-2)
     assert ei.value.status == gm.GM_ERR_ARG
