@@ -183,6 +183,8 @@ def main() -> int:
     ap.add_argument("--time-limit", type=float, default=-1.0, help="override the workload's per-query limit")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle time budget for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the extra gm_count_batch pass over the same queries (profiling runs)")
     ap.add_argument("--tau", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--disable-stealing", action="store_true")
@@ -319,15 +321,16 @@ def main() -> int:
             "algorithmic_bytes_per_launch": b_alg / max(1, launches),
         },
     }
-    # the same queries in shared persistent launches (gm_count_batch), one call
-    e.count_batch(qids, cap=cap, time_limit_s=limit)
-    t0 = time.perf_counter()
-    bres, binfo = e.count_batch(qids, cap=cap, time_limit_s=limit)
-    bwall = time.perf_counter() - t0
-    out["batched"] = {"value": binfo.count / bwall, "unit": "embeddings/s", "ms": bwall * 1000.0,
-                      "kernel_ms": binfo.kernel_ms, "launches": binfo.launches,
-                      "same_counts": all((a.count, a.outcome) == (b.count, b.outcome)
-                                         for a, b in zip(steps[-1], bres))}
+    if not args.no_batched:
+        # the same queries in shared persistent launches (gm_count_batch), one call
+        e.count_batch(qids, cap=cap, time_limit_s=limit)
+        t0 = time.perf_counter()
+        bres, binfo = e.count_batch(qids, cap=cap, time_limit_s=limit)
+        bwall = time.perf_counter() - t0
+        out["batched"] = {"value": binfo.count / bwall, "unit": "embeddings/s", "ms": bwall * 1000.0,
+                          "kernel_ms": binfo.kernel_ms, "launches": binfo.launches,
+                          "same_counts": all((a.count, a.outcome) == (b.count, b.outcome)
+                                             for a, b in zip(steps[-1], bres))}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w, phis, args.cpu_seconds, cap, per_query_s=10.0)

@@ -695,7 +695,11 @@ __device__ __forceinline__ bool count_flush(const SearchArgs &a, PlanPtr P, int3
     if (!t.count) return false;
     const unsigned long long before = lane0_atomic_add(&a.qctl[q].count, t.count);
     const bool capped = P->cap && before + t.count >= P->cap;
-    if (capped && lane_id() == 0) atomicCAS(&a.qctl[q].abort, kAbortNone, kAbortCap);
+    if (capped && lane_id() == 0) {
+        atomicCAS(&a.qctl[q].abort, kAbortNone, kAbortCap);
+        // a launch of one query is over: every wavefront, idle ones included, exits
+        if (a.nq == 1) atomicCAS(&a.ctl->abort, kAbortNone, kAbortCap);
+    }
     t.count = 0;
     return capped;
 }
@@ -761,12 +765,14 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
         while (items_left) {
             StreamCtl &sc = a.streams[sid];
             const unsigned long long it = lane0_atomic_add(&sc.next, 1ull);
-            if (it >= sc.items) {  // this stream ran dry: help the next one
+            // the stream's fields are fixed during the launch: read them as wave-uniform
+            if (it >= read_lane64(sc.items, 0)) {  // this stream ran dry: help the next one
                 if (++dry >= a.nstreams) items_left = false;
                 sid = sid + 1 == a.nstreams ? 0 : sid + 1;
                 continue;
             }
-            const int32_t q = find_query(a, P, cq, sc.plan0, sc.plan1, it);
+            const int32_t q = find_query(a, P, cq, __builtin_amdgcn_readfirstlane(sc.plan0),
+                                         __builtin_amdgcn_readfirstlane(sc.plan1), it);
             if (q != cq) {
                 tally_flush(a, P, cq, t);
                 cq = q;
@@ -959,16 +965,18 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
             }
             ++rounds;
             if (t.count >= P->flush || (rounds & 31u) == 0) {
-                if (count_flush(a, P, cq, t)) dropped = true;
+                (void)count_flush(a, P, cq, t);
                 if ((rounds & 31u) == 0) {
                     if (deadline | P->budget) {
                         const unsigned long long now = wall_clock64();
                         if (deadline && now > deadline) set_abort(ctl, kAbortTime);
-                        if (P->budget && now > qstart + P->budget && lane == 0)
+                        if (P->budget && now > qstart + P->budget && lane == 0) {
                             atomicCAS(&a.qctl[cq].abort, kAbortNone, kAbortTime);
+                            if (a.nq == 1) atomicCAS(&ctl->abort, kAbortNone, kAbortTime);
+                        }
                     }
                     if (load_abort(ctl) != kAbortNone) stop = true;
-                    else if (!dropped && load_word(&a.qctl[cq].abort) != kAbortNone) dropped = true;
+                    else if (a.nq > 1 && !dropped && load_word(&a.qctl[cq].abort) != kAbortNone) dropped = true;
                     if (stealing && !stop && !dropped && (rounds & 127u) == 0) {
                         int waiting = 0;
                         if (lane == 0) waiting = load_agent(&ctl->idle_count);
