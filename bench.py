@@ -223,8 +223,8 @@ def main() -> int:
         return 0
 
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(the method is single-GPU; see DESIGN.md for how it would shard)", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported: the engine "
+              "searches each query on a single GPU (multi-GPU sharding is a design, not built)", file=sys.stderr)
         return 2
 
     import paper_2604_10601_amd as gm

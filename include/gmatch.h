@@ -50,12 +50,17 @@ typedef struct gm_engine gm_engine;
 
 /* Engine options.  A zero-initialised struct selects every default. */
 typedef struct {
-    /* Initial task pool threshold tau (Sec. 4.3, "Initialization Phase"): the
-     * breadth-first expansion stops at the first level holding >= tau partial
-     * matches.  0 = default: 64 rows (one full batch) for every wavefront the
-     * search keeps resident, about 2.5e5 on MI355X (the paper's own setting is
-     * 1e6).  Negative = no expansion: the pool is the candidate set of the first
-     * query vertex (the BFS-disabled mode of Sec. 6.2). */
+    /* Initial task pool (Sec. 4.3, "Initialization Phase").
+     * 0 = default: a virtual pool at position 1.  The first query vertex's
+     * candidates each contribute their candidate slice for position 1, the
+     * slices are laid out as one task list by a prefix sum, and wavefronts claim
+     * 64 consecutive tasks at a time: every wavefront starts on a full batch with
+     * no breadth-first launch and no host round trip, and hub roots are split
+     * across wavefronts from the start.
+     * > 0 = the paper's scheme: breadth-first expansion up to the first level
+     * holding >= tau partial matches (the paper's own setting is 1e6).
+     * < 0 = no expansion: the pool is the candidate set of the first query vertex,
+     * 64 candidates per work item (the BFS-disabled mode of Sec. 6.2). */
     int64_t tau;
     /* Largest pool the expansion may build, in rows; 0 = default 64 * tau. */
     int64_t pool_row_limit;
@@ -92,7 +97,8 @@ typedef struct {
 typedef struct {
     uint64_t count;        /* min(#matches, cap) */
     int32_t outcome;       /* gm_outcome */
-    int32_t pool_depth;    /* matched positions per initial-pool row */
+    int32_t pool_depth;    /* matched positions per initial-pool row (1 for the virtual pool:
+                              its rows are the first vertex's candidates) */
     double search_ms;      /* wall time of the search on the device: from the first
                               launch to the result being back on the host */
     uint64_t pool_rows;    /* size of the initial task pool */

@@ -139,6 +139,11 @@ struct gm_engine {
     size_t qctl_cap = 0;
     std::vector<Plan> h_plans;     // host copies (kept until the uploads complete)
     std::vector<gm::QCtl> h_qctl;
+    uint32_t *d_vlen = nullptr;    // virtual level-1 pool: slice length, start and first task per root
+    uint32_t *d_vstart = nullptr;
+    uint32_t *d_voff = nullptr;
+    uint32_t *d_vtmp = nullptr;    // chunk totals of the prefix sum
+    size_t v_cap = 0;
     gm::StreamCtl *d_streams = nullptr;  // work-item streams of a launch
     size_t streams_cap = 0;
     std::vector<gm::StreamCtl> h_streams;
@@ -190,6 +195,30 @@ gm_status ensure_buffer(gm_engine *e, int32_t **buf, size_t *cap, size_t need_in
         }
     }
     *cap = want;
+    return GM_OK;
+}
+
+// Room for the virtual level-1 pool of up to R roots.
+gm_status ensure_level1(gm_engine *e, size_t R) {
+    if (R <= e->v_cap && e->d_voff) return GM_OK;
+    uint32_t **bufs[] = {&e->d_vlen, &e->d_vstart, &e->d_voff, &e->d_vtmp};
+    for (uint32_t **b : bufs) {
+        if (*b) hipFree(*b);
+        *b = nullptr;
+    }
+    e->v_cap = 0;
+    const size_t want = std::max<size_t>(R, 4096);
+    hipError_t h = hipSuccess;
+    for (int i = 0; i < 3 && h == hipSuccess; ++i) h = hipMalloc(reinterpret_cast<void **>(bufs[i]), want * 4);
+    if (h == hipSuccess) h = hipMalloc(reinterpret_cast<void **>(&e->d_vtmp), (want / 4096 + 2) * 4);
+    if (h != hipSuccess) {
+        for (uint32_t **b : bufs) {
+            if (*b) hipFree(*b);
+            *b = nullptr;
+        }
+        return e->fail(GM_ERR_NOMEM, "device allocation of the level-1 pool failed");
+    }
+    e->v_cap = want;
     return GM_OK;
 }
 
@@ -255,12 +284,7 @@ bool use_slim(const gm_engine *e, int32_t k) {
     return e->opt.stack_layout != 1;
 }
 
-// tau (Sec. 4.3): the option, or by default one full batch of 64 pool rows for
-// every wavefront the search launch keeps resident (about 2.5e5 on MI355X).
-int64_t option_tau(const gm_engine *e, int32_t k) {
-    if (e->opt.tau != 0) return e->opt.tau;
-    return 64LL * gm::search_waves(k, e->num_cu, e->opt.waves_per_cu, use_slim(e, k));
-}
+
 
 gm_status check_graph(gm_engine *e, int32_t n, const int64_t *row_ptr, const int32_t *col, bool symmetric) {
     if (row_ptr[0] != 0) return e->fail(GM_ERR_GRAPH, "row_ptr[0] must be 0");
@@ -407,6 +431,149 @@ bool query_finished(const Plan &p, const gm::QCtl &qc, const gm::StreamCtl &sc) 
     return qc.live == 0 && sc.next >= p.item_end;
 }
 
+// Candidates of the first query vertex as a share of the label buckets: the
+// vertices with its label and at least its degree, a prefix of that bucket.
+void root_share(const gm_engine *e, const Plan &p, unsigned long long *row0, unsigned long long *rows) {
+    *row0 = 0;
+    *rows = 0;
+    if (p.lab[0] == 255 || e->n == 0) return;
+    const int64_t b = e->lab_start[p.lab[0]], en = e->lab_start[p.lab[0] + 1];
+    const uint32_t need = static_cast<uint32_t>(p.qdeg[0]);
+    auto first = e->bylabel_deg.begin() + b;
+    auto it = std::partition_point(first, e->bylabel_deg.begin() + en, [need](uint32_t d) { return d >= need; });
+    *row0 = static_cast<unsigned long long>(b);
+    *rows = static_cast<unsigned long long>(it - first);
+}
+
+// One search with the virtual level-1 pool (the default): the roots are a
+// bucket prefix, one pass gives every root's candidate slice for position 1 and
+// a prefix sum lays all of them out as one task list, and the persistent kernel
+// claims 64 consecutive tasks per work item, so hub roots spread over wavefronts
+// from the first round on.  Everything is queued without a host round trip.
+gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, uint64_t cap, double time_limit_s,
+                      int32_t *rows, gm_result *out) {
+    const bool enumerate = rows != nullptr;
+    const auto t_start = std::chrono::steady_clock::now();
+    Plan p = base_plan;
+    unsigned long long row0 = 0, R = 0;
+    root_share(e, p, &row0, &R);
+    out->pool_depth = 1;
+    out->pool_rows = R;
+    out->outcome = GM_DONE;
+    if (R == 0 || q->k == 1) {
+        // no candidates, or a single query vertex: its candidates are the matches
+        out->count = cap && R >= cap ? cap : R;
+        out->outcome = cap && R >= cap ? GM_CAPPED : GM_DONE;
+        if (enumerate && out->count) {
+            HIP_TRY(e, hipMemcpyAsync(rows, e->d_bylabel + row0, out->count * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                      e->stream));
+            HIP_TRY(e, hipStreamSynchronize(e->stream));
+            out->rows = out->count;
+        }
+        std::chrono::duration<double, std::milli> ms = std::chrono::steady_clock::now() - t_start;
+        out->search_ms = ms.count();
+        return GM_OK;
+    }
+    if (R >= (1ull << 31)) return e->fail(GM_ERR_GRAPH, "more than 2^31 candidates for the first query vertex");
+    gm_status st = ensure_query_slots(e, 2);
+    if (!st) st = ensure_streams(e, 1);
+    if (!st) st = ensure_level1(e, R);
+    if (!st && enumerate) st = ensure_buffer(e, &e->d_rows, &e->rows_cap, static_cast<size_t>(cap) * q->k);
+    if (st) return st;
+
+    p.depth = 1;
+    p.cap = cap;
+    p.flush = flush_for_cap(e, cap);
+    p.row0 = row0;
+    p.rows = R;
+    p.item0 = 0;
+    p.item_end = 0;  // set on the device from the level-1 total
+    p.vmode = 1;
+    p.vrow0 = 0;
+    e->h_plans.assign(1, p);
+    e->h_streams.assign(1, gm::StreamCtl{});
+    e->h_streams[0].plan0 = 0;
+    e->h_streams[0].plan1 = 1;
+    HIP_TRY(e, hipMemsetAsync(e->d_ctl, 0, sizeof(Control), e->stream));
+    HIP_TRY(e, hipMemsetAsync(e->d_qctl, 0, 2 * sizeof(gm::QCtl), e->stream));
+    HIP_TRY(e, hipMemcpyAsync(e->d_plans, e->h_plans.data(), sizeof(Plan), hipMemcpyHostToDevice, e->stream));
+    HIP_TRY(e, hipMemcpyAsync(e->d_streams, e->h_streams.data(), sizeof(gm::StreamCtl), hipMemcpyHostToDevice,
+                              e->stream));
+    HIP_TRY(e, gm::launch_start_clock(e->d_ctl, e->stream));
+    // level-1 counters go to the second slot, so the first holds the search launch's own
+    const int32_t lab1 = e->loff_stride > 1 ? p.lab[1] : 0;
+    const bool slim = use_slim(e, q->k);
+    HIP_TRY(e, gm::launch_level1(e->d_bylabel + row0, static_cast<int32_t>(R), e->d_vinfo, e->d_loff, e->loff_stride,
+                                 lab1, slim || e->loff_stride > 1 ? 1 : 0, e->d_vlen, e->d_vstart, e->d_voff,
+                                 e->d_vtmp, e->d_qctl + 1, e->d_plans, e->d_streams, e->num_cu, e->stream));
+    SearchArgs a = graph_args(e);
+    a.nq = 1;
+    a.nstreams = 1;
+    a.levels = q->k;
+    a.pool = e->d_bylabel;
+    a.voff = e->d_voff;
+    a.vstart = e->d_vstart;
+    a.slim = slim ? 1 : 0;
+    a.budget = time_limit_s > 0
+                   ? std::max<unsigned long long>(
+                         1, static_cast<unsigned long long>(time_limit_s * 1000.0 * static_cast<double>(e->wall_khz)))
+                   : 0ull;
+    a.out = enumerate ? e->d_rows : nullptr;
+    a.out_cap = enumerate ? cap : 0;
+    st = attach_stealing(e, a);
+    if (!st) st = reset_stealing(e, a);
+    if (st) return st;
+    int grid_waves = 0;
+    float kernel_ms = 0.f;
+    HIP_TRY(e, hipEventRecord(e->ev0, e->stream));
+    HIP_TRY(e, gm::launch_search(a, enumerate, e->num_cu, e->opt.waves_per_cu, e->stream, &grid_waves));
+    HIP_TRY(e, hipEventRecord(e->ev1, e->stream));
+    gm::QCtl qc[2];
+    gm::StreamCtl sc{};
+    Control c{};
+    HIP_TRY(e, hipMemcpyAsync(qc, e->d_qctl, 2 * sizeof(gm::QCtl), hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(e, hipMemcpyAsync(&sc, e->d_streams, sizeof(gm::StreamCtl), hipMemcpyDeviceToHost, e->stream));
+    st = read_ctl(e, &c);
+    if (st) return st;
+    HIP_TRY(e, hipEventElapsedTime(&kernel_ms, e->ev0, e->ev1));
+
+    const gm::QCtl &k0 = qc[0], &l1 = qc[1];
+    if (cap && k0.count >= cap) {
+        out->count = cap;
+        out->outcome = GM_CAPPED;
+    } else {
+        out->count = k0.count;
+        const bool done = k0.live == 0 && sc.next >= sc.items && c.abort != gm::kAbortTime;
+        out->outcome = done ? GM_DONE : GM_TIMEOUT;
+    }
+    out->groups = k0.groups + l1.groups;
+    out->tasks = k0.tasks + l1.tasks;
+    out->lanes_active = k0.lanes_active;
+    out->lanes_issued = k0.lanes_issued;
+    out->probes = k0.probes;
+    out->steals = k0.steals;
+    out->kernel_ms = kernel_ms;
+    out->grid_waves = grid_waves;
+    out->kernel_tasks = k0.tasks;
+    out->kernel_probes = k0.probes;
+    out->kernel_groups = k0.groups;
+    out->scanned = k0.scanned + l1.scanned;
+    out->kernel_scanned = k0.scanned + l1.scanned;  // the search launch reads the level-1 candidates itself
+    out->kernel_lookups = k0.lookups;
+    if (enumerate) {
+        const uint64_t nrows = std::min<uint64_t>(out->count, std::min<uint64_t>(c.out_rows, cap));
+        if (nrows) {
+            HIP_TRY(e, hipMemcpyAsync(rows, e->d_rows, nrows * q->k * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                      e->stream));
+            HIP_TRY(e, hipStreamSynchronize(e->stream));
+        }
+        out->rows = nrows;
+    }
+    std::chrono::duration<double, std::milli> ms = std::chrono::steady_clock::now() - t_start;
+    out->search_ms = ms.count();
+    return GM_OK;
+}
+
 // One search (Alg. 2): root candidates, breadth-first pool to tau, then the
 // persistent depth-first kernel.  rows != null selects enumeration.
 gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_s, int32_t *rows,
@@ -426,6 +593,7 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
         out->outcome = GM_DONE;
         return GM_OK;
     }
+    if (e->opt.tau == 0) return run_virtual(e, q, base_plan, cap, time_limit_s, rows, out);
     st = ensure_query_slots(e, 1);
     if (!st) st = ensure_streams(e, 1);
     if (st) return st;
@@ -512,7 +680,7 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
     };
 
     // Initialisation phase (Sec. 4.3): breadth-first levels until >= tau rows.
-    const int64_t tau = option_tau(e, q->k);
+    const int64_t tau = e->opt.tau;  // > 0 here: breadth-first to tau; < 0: no expansion
     const int64_t row_limit = e->opt.pool_row_limit > 0 ? e->opt.pool_row_limit : 64 * std::max<int64_t>(tau, 1);
     bool aborted = false;
     while (tau > 0 && pool_rows > 0 && pool_rows < static_cast<uint64_t>(tau) && depth < q->k - 1) {
@@ -655,14 +823,7 @@ gm_status run_batch(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t cap,
         p.flush = flush_for_cap(e, cap);
         p.depth = 1;
         p.budget = budget_ticks;
-        if (!missing && e->n > 0) {
-            const int64_t b = e->lab_start[p.lab[0]], en = e->lab_start[p.lab[0] + 1];
-            const uint32_t need = static_cast<uint32_t>(p.qdeg[0]);
-            auto first = e->bylabel_deg.begin() + b;
-            auto it = std::partition_point(first, e->bylabel_deg.begin() + en, [need](uint32_t d) { return d >= need; });
-            p.row0 = static_cast<unsigned long long>(b);
-            p.rows = static_cast<unsigned long long>(it - first);
-        }
+        if (!missing) root_share(e, p, &p.row0, &p.rows);
         plans[i] = p;
         out[i].pool_depth = 1;
         out[i].pool_rows = p.rows;
@@ -926,6 +1087,9 @@ void gm_destroy(gm_engine *e) {
         if (e->d_rows) hipFree(e->d_rows);
         if (e->d_plans) hipFree(e->d_plans);
         if (e->d_qctl) hipFree(e->d_qctl);
+        if (e->d_streams) hipFree(e->d_streams);
+        for (uint32_t *b : {e->d_vlen, e->d_vstart, e->d_voff, e->d_vtmp})
+            if (b) hipFree(b);
         if (e->d_ctl) hipFree(e->d_ctl);
         if (e->d_mail) hipFree(e->d_mail);
         if (e->d_idle_bits) hipFree(e->d_idle_bits);

@@ -792,6 +792,68 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
                 }
                 qstart = read_lane64(old, 0);
             }
+            if (P->vmode) {
+                // virtual level-1 pool: 64 consecutive tasks of position 1.  Each lane finds
+                // its task's root (the last root whose first task index is <= the task),
+                // puts the root at level 0 and processes the candidate as a scatter round
+                // at level 1 would.
+                const unsigned long long tb = (it - P->item0) * kWave;
+                const unsigned long long left = P->tasks1 - tb;
+                const uint32_t ntask = left < kWave ? static_cast<uint32_t>(left) : kWave;
+                const int32_t *roots = a.pool + P->row0;
+                const uint32_t *off = a.voff + P->vrow0;
+                int32_t root = 0, v = -1;
+                VInfo rvi = make_uint2(0u, 0u);
+                if (lane < ntask) {
+                    const uint32_t task = static_cast<uint32_t>(tb) + lane;
+                    uint32_t lo = 0, hi = static_cast<uint32_t>(P->rows) - 1u;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi + 1u) >> 1;
+                        if (off[mid] <= task) lo = mid;
+                        else hi = mid - 1u;
+                    }
+                    root = roots[lo];
+                    if (!SLIM) rvi = a.vinfo[root];
+                    v = a.lcol[a.vstart[P->vrow0 + lo] + (task - off[lo])];
+                }
+                push_entry<SLIM>(S, 0, lane, root, rvi, lane);
+                S.cl[kWave + lane] = 0u;  // the candidate came from position 0's list
+                Round r1;
+                r1.ntask = ntask;
+                r1.owner = lane;
+                r1.v = v;
+                VInfo vi;
+                const bool ok = process<SLIM>(S, a, P, 1, r1, lane, vi, t.probes_run, t.lookups_run);
+                const uint64_t m = ballot(ok);
+                t.active += ntask;
+                t.issued += kWave;
+                if (P->k == 2) {
+                    if (MODE == kEnumerate && m) {
+                        const unsigned long long b0 = lane0_atomic_add(&ctl->out_rows, __popcll(m));
+                        const unsigned long long slot = b0 + popc_below(m);
+                        if (ok && slot < a.out_cap) {
+                            int32_t *row = a.out + slot * 2ull;
+                            row[P->phi[0]] = root;
+                            row[P->phi[1]] = v;
+                        }
+                    }
+                    t.count += __popcll(m);
+                    (void)count_flush(a, P, cq, t);
+                    continue;
+                }
+                if (!m) continue;
+                lane0_add(&a.qctl[cq].live, 1);
+                push_entry<SLIM>(S, 1, lane, v, vi, lane);
+                const Gen g = generate_tasks<SLIM>(S, a, P, 2, m, lane);
+                t.tasks += g.tasks;
+                t.scanned += g.scanned;
+                t.lookups += g.lookups;
+                t.groups += __popcll(m);
+                open_level(S, 2, lane);
+                base = 2;
+                have = true;
+                break;
+            }
             const int d = P->depth;
             const unsigned long long r0 = (it - P->item0) * kWave;
             const unsigned long long left = P->rows - r0;
@@ -977,7 +1039,7 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
                     }
                     if (load_abort(ctl) != kAbortNone) stop = true;
                     else if (a.nq > 1 && !dropped && load_word(&a.qctl[cq].abort) != kAbortNone) dropped = true;
-                    if (stealing && !stop && !dropped && (rounds & 127u) == 0) {
+                    if (stealing && !stop && !dropped) {
                         int waiting = 0;
                         if (lane == 0) waiting = load_agent(&ctl->idle_count);
                         if (static_cast<int>(read_lane(static_cast<uint32_t>(waiting), 0)) > 0)
@@ -999,6 +1061,114 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
         }
     }
     tally_flush(a, P, cq, t);
+}
+
+// Virtual level-1 pool, first pass: each root's candidate slice for position 1
+// (GenerateTask there: position 0 is position 1's only backward neighbour, so
+// C^L is the root's list, and its slice with position 1's label is scanned).
+__global__ __launch_bounds__(256) void level1_kernel(const int32_t *__restrict__ roots, int32_t R,
+                                                     const VInfo *__restrict__ vinfo,
+                                                     const uint32_t *__restrict__ loff, int32_t stride, int32_t lab1,
+                                                     int32_t count_lookups, uint32_t *__restrict__ lens,
+                                                     uint32_t *__restrict__ vstart, QCtl *qc) {
+    uint64_t tasks = 0, scanned = 0, groups = 0;
+    for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < R;
+         i += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int32_t v = roots[i];
+        const uint32_t *o = loff + static_cast<unsigned long long>(v) * stride + (stride > 1 ? lab1 : 0);
+        const uint32_t st = o[0], len = o[1] - o[0];
+        lens[i] = len;
+        vstart[i] = st;
+        tasks += vi_deg(vinfo[v]);
+        scanned += len;
+        ++groups;
+    }
+    tasks = wave_sum64(tasks);
+    scanned = wave_sum64(scanned);
+    groups = wave_sum64(groups);
+    if (lane_id() == 0 && groups) {
+        atomicAdd(&qc->tasks, static_cast<unsigned long long>(tasks));
+        atomicAdd(&qc->scanned, static_cast<unsigned long long>(scanned));
+        atomicAdd(&qc->groups, static_cast<unsigned long long>(groups));
+        if (count_lookups) atomicAdd(&qc->lookups, static_cast<unsigned long long>(groups));
+    }
+}
+
+// Exclusive prefix sum of up to 2^31 uint32 values in three passes: per-block
+// scans of kScanChunk values, a scan of the block totals, and the block offsets
+// added back.  (Totals stay below 2^32: they are sums of degrees of one graph.)
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 16;
+constexpr int kScanChunk = kScanThreads * kScanPer;
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *sh, uint32_t &total) {
+    const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+    const uint32_t incl = wave_incl_scan(x);
+    if (lane == kWave - 1) sh[w] = incl;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (uint32_t j = 0; j < blockDim.x / kWave; ++j) {
+        base += j < w ? sh[j] : 0u;
+        tot += sh[j];
+    }
+    __syncthreads();
+    total = tot;
+    return base + incl - x;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_chunks_kernel(const uint32_t *__restrict__ in, int32_t n,
+                                                                   uint32_t *__restrict__ out,
+                                                                   uint32_t *__restrict__ sums) {
+    __shared__ uint32_t sh[kScanThreads / kWave];
+    const long long b0 = static_cast<long long>(blockIdx.x) * kScanChunk + threadIdx.x * kScanPer;
+    uint32_t v[kScanPer];
+    uint32_t local = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        v[j] = b0 + j < n ? in[b0 + j] : 0u;
+        local += v[j];
+    }
+    uint32_t total = 0;
+    uint32_t run = block_excl_scan(local, sh, total);
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        if (b0 + j < n) out[b0 + j] = run;
+        run += v[j];
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// One block: exclusive scan of the nb chunk totals in place; the grand total
+// sizes the query's virtual pool (tasks1, its work items, the stream's items).
+__global__ __launch_bounds__(1024) void scan_sums_kernel(uint32_t *sums, int32_t nb, Plan *plan, StreamCtl *sc) {
+    __shared__ uint32_t sh[1024 / kWave];
+    const int32_t per = (nb + blockDim.x - 1) / blockDim.x;
+    const int32_t b = threadIdx.x * per;
+    uint32_t local = 0;
+    for (int32_t j = 0; j < per; ++j)
+        if (b + j < nb) local += sums[b + j];
+    uint32_t total = 0;
+    uint32_t run = block_excl_scan(local, sh, total);
+    for (int32_t j = 0; j < per; ++j) {
+        if (b + j < nb) {
+            const uint32_t x = sums[b + j];
+            sums[b + j] = run;
+            run += x;
+        }
+    }
+    if (threadIdx.x == 0) {
+        const unsigned long long items = (static_cast<unsigned long long>(total) + kWave - 1) / kWave;
+        plan->tasks1 = total;
+        plan->item_end = plan->item0 + items;
+        sc->items = plan->item_end;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_add_kernel(uint32_t *__restrict__ out, int32_t n,
+                                                                const uint32_t *__restrict__ sums) {
+    for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<long long>(gridDim.x) * blockDim.x)
+        out[i] += sums[i / kScanChunk];
 }
 
 __global__ void start_clock_kernel(Control *ctl) {
@@ -1109,6 +1279,23 @@ hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int wa
     }
     if (enumerate) return launch_persistent<kEnumerate, false>(a, num_cu, waves_per_cu, s, grid_waves_out);
     return launch_persistent<kCount, false>(a, num_cu, waves_per_cu, s, grid_waves_out);
+}
+
+hipError_t launch_level1(const int32_t *roots, int32_t R, const VInfo *vinfo, const uint32_t *loff, int32_t stride,
+                         int32_t lab1, int32_t count_lookups, uint32_t *lens, uint32_t *vstart, uint32_t *voff,
+                         uint32_t *tmp, QCtl *qc, Plan *plan, StreamCtl *sc, int num_cu, hipStream_t s) {
+    if (R < 1) return hipErrorInvalidValue;
+    long long blocks = (static_cast<long long>(R) + 255) / 256;
+    if (blocks > num_cu * 8LL) blocks = num_cu * 8LL;
+    hipLaunchKernelGGL(level1_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, roots, R, vinfo, loff,
+                       stride, lab1, count_lookups, lens, vstart, qc);
+    const int32_t nb = static_cast<int32_t>((static_cast<long long>(R) + kScanChunk - 1) / kScanChunk);
+    hipLaunchKernelGGL(scan_chunks_kernel, dim3(nb), dim3(kScanThreads), 0, s, lens, R, voff, tmp);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, tmp, nb, plan, sc);
+    long long ablocks = (static_cast<long long>(R) + 255) / 256;
+    if (ablocks > num_cu * 8LL) ablocks = num_cu * 8LL;
+    hipLaunchKernelGGL(scan_add_kernel, dim3(static_cast<unsigned>(ablocks)), dim3(kScanThreads), 0, s, voff, R, tmp);
+    return hipGetLastError();
 }
 
 hipError_t launch_start_clock(Control *ctl, hipStream_t s) {
