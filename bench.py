@@ -298,7 +298,8 @@ def main() -> int:
         "config": {"workload": w.name, "graph_vertices": w.graph.n, "graph_edges": w.graph.num_edges,
                    "queries": len(w.queries), "query_sizes": sorted({q.k for q in w.queries}),
                    "cap": cap, "time_limit_s": limit, "order": "RI heuristic",
-                   "tau": args.tau if args.tau else "64 rows per resident wavefront",
+                   "initial_pool": (f"breadth-first to tau={args.tau}" if args.tau > 0 else
+                                    "first-vertex candidates" if args.tau < 0 else "virtual level-1 pool"),
                    "work_stealing": not args.disable_stealing},
         "intersected_edges_per_s": tasks / wall,
         "scanned_candidates_per_s": sum(r.scanned for r in flat) / wall,
