@@ -71,7 +71,10 @@ def make_workload(name: str, num_queries: int, stride: int = 1):
     elif name == "small":
         w = wl.small_er()
     elif name == "large":
-        w = wl.large_rmat24()
+        t = time.time()
+        g = wl.rmat24_graph()
+        log(f"R-MAT scale 24 graph generated in {time.time() - t:.1f} s; extracting queries")
+        w = wl.large_rmat24(g=g)
     elif name == "batch":
         w = wl.batch_rmat20()
     else:

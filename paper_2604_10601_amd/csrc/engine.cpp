@@ -425,10 +425,34 @@ SearchArgs graph_args(const gm_engine *e) {
 
 unsigned long long items_of(unsigned long long rows) { return (rows + gm::kWave - 1) / gm::kWave; }
 
+// Two-phase pool: tasks of position 1 a root keeps in its first-phase item.
+constexpr uint32_t kHubCut = 64;
+
 // A query is finished when every work item of it was claimed (its stream's
 // counter passed them) and every unit of its work (item or donation) ran to its end.
 bool query_finished(const Plan &p, const gm::QCtl &qc, const gm::StreamCtl &sc) {
     return qc.live == 0 && sc.next >= p.item_end;
+}
+
+// Multiplier of the order in which a share of n roots is visited: near n times
+// the golden ratio's fraction and coprime to n, so consecutive work items mix
+// high- and low-degree roots (the bucket stores them by degree).  A capped
+// search that starts on the hubs alone can spend its time in their subtrees
+// (one 32-vertex query on the scale-24 graph: 5 s without reaching the cap,
+// 0.1 s with the roots in id order).
+unsigned long long root_order(unsigned long long n) {
+    if (n < 3) return 0;
+    unsigned long long m = static_cast<unsigned long long>(static_cast<double>(n) * 0.6180339887498949) | 1ull;
+    auto gcd = [](unsigned long long x, unsigned long long y) {
+        while (y) {
+            const unsigned long long t = x % y;
+            x = y;
+            y = t;
+        }
+        return x;
+    };
+    while (gcd(m, n) != 1) m += 2;
+    return m % n;
 }
 
 // Candidates of the first query vertex as a share of the label buckets: the
@@ -445,11 +469,15 @@ void root_share(const gm_engine *e, const Plan &p, unsigned long long *row0, uns
     *rows = static_cast<unsigned long long>(it - first);
 }
 
-// One search with the virtual level-1 pool (the default): the roots are a
-// bucket prefix, one pass gives every root's candidate slice for position 1 and
-// a prefix sum lays all of them out as one task list, and the persistent kernel
-// claims 64 consecutive tasks per work item, so hub roots spread over wavefronts
-// from the first round on.  Everything is queued without a host round trip.
+// One search with the two-phase pool (the default).  The roots are a bucket
+// prefix, visited in a mixed order.  First-phase items hold 64 roots each, every
+// root with at most its first kHubCut tasks of position 1, so every root is
+// sampled early and a hub holds up one wavefront, not all of them.  The rest of
+// the hubs' tasks form the second phase: one pass gives each root's remaining
+// slice, a prefix sum lays them out as one task list, and an item is 64
+// consecutive tasks of it, so a hub's work spreads over many wavefronts.
+// Wavefronts that find no first-phase item start on second-phase items at once.
+// Everything is queued without a host round trip.
 gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, uint64_t cap, double time_limit_s,
                       int32_t *rows, gm_result *out) {
     const bool enumerate = rows != nullptr;
@@ -489,7 +517,10 @@ gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, ui
     p.item0 = 0;
     p.item_end = 0;  // set on the device from the level-1 total
     p.vmode = 1;
+    p.hub_cut = kHubCut;
     p.vrow0 = 0;
+    p.perm_mul = root_order(R);
+    p.item_split = items_of(R);
     e->h_plans.assign(1, p);
     e->h_streams.assign(1, gm::StreamCtl{});
     e->h_streams[0].plan0 = 0;
@@ -500,12 +531,12 @@ gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, ui
     HIP_TRY(e, hipMemcpyAsync(e->d_streams, e->h_streams.data(), sizeof(gm::StreamCtl), hipMemcpyHostToDevice,
                               e->stream));
     HIP_TRY(e, gm::launch_start_clock(e->d_ctl, e->stream));
-    // level-1 counters go to the second slot, so the first holds the search launch's own
+    // the second phase's scanned candidates go to the second slot
     const int32_t lab1 = e->loff_stride > 1 ? p.lab[1] : 0;
     const bool slim = use_slim(e, q->k);
-    HIP_TRY(e, gm::launch_level1(e->d_bylabel + row0, static_cast<int32_t>(R), e->d_vinfo, e->d_loff, e->loff_stride,
-                                 lab1, slim || e->loff_stride > 1 ? 1 : 0, e->d_vlen, e->d_vstart, e->d_voff,
-                                 e->d_vtmp, e->d_qctl + 1, e->d_plans, e->d_streams, e->num_cu, e->stream));
+    HIP_TRY(e, gm::launch_level1(e->d_bylabel + row0, static_cast<int32_t>(R), p.perm_mul, p.hub_cut, e->d_loff,
+                                 e->loff_stride, lab1, e->d_vlen, e->d_vstart, e->d_voff, e->d_vtmp, e->d_qctl + 1,
+                                 e->d_plans, e->d_streams, e->num_cu, e->stream));
     SearchArgs a = graph_args(e);
     a.nq = 1;
     a.nstreams = 1;
@@ -824,6 +855,7 @@ gm_status run_batch(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t cap,
         p.depth = 1;
         p.budget = budget_ticks;
         if (!missing) root_share(e, p, &p.row0, &p.rows);
+        p.perm_mul = root_order(p.rows);
         plans[i] = p;
         out[i].pool_depth = 1;
         out[i].pool_rows = p.rows;

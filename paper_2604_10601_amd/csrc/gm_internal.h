@@ -38,14 +38,20 @@ struct Plan {
     unsigned long long rows;
     unsigned long long item0;
     unsigned long long item_end;
-    // virtual level-1 pool (vmode = 1): the rows are roots (depth 1) and a work
-    // item is 64 consecutive tasks of position 1, taken from the concatenation of
-    // the roots' candidate slices; root i's slice starts at lcol[vstart[vrow0 + i]]
-    // and its first task has index voff[vrow0 + i]; tasks1 tasks in all
+    // two-phase pool (vmode = 1): the rows are roots (depth 1).  Items item0 ..
+    // item_split - 1 hold 64 roots each, every root with at most its first hub_cut
+    // tasks of position 1; items from item_split on hold 64 consecutive tasks of
+    // the rest, taken from the concatenation of the roots' remaining slices: root
+    // i's remainder starts at lcol[vstart[vrow0 + i]] and its first task has index
+    // voff[vrow0 + i]; tasks1 such tasks in all
     int32_t vmode;
-    int32_t pad_v;
+    uint32_t hub_cut;
     unsigned long long vrow0;
     unsigned long long tasks1;
+    unsigned long long item_split;
+    // order of a depth-1 share: root r is pool row row0 + (r * perm_mul) mod rows
+    // (perm_mul coprime to rows; 0 = rows in stored order)
+    unsigned long long perm_mul;
 };
 
 // Per-query results of a launch.  The count (atomics from every wavefront on
@@ -164,14 +170,16 @@ hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int wa
                          int *grid_waves_out);
 // Writes the device wall clock into ctl->t0 (start of a search's time budget).
 hipError_t launch_start_clock(Control *ctl, hipStream_t s);
-// Virtual level-1 pool of one query: per root (roots[0 .. R)), the slice of its
-// list with label id lab1 (the whole list when stride == 1): start in lcol and
-// length; adds the level's groups, tasks, scanned candidates and lookups to qc.
-// Then voff = exclusive prefix sum of the lengths (tmp: R / 4096 + 1 words), and
-// plan->tasks1, plan->item_end and sc->items are set from the total.
-hipError_t launch_level1(const int32_t *roots, int32_t R, const VInfo *vinfo, const uint32_t *loff, int32_t stride,
-                         int32_t lab1, int32_t count_lookups, uint32_t *lens, uint32_t *vstart, uint32_t *voff,
-                         uint32_t *tmp, QCtl *qc, Plan *plan, StreamCtl *sc, int num_cu, hipStream_t s);
+// Second phase of a two-phase pool: per root (roots in the order given by
+// perm_mul), the part of its position-1 slice (label id lab1; the whole list
+// when stride == 1) beyond its first hub_cut tasks: start in lcol and length;
+// adds those candidates to qc->scanned.  Then voff = exclusive prefix sum of the
+// lengths (tmp: R / 4096 + 2 words), and plan->tasks1, plan->item_end and
+// sc->items are set from the total.
+hipError_t launch_level1(const int32_t *roots, int32_t R, unsigned long long perm_mul, uint32_t hub_cut,
+                         const uint32_t *loff, int32_t stride, int32_t lab1, uint32_t *lens, uint32_t *vstart,
+                         uint32_t *voff, uint32_t *tmp, QCtl *qc, Plan *plan, StreamCtl *sc, int num_cu,
+                         hipStream_t s);
 // Wavefronts a depth-first search launch for a query of `levels` positions keeps resident.
 int search_waves(int levels, int num_cu, int waves_per_cu, bool slim);
 hipError_t launch_steal_init(Mailbox *mail, unsigned long long *idle_bits, int32_t n, hipStream_t s);

@@ -52,6 +52,13 @@ __device__ __forceinline__ PlanPtr plan_at(const SearchArgs &a, int32_t q) {
     return reinterpret_cast<PlanPtr>(reinterpret_cast<uintptr_t>(a.plans)) + q;
 }
 
+// Stored position of root r of a depth-1 share of n rows visited in the order
+// r -> (r * mul) mod n (mul coprime to n); mul = 0 keeps the stored order.
+__host__ __device__ __forceinline__ unsigned long long permuted(unsigned long long r, unsigned long long mul,
+                                                                unsigned long long n) {
+    return mul ? (r * mul) % n : r;
+}
+
 // Number of set bits of m below this lane.
 __device__ __forceinline__ uint32_t popc_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
@@ -660,6 +667,13 @@ __host__ __device__ constexpr size_t wave_lds_bytes(int levels, bool expand, boo
     return stack_bytes(levels, slim) + (expand ? static_cast<size_t>(kStageRows) * kStageWidth * 4u : 0u);
 }
 
+// First phase of a two-phase pool: a root's position-1 task group keeps only
+// its first hub_cut tasks (the second phase holds the rest).
+__device__ __forceinline__ void first_phase_cut(WaveStack &S, PlanPtr P, uint32_t lane) {
+    const uint32_t cl = S.cl[kWave + lane];
+    if ((cl >> 8) > P->hub_cut) S.cl[kWave + lane] = (P->hub_cut << 8) | (cl & 0xffu);
+}
+
 // Query that item t of a stream (queries p0 .. p1 - 1) belongs to: the current
 // one when t is in its range, else a bisection of the plans' first items.
 __device__ __forceinline__ int32_t find_query(const SearchArgs &a, PlanPtr P, int32_t cq, int32_t p0, int32_t p1,
@@ -792,12 +806,12 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
                 }
                 qstart = read_lane64(old, 0);
             }
-            if (P->vmode) {
-                // virtual level-1 pool: 64 consecutive tasks of position 1.  Each lane finds
-                // its task's root (the last root whose first task index is <= the task),
-                // puts the root at level 0 and processes the candidate as a scatter round
-                // at level 1 would.
-                const unsigned long long tb = (it - P->item0) * kWave;
+            if (P->vmode && it >= P->item_split) {
+                // second phase of the pool: 64 consecutive tasks of position 1.  Each lane
+                // finds its task's root (the last root whose first task index is <= the
+                // task), puts the root at level 0 and processes the candidate as a scatter
+                // round at level 1 would.
+                const unsigned long long tb = (it - P->item_split) * kWave;
                 const unsigned long long left = P->tasks1 - tb;
                 const uint32_t ntask = left < kWave ? static_cast<uint32_t>(left) : kWave;
                 const int32_t *roots = a.pool + P->row0;
@@ -812,7 +826,7 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
                         if (off[mid] <= task) lo = mid;
                         else hi = mid - 1u;
                     }
-                    root = roots[lo];
+                    root = roots[permuted(lo, P->perm_mul, P->rows)];
                     if (!SLIM) rvi = a.vinfo[root];
                     v = a.lcol[a.vstart[P->vrow0 + lo] + (task - off[lo])];
                 }
@@ -859,7 +873,8 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
             const unsigned long long left = P->rows - r0;
             const uint32_t nrows = left < kWave ? static_cast<uint32_t>(left) : kWave;
             const bool mine = lane < nrows;
-            const int32_t *src = a.pool + P->row0 + (r0 + lane) * static_cast<unsigned long long>(d);
+            const int32_t *src = a.pool + P->row0 + permuted(r0 + lane, P->perm_mul, P->rows) *
+                                                        static_cast<unsigned long long>(d);
             for (int i = 0; i < d; ++i) {
                 int32_t v = 0;
                 VInfo vi = make_uint2(0u, 0u);
@@ -876,7 +891,11 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
                 continue;
             }
             lane0_add(&a.qctl[cq].live, 1);
-            const Gen g = generate_tasks<SLIM>(S, a, P, d, F0, lane);
+            Gen g = generate_tasks<SLIM>(S, a, P, d, F0, lane);
+            if (P->vmode) {  // first phase: each root's first hub_cut tasks only
+                first_phase_cut(S, P, lane);
+                g.scanned = g.scanned < P->hub_cut ? g.scanned : P->hub_cut;
+            }
             t.tasks += g.tasks;
             t.scanned += g.scanned;
             t.lookups += g.lookups;
@@ -947,6 +966,8 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
                 push_entry<SLIM>(S, i, lane, v, vi, lane);
             }
             generate_tasks<SLIM>(S, a, P, L, lanes, lane);  // already counted by the donor
+            // position 1 is donated only by first-phase items of a two-phase pool: keep their cut
+            if (P->vmode && L == 1) first_phase_cut(S, P, lane);
             if (lane == 0) {
                 S.cur_i[L] = static_cast<uint32_t>(load_agent(&mb.pi));
                 S.cur_j[L] = static_cast<uint32_t>(load_agent(&mb.pj));
@@ -1063,35 +1084,28 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
     tally_flush(a, P, cq, t);
 }
 
-// Virtual level-1 pool, first pass: each root's candidate slice for position 1
-// (GenerateTask there: position 0 is position 1's only backward neighbour, so
-// C^L is the root's list, and its slice with position 1's label is scanned).
+// Second phase of a two-phase pool, first pass: each root's position-1 slice
+// beyond its first hub_cut tasks (position 0 is position 1's only backward
+// neighbour, so C^L is the root's list, and its slice with position 1's label is
+// scanned).  The roots' groups and tasks are counted by the first phase.
 __global__ __launch_bounds__(256) void level1_kernel(const int32_t *__restrict__ roots, int32_t R,
-                                                     const VInfo *__restrict__ vinfo,
+                                                     unsigned long long perm_mul, uint32_t hub_cut,
                                                      const uint32_t *__restrict__ loff, int32_t stride, int32_t lab1,
-                                                     int32_t count_lookups, uint32_t *__restrict__ lens,
-                                                     uint32_t *__restrict__ vstart, QCtl *qc) {
-    uint64_t tasks = 0, scanned = 0, groups = 0;
+                                                     uint32_t *__restrict__ lens, uint32_t *__restrict__ vstart,
+                                                     QCtl *qc) {
+    uint64_t scanned = 0;
     for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < R;
          i += static_cast<long long>(gridDim.x) * blockDim.x) {
-        const int32_t v = roots[i];
+        const int32_t v = roots[permuted(static_cast<unsigned long long>(i), perm_mul, static_cast<unsigned long long>(R))];
         const uint32_t *o = loff + static_cast<unsigned long long>(v) * stride + (stride > 1 ? lab1 : 0);
         const uint32_t st = o[0], len = o[1] - o[0];
-        lens[i] = len;
-        vstart[i] = st;
-        tasks += vi_deg(vinfo[v]);
-        scanned += len;
-        ++groups;
+        const uint32_t rest = len > hub_cut ? len - hub_cut : 0u;
+        lens[i] = rest;
+        vstart[i] = st + (len > hub_cut ? hub_cut : len);
+        scanned += rest;
     }
-    tasks = wave_sum64(tasks);
     scanned = wave_sum64(scanned);
-    groups = wave_sum64(groups);
-    if (lane_id() == 0 && groups) {
-        atomicAdd(&qc->tasks, static_cast<unsigned long long>(tasks));
-        atomicAdd(&qc->scanned, static_cast<unsigned long long>(scanned));
-        atomicAdd(&qc->groups, static_cast<unsigned long long>(groups));
-        if (count_lookups) atomicAdd(&qc->lookups, static_cast<unsigned long long>(groups));
-    }
+    if (lane_id() == 0 && scanned) atomicAdd(&qc->scanned, static_cast<unsigned long long>(scanned));
 }
 
 // Exclusive prefix sum of up to 2^31 uint32 values in three passes: per-block
@@ -1159,7 +1173,7 @@ __global__ __launch_bounds__(1024) void scan_sums_kernel(uint32_t *sums, int32_t
     if (threadIdx.x == 0) {
         const unsigned long long items = (static_cast<unsigned long long>(total) + kWave - 1) / kWave;
         plan->tasks1 = total;
-        plan->item_end = plan->item0 + items;
+        plan->item_end = plan->item_split + items;
         sc->items = plan->item_end;
     }
 }
@@ -1281,14 +1295,15 @@ hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int wa
     return launch_persistent<kCount, false>(a, num_cu, waves_per_cu, s, grid_waves_out);
 }
 
-hipError_t launch_level1(const int32_t *roots, int32_t R, const VInfo *vinfo, const uint32_t *loff, int32_t stride,
-                         int32_t lab1, int32_t count_lookups, uint32_t *lens, uint32_t *vstart, uint32_t *voff,
-                         uint32_t *tmp, QCtl *qc, Plan *plan, StreamCtl *sc, int num_cu, hipStream_t s) {
+hipError_t launch_level1(const int32_t *roots, int32_t R, unsigned long long perm_mul, uint32_t hub_cut,
+                         const uint32_t *loff, int32_t stride, int32_t lab1, uint32_t *lens, uint32_t *vstart,
+                         uint32_t *voff, uint32_t *tmp, QCtl *qc, Plan *plan, StreamCtl *sc, int num_cu,
+                         hipStream_t s) {
     if (R < 1) return hipErrorInvalidValue;
     long long blocks = (static_cast<long long>(R) + 255) / 256;
     if (blocks > num_cu * 8LL) blocks = num_cu * 8LL;
-    hipLaunchKernelGGL(level1_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, roots, R, vinfo, loff,
-                       stride, lab1, count_lookups, lens, vstart, qc);
+    hipLaunchKernelGGL(level1_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, roots, R, perm_mul,
+                       hub_cut, loff, stride, lab1, lens, vstart, qc);
     const int32_t nb = static_cast<int32_t>((static_cast<long long>(R) + kScanChunk - 1) / kScanChunk);
     hipLaunchKernelGGL(scan_chunks_kernel, dim3(nb), dim3(kScanThreads), 0, s, lens, R, voff, tmp);
     hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, tmp, nb, plan, sc);

@@ -286,9 +286,9 @@ def rmat24_graph() -> Graph:
     return Graph(row_ptr, col, zipf_labels(1 << 24, 8, 1.2, seed=25))
 
 
-def large_rmat24(per_class: int = 25) -> Workload:
+def large_rmat24(per_class: int = 25, g: Optional[Graph] = None) -> Workload:
     """R-MAT scale 24 with 12/16/24/32-vertex queries, cap 1e9, 60 s per query."""
-    g = rmat24_graph()
+    g = rmat24_graph() if g is None else g
     qs = extract_queries(g, [12, 16, 24, 32], per_class, per_class, seed=26)
     return Workload("rmat24_ef16_zipf8_q12-32", g, qs, cap=1_000_000_000, time_limit_s=60.0)
 

@@ -116,6 +116,27 @@ def test_cliques_closed_form(engine, n, k):
         assert_same(r, o)
 
 
+@pytest.mark.parametrize("opts", [dict(), dict(steal_threshold=2), dict(disable_stealing=True),
+                                  dict(stack_layout=1, steal_threshold=2)])
+def test_first_vertex_lists_around_the_two_phase_cut(opts):
+    """Roots with 63..130 candidates at position 1: the first phase keeps 64
+    tasks per root and the second phase the rest, also when position 1 is
+    donated (steal threshold 2)."""
+    with gm.Engine(device=0, **opts) as e:
+        for n in (64, 65, 66, 100, 131):
+            g = S.complete(n)
+            e.load(g)
+            for k in (2, 3, 4):
+                for q in (S.clique_q(k), S.path_q(k)):
+                    _say(f"two-phase cut n={n} k={k} m={q.m} {opts}")
+                    qid = e.add(q)
+                    r = e.count(qid)
+                    assert r.count == math.perm(n, k), (n, k)
+                    groups = sum(math.perm(n, i) for i in range(1, k))
+                    assert (r.groups, r.tasks) == (groups, (n - 1) * groups), (n, k)
+                    e.free_query(qid)
+
+
 def test_grid_closed_forms(engine):
     a, b = 40, 33
     g = S.grid(a, b)
