@@ -193,6 +193,7 @@ def main() -> int:
     ap.add_argument("--disable-stealing", action="store_true")
     ap.add_argument("--stack-layout", type=int, default=0, help="0 auto, 1 full, 2 slim")
     ap.add_argument("--steal-threshold", type=int, default=0)
+    ap.add_argument("--hub-cut", type=int, default=0, help="first-phase tasks per root (0 = default 16)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB device-to-device (counter calibration)")
     ap.add_argument("--summarize-stats", metavar="DIR", help="print the kernel table of a rocprofv3 --stats run")
@@ -243,7 +244,7 @@ def main() -> int:
         f"({time.time() - t:.1f} s to generate)")
     e = gm.Engine(device=0, tau=args.tau, waves_per_cu=args.waves_per_cu,
                   disable_stealing=args.disable_stealing, steal_threshold=args.steal_threshold,
-                  stack_layout=args.stack_layout)
+                  stack_layout=args.stack_layout, pool_hub_cut=args.hub_cut)
     e.load(w.graph)
     qids = [e.add(q) for q in w.queries]
     phis = [e.get_order(qid) for qid in qids]
@@ -302,7 +303,7 @@ def main() -> int:
                    "queries": len(w.queries), "query_sizes": sorted({q.k for q in w.queries}),
                    "cap": cap, "time_limit_s": limit, "order": "RI heuristic",
                    "initial_pool": (f"breadth-first to tau={args.tau}" if args.tau > 0 else
-                                    "first-vertex candidates" if args.tau < 0 else "virtual level-1 pool"),
+                                    "first-vertex candidates" if args.tau < 0 else "two-phase pool"),
                    "work_stealing": not args.disable_stealing},
         "intersected_edges_per_s": tasks / wall,
         "scanned_candidates_per_s": sum(r.scanned for r in flat) / wall,

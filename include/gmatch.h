@@ -51,12 +51,14 @@ typedef struct gm_engine gm_engine;
 /* Engine options.  A zero-initialised struct selects every default. */
 typedef struct {
     /* Initial task pool (Sec. 4.3, "Initialization Phase").
-     * 0 = default: a virtual pool at position 1.  The first query vertex's
-     * candidates each contribute their candidate slice for position 1, the
-     * slices are laid out as one task list by a prefix sum, and wavefronts claim
-     * 64 consecutive tasks at a time: every wavefront starts on a full batch with
-     * no breadth-first launch and no host round trip, and hub roots are split
-     * across wavefronts from the start.
+     * 0 = default: a two-phase pool at position 1, with no breadth-first launch
+     * and no host round trip.  First-phase work items hold 64 candidates of the
+     * first query vertex each, every one with at most pool_hub_cut of its tasks
+     * at position 1, so each candidate is sampled early and a hub holds up one
+     * wavefront only.  The rest of the hubs' tasks are laid out as one list by a
+     * prefix sum; second-phase items are 64 consecutive tasks of it, so a hub's
+     * work spreads over many wavefronts, and wavefronts with no first-phase item
+     * start on them at once.
      * > 0 = the paper's scheme: breadth-first expansion up to the first level
      * holding >= tau partial matches (the paper's own setting is 1e6).
      * < 0 = no expansion: the pool is the candidate set of the first query vertex,
@@ -90,7 +92,11 @@ typedef struct {
      * once.  Every wavefront serves its home stream's queries in order and
      * helps the next stream once its own runs dry.  0 = default 64. */
     int32_t batch_streams;
-    int32_t reserved[4];
+    /* Default pool (tau = 0): position-1 tasks a first-vertex candidate keeps
+     * in its first-phase work item; the rest of a hub's tasks go to the second
+     * phase.  0 = default 16. */
+    int32_t pool_hub_cut;
+    int32_t reserved[3];
 } gm_options;
 
 /* Result of one count or enumerate call. */

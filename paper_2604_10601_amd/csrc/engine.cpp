@@ -425,8 +425,8 @@ SearchArgs graph_args(const gm_engine *e) {
 
 unsigned long long items_of(unsigned long long rows) { return (rows + gm::kWave - 1) / gm::kWave; }
 
-// Two-phase pool: tasks of position 1 a root keeps in its first-phase item.
-constexpr uint32_t kHubCut = 64;
+// Two-phase pool: tasks of position 1 a root keeps in its first-phase item (default).
+constexpr uint32_t kHubCut = 16;
 
 // A query is finished when every work item of it was claimed (its stream's
 // counter passed them) and every unit of its work (item or donation) ran to its end.
@@ -517,7 +517,7 @@ gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, ui
     p.item0 = 0;
     p.item_end = 0;  // set on the device from the level-1 total
     p.vmode = 1;
-    p.hub_cut = kHubCut;
+    p.hub_cut = e->opt.pool_hub_cut > 0 ? static_cast<uint32_t>(e->opt.pool_hub_cut) : kHubCut;
     p.vrow0 = 0;
     p.perm_mul = root_order(R);
     p.item_split = items_of(R);
@@ -1070,7 +1070,8 @@ gm_status gm_create(int32_t device, const gm_options *opt, gm_engine **out) {
     gm_options o{};
     if (opt) o = *opt;
     if (o.stack_layout < 0 || o.stack_layout > 2 || o.steal_threshold < 0 || o.waves_per_cu < 0 ||
-        o.pool_row_limit < 0 || o.batch_single_launch < 0 || o.batch_single_launch > 1 || o.batch_streams < 0) {
+        o.pool_row_limit < 0 || o.batch_single_launch < 0 || o.batch_single_launch > 1 || o.batch_streams < 0 ||
+        o.pool_hub_cut < 0) {
         g_create_error = "option out of range";
         return GM_ERR_ARG;
     }
