@@ -75,7 +75,7 @@ def make_workload(name: str, num_queries: int, stride: int = 1):
         g = wl.rmat24_graph()
         log(f"R-MAT scale 24 graph generated in {time.time() - t:.1f} s; extracting queries")
         w = wl.large_rmat24(g=g)
-    elif name == "batch":
+    elif name in ("batch", "serve"):
         w = wl.batch_rmat20()
     else:
         raise SystemExit(f"unknown workload {name}")
@@ -176,8 +176,13 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="medium", choices=["medium", "small", "large", "batch"],
-                    help="batch = 10,000 mixed-size queries in shared launches (autotuned)")
+    ap.add_argument("--workload", default="medium", choices=["medium", "small", "large", "batch", "serve"],
+                    help="batch = 10,000 mixed-size queries in shared launches (autotuned); "
+                         "serve = the same queries as a Poisson request stream through the server")
+    ap.add_argument("--load", type=float, default=0.7,
+                    help="serve: offered rate as a fraction of the measured batched throughput")
+    ap.add_argument("--slots", type=int, default=0, help="serve: concurrent launches (0 = default)")
+    ap.add_argument("--max-batch", type=int, default=0, help="serve: requests per launch (0 = default)")
     ap.add_argument("--no-tune", action="store_true", help="batch workload: keep the default launch settings")
     ap.add_argument("--alone-sample", type=int, default=10,
                     help="batch workload: time every N-th query alone as the one-at-a-time reference")
@@ -235,6 +240,8 @@ def main() -> int:
 
     if args.workload == "batch":
         return bench_batch(args, gm)
+    if args.workload == "serve":
+        return bench_serve(args, gm)
 
     t = time.time()
     w = make_workload(args.workload, args.queries, args.query_stride)
@@ -425,6 +432,98 @@ def bench_batch(args, gm) -> int:
                      "kernel": "search_kernel (persistent depth-first search, shared by the batch)",
                      "launches": launches, "avg_launch_ms": kernel_s * 1000.0 / max(1, launches),
                      "algorithmic_bytes_per_launch": b_alg / max(1, launches)},
+    }
+    e.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_serve(args, gm) -> int:
+    """Continuous batching: the batched workload's queries as a Poisson request
+    stream at a fixed rate (a fraction of the measured batched throughput)
+    through gm_serve_*, with per-request latency.  Reference: the same arrivals
+    served one query at a time by gm_count in a FIFO queue, replayed with every
+    query's measured gm_count time."""
+    t = time.time()
+    w = make_workload("serve", args.queries, args.query_stride)
+    if args.time_limit >= 0:
+        w.time_limit_s = args.time_limit
+    log(f"workload {w.name}: n={w.graph.n} |E|={w.graph.num_edges} queries={len(w.queries)} "
+        f"({time.time() - t:.1f} s to generate)")
+    e = gm.Engine(device=0)
+    e.load(w.graph)
+    qids = [e.add(q) for q in w.queries]
+    cap, limit = w.cap, w.time_limit_s
+    tuning = None if args.no_tune else e.tune_batch(qids[::20], cap=cap, time_limit_s=limit).as_dict()
+    e.count_batch(qids, cap=cap, time_limit_s=limit)
+    t0 = time.perf_counter()
+    bres, _ = e.count_batch(qids, cap=cap, time_limit_s=limit)
+    batch_qps = len(qids) / (time.perf_counter() - t0)
+    rate = args.load * batch_qps
+    log(f"batched throughput {batch_qps:.0f} queries/s; offered load {rate:.0f} requests/s; tuning {tuning}")
+    # one query at a time: every query's gm_count time (the service time of a FIFO server)
+    t0 = time.perf_counter()
+    alone = [e.count(q, cap=cap, time_limit_s=limit) for q in qids]
+    alone_wall = time.perf_counter() - t0
+    service = np.array([a.search_ms for a in alone]) / 1000.0
+    rng = np.random.default_rng(4242)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(qids)))
+    fifo_done = np.empty_like(arrivals)
+    free_at = 0.0
+    for i, (a, sv) in enumerate(zip(arrivals, service)):
+        free_at = max(a, free_at) + sv
+        fifo_done[i] = free_at
+    fifo_lat = (fifo_done - arrivals) * 1000.0
+    # the stream through the server
+    srv = e.serve(slots=args.slots, max_batch=args.max_batch)
+    results = {}
+    tickets = {}
+    start = time.perf_counter()
+    for i, qid in enumerate(qids):
+        while time.perf_counter() - start < arrivals[i]:
+            for r in srv.poll():
+                results[r.ticket] = r
+        tickets[srv.submit(qid, cap=cap, time_limit_s=limit)] = i
+    while len(results) < len(tickets):
+        for r in srv.poll(wait_s=0.01):
+            results[r.ticket] = r
+    wall = time.perf_counter() - start
+    srv.close()
+    lat = np.array([r.latency_ms for r in results.values()])
+    served = [None] * len(qids)
+    for tk, i in tickets.items():
+        served[i] = results[tk].result
+    same = all((a.count, a.outcome) == (b.count, b.outcome) for a, b in zip(alone, served)
+               if a.outcome != gm.GM_TIMEOUT and b.outcome != gm.GM_TIMEOUT)
+    embeddings = sum(r.count for r in served)
+    slots_used = sorted({r.slot for r in results.values()})
+    out = {
+        "metric": "embeddings/s",
+        "value": embeddings / wall,
+        "unit": "embeddings/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": wall * 1000.0,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "graph_vertices": w.graph.n, "graph_edges": w.graph.num_edges,
+                   "queries": len(qids), "cap": cap, "time_limit_s": limit, "order": "RI heuristic",
+                   "launch": "gm_serve (continuous batching)", "arrivals": "Poisson, seed 4242",
+                   "offered_requests_per_s": rate, "load_vs_batched": args.load},
+        "serving": {"requests_per_s": len(qids) / wall,
+                    "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                                   "mean": float(lat.mean())},
+                    "slots_used": slots_used, "same_counts_as_alone": same},
+        "one_at_a_time": {"requests_per_s_capacity": len(qids) / alone_wall,
+                          "fifo_latency_ms": {"p50": float(np.percentile(fifo_lat, 50)),
+                                              "p99": float(np.percentile(fifo_lat, 99))},
+                          "note": "same arrivals replayed through a one-query FIFO with each query's gm_count time"},
+        "batched_queries_per_s": batch_qps,
+        "tuning": tuning,
     }
     e.close()
     print(json.dumps(out), flush=True)

@@ -238,6 +238,70 @@ gm_status gm_tune_batch(gm_engine *engine, int32_t nq, const int32_t *qids, uint
 /* Copy the engine's current options (after gm_tune_batch, its choices). */
 gm_status gm_get_options(const gm_engine *engine, gm_options *out);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching over a resident graph.
+ *
+ * A server owns `slots` launch contexts (a HIP stream each, with its own
+ * control block, plans, result blocks and stealing mailboxes) and a native
+ * worker thread.  gm_serve_submit only queues a request (the query's plan is
+ * built at once, so the query may be freed afterwards).  Whenever a slot is
+ * free, the worker admits up to max_batch queued requests, oldest first, into
+ * one persistent launch on that slot (the batched launch of gm_count_batch,
+ * every query with its own cap and time limit); launches of different slots
+ * run on the GPU at the same time, each with its share of the wavefronts, so
+ * requests that arrive while others run are admitted as soon as a slot frees
+ * up and their work overlaps with the work in flight.  Admission is bounded by
+ * slot memory: each slot holds at most max_batch plans and result blocks, and
+ * its wavefronts' stacks are sized for its largest query.  Results come back
+ * through gm_serve_poll with their submit, start and completion times.
+ * Each result equals what gm_count gives for the query with the same cap and
+ * time limit (exact when it finishes; with GM_TIMEOUT a lower bound).
+ * While a server is open, gm_load_graph and gm_tune_batch on its engine return
+ * GM_ERR_STATE; other engine calls may run alongside it.  Close every server
+ * before gm_destroy of its engine.
+ * ------------------------------------------------------------------------ */
+typedef struct gm_server gm_server;
+
+typedef struct {
+    int32_t slots;          /* concurrent launches; 0 = default 2 */
+    int32_t max_batch;      /* requests admitted into one launch; 0 = default 256 */
+    int32_t waves_per_cu;   /* wavefronts per CU of each launch; 0 = an equal share of what fits */
+    int32_t batch_streams;  /* work-item streams per launch (queries in flight); 0 = the engine's */
+    int64_t max_pending;    /* queued requests beyond which submit returns GM_ERR_BUFFER; 0 = no limit */
+    int32_t reserved[6];
+} gm_serve_options;
+
+typedef struct {
+    uint64_t ticket;        /* as returned by gm_serve_submit */
+    int32_t qid;
+    int32_t slot;           /* slot whose launch ran it */
+    double submit_ms;       /* times on the server's clock, ms since gm_serve_open */
+    double start_ms;        /* launch of its batch queued */
+    double done_ms;         /* its batch's results read back */
+    gm_result result;
+} gm_serve_result;
+
+/* Start a server on an engine with a loaded graph.  opt may be NULL. */
+gm_status gm_serve_open(gm_engine *engine, const gm_serve_options *opt, gm_server **out);
+
+/* Queue a count of query qid with its cap (0 = none) and time limit (<= 0 =
+ * none; counted from the query's first work item on the device).  *ticket
+ * identifies its result. */
+gm_status gm_serve_submit(gm_server *server, int32_t qid, uint64_t cap, double time_limit_s, uint64_t *ticket);
+
+/* Move up to max_results finished results into out[], oldest first, waiting
+ * up to wait_s seconds for at least one if none is ready (0 = do not wait).
+ * *n_out receives the number written. */
+gm_status gm_serve_poll(gm_server *server, gm_serve_result *out, int32_t max_results, double wait_s,
+                        int32_t *n_out);
+
+/* Numbers of requests queued, running and finished-but-not-polled. */
+gm_status gm_serve_stats(gm_server *server, int64_t *pending, int64_t *running, int64_t *ready);
+
+/* Finish every queued and running request, stop the worker and free the
+ * server; results not yet polled are dropped.  NULL is ignored. */
+gm_status gm_serve_close(gm_server *server);
+
 /* Forget a query; its id is not reused. */
 gm_status gm_free_query(gm_engine *engine, int32_t qid);
 

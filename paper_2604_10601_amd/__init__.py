@@ -10,7 +10,7 @@ from __future__ import annotations
 import ctypes
 import dataclasses
 import os
-from typing import Optional, Sequence
+from typing import List, Optional, Sequence
 
 import numpy as np
 
@@ -23,7 +23,8 @@ GM_DONE, GM_CAPPED, GM_TIMEOUT = 0, 1, 2
 
 ABI_FUNCTIONS = ("gm_create", "gm_destroy", "gm_load_graph", "gm_load_query", "gm_set_order",
                  "gm_get_order", "gm_count", "gm_enumerate", "gm_count_batch", "gm_tune_batch",
-                 "gm_get_options", "gm_free_query", "gm_last_error")
+                 "gm_get_options", "gm_serve_open", "gm_serve_submit", "gm_serve_poll", "gm_serve_stats",
+                 "gm_serve_close", "gm_free_query", "gm_last_error")
 
 
 class GmError(RuntimeError):
@@ -111,6 +112,17 @@ class _CResult(ctypes.Structure):
     ]
 
 
+class ServeOptions(ctypes.Structure):
+    _fields_ = [
+        ("slots", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+        ("waves_per_cu", ctypes.c_int32),
+        ("batch_streams", ctypes.c_int32),
+        ("max_pending", ctypes.c_int64),
+        ("reserved", ctypes.c_int32 * 6),
+    ]
+
+
 @dataclasses.dataclass
 class Result:
     count: int
@@ -140,6 +152,33 @@ class Result:
         return 1.0 - self.lanes_active / self.lanes_issued if self.lanes_issued else 0.0
 
 
+class _CServeResult(ctypes.Structure):
+    _fields_ = [
+        ("ticket", ctypes.c_uint64),
+        ("qid", ctypes.c_int32),
+        ("slot", ctypes.c_int32),
+        ("submit_ms", ctypes.c_double),
+        ("start_ms", ctypes.c_double),
+        ("done_ms", ctypes.c_double),
+        ("result", _CResult),
+    ]
+
+
+@dataclasses.dataclass
+class ServeResult:
+    ticket: int
+    qid: int
+    slot: int
+    submit_ms: float
+    start_ms: float
+    done_ms: float
+    result: "Result"
+
+    @property
+    def latency_ms(self) -> float:
+        return self.done_ms - self.submit_ms
+
+
 _lib = None
 
 
@@ -164,11 +203,18 @@ def load_library():
     lib.gm_count_batch.argtypes = [p, i32, p, u64, dbl, p, ctypes.POINTER(BatchInfo)]
     lib.gm_tune_batch.argtypes = [p, i32, p, u64, dbl, ctypes.POINTER(Tuning)]
     lib.gm_get_options.argtypes = [p, ctypes.POINTER(Options)]
+    lib.gm_serve_open.argtypes = [p, ctypes.POINTER(ServeOptions), ctypes.POINTER(p)]
+    lib.gm_serve_submit.argtypes = [p, i32, u64, dbl, ctypes.POINTER(u64)]
+    lib.gm_serve_poll.argtypes = [p, p, i32, dbl, ctypes.POINTER(i32)]
+    lib.gm_serve_stats.argtypes = [p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.POINTER(ctypes.c_int64)]
+    lib.gm_serve_close.argtypes = [p]
     lib.gm_free_query.argtypes = [p, i32]
     lib.gm_last_error.argtypes = [p]
     lib.gm_last_error.restype = ctypes.c_char_p
     for name in ("gm_create", "gm_load_graph", "gm_load_query", "gm_set_order", "gm_get_order", "gm_count",
-                 "gm_enumerate", "gm_count_batch", "gm_tune_batch", "gm_get_options", "gm_free_query"):
+                 "gm_enumerate", "gm_count_batch", "gm_tune_batch", "gm_get_options", "gm_serve_open",
+                 "gm_serve_submit", "gm_serve_poll", "gm_serve_stats", "gm_serve_close", "gm_free_query"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -292,6 +338,11 @@ class Engine:
         self._check(self._lib.gm_get_options(self._h, ctypes.byref(o)))
         return o
 
+    def serve(self, slots: int = 0, max_batch: int = 0, waves_per_cu: int = 0, batch_streams: int = 0,
+              max_pending: int = 0) -> "Server":
+        """Open a continuous-batching server on this engine's resident graph."""
+        return Server(self, slots, max_batch, waves_per_cu, batch_streams, max_pending)
+
     def free_query(self, qid: int) -> None:
         self._check(self._lib.gm_free_query(self._h, qid))
         self._k.pop(qid, None)
@@ -302,3 +353,58 @@ class Engine:
 
     def add(self, q) -> int:
         return self.load_query(q.k, q.edges, q.labels)
+
+
+class Server:
+    """Continuous batching over the engine's resident graph (gm_serve_*)."""
+
+    def __init__(self, engine: Engine, slots: int = 0, max_batch: int = 0, waves_per_cu: int = 0,
+                 batch_streams: int = 0, max_pending: int = 0):
+        self._engine = engine
+        self._lib = engine._lib
+        o = ServeOptions()
+        o.slots, o.max_batch, o.waves_per_cu = slots, max_batch, waves_per_cu
+        o.batch_streams, o.max_pending = batch_streams, max_pending
+        h = ctypes.c_void_p()
+        engine._check(self._lib.gm_serve_open(engine._h, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._buf = (_CServeResult * 4096)()
+
+    def submit(self, qid: int, cap: int = 0, time_limit_s: float = 0.0) -> int:
+        t = ctypes.c_uint64()
+        self._engine._check(self._lib.gm_serve_submit(self._h, qid, int(cap), float(time_limit_s), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, wait_s: float = 0.0, max_results: int = 4096) -> List[ServeResult]:
+        n = ctypes.c_int32()
+        m = min(max_results, len(self._buf))
+        self._engine._check(self._lib.gm_serve_poll(self._h, ctypes.cast(self._buf, ctypes.c_void_p), m,
+                                                    float(wait_s), ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            r = self._buf[i]
+            out.append(ServeResult(int(r.ticket), int(r.qid), int(r.slot), float(r.submit_ms), float(r.start_ms),
+                                   float(r.done_ms), Engine._result(r.result)))
+        return out
+
+    def stats(self):
+        p, r, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._engine._check(self._lib.gm_serve_stats(self._h, ctypes.byref(p), ctypes.byref(r), ctypes.byref(d)))
+        return p.value, r.value, d.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            self._engine._check(self._lib.gm_serve_close(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -7,8 +7,10 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -106,6 +108,27 @@ void parallel_ranges(int64_t n, F f) {
 
 }  // namespace
 
+// Device state of one persistent launch in flight: its HIP stream and events,
+// the control block, per-query plans and result blocks, work-item streams and
+// the stealing mailboxes.  The engine has one for its own calls; a server has
+// one per slot, so several launches can run at once.
+struct LaunchCtx {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    Control *d_ctl = nullptr;
+    Plan *d_plans = nullptr;       // per-query plans of a launch
+    gm::QCtl *d_qctl = nullptr;    // per-query results of a launch
+    size_t plans_cap = 0;
+    gm::StreamCtl *d_streams = nullptr;  // work-item streams of a launch
+    size_t streams_cap = 0;
+    gm::Mailbox *d_mail = nullptr;
+    unsigned long long *d_idle_bits = nullptr;
+    int32_t steal_slots = 0;
+    std::vector<Plan> h_plans;     // host copies (kept until the uploads complete)
+    std::vector<gm::QCtl> h_qctl;
+    std::vector<gm::StreamCtl> h_streams;
+};
+
 struct gm_engine {
     int32_t device = -1;
     gm_options opt{};
@@ -133,26 +156,13 @@ struct gm_engine {
     size_t pool_cap[2] = {0, 0};  // in int32
     int32_t *d_rows = nullptr;
     size_t rows_cap = 0;           // in int32
-    Plan *d_plans = nullptr;       // per-query plans of a launch
-    size_t plans_cap = 0;
-    gm::QCtl *d_qctl = nullptr;    // per-query results of a launch
-    size_t qctl_cap = 0;
-    std::vector<Plan> h_plans;     // host copies (kept until the uploads complete)
-    std::vector<gm::QCtl> h_qctl;
     uint32_t *d_vlen = nullptr;    // virtual level-1 pool: slice length, start and first task per root
     uint32_t *d_vstart = nullptr;
     uint32_t *d_voff = nullptr;
     uint32_t *d_vtmp = nullptr;    // chunk totals of the prefix sum
     size_t v_cap = 0;
-    gm::StreamCtl *d_streams = nullptr;  // work-item streams of a launch
-    size_t streams_cap = 0;
-    std::vector<gm::StreamCtl> h_streams;
-    Control *d_ctl = nullptr;
-    gm::Mailbox *d_mail = nullptr;
-    unsigned long long *d_idle_bits = nullptr;
-    int32_t steal_slots = 0;
-    hipStream_t stream = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    LaunchCtx lc;                  // device state of the engine's own launches
+    std::atomic<int> servers{0};   // open servers (the graph must stay as it is)
     int num_cu = 0;
     long long wall_khz = 0;
 
@@ -163,6 +173,27 @@ struct gm_engine {
 };
 
 namespace {
+
+// Stream, events and control block of a launch context (the rest is allocated on first use).
+hipError_t ctx_create(LaunchCtx &c) {
+    hipError_t h = hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking);
+    if (h == hipSuccess) h = hipEventCreate(&c.ev0);
+    if (h == hipSuccess) h = hipEventCreate(&c.ev1);
+    if (h == hipSuccess) h = hipMalloc(reinterpret_cast<void **>(&c.d_ctl), sizeof(Control));
+    return h;
+}
+
+// Waits for the context's work and frees everything it holds.
+void ctx_destroy(LaunchCtx &c) {
+    if (c.stream) (void)hipStreamSynchronize(c.stream);
+    for (void *b : {static_cast<void *>(c.d_ctl), static_cast<void *>(c.d_plans), static_cast<void *>(c.d_qctl),
+                    static_cast<void *>(c.d_streams), static_cast<void *>(c.d_mail), static_cast<void *>(c.d_idle_bits)})
+        if (b) (void)hipFree(b);
+    if (c.ev0) (void)hipEventDestroy(c.ev0);
+    if (c.ev1) (void)hipEventDestroy(c.ev1);
+    if (c.stream) (void)hipStreamDestroy(c.stream);
+    c = LaunchCtx{};
+}
 
 gm_status hip_fail(const gm_engine *e, hipError_t h, const char *what) {
     return e->fail(GM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(h));
@@ -177,7 +208,7 @@ gm_status hip_fail(const gm_engine *e, hipError_t h, const char *what) {
 gm_status ensure_buffer(gm_engine *e, int32_t **buf, size_t *cap, size_t need_ints) {
     if (need_ints <= *cap && *buf) return GM_OK;
     if (*buf) {
-        hipFree(*buf);
+        (void)hipFree(*buf);
         *buf = nullptr;
         *cap = 0;
     }
@@ -203,7 +234,7 @@ gm_status ensure_level1(gm_engine *e, size_t R) {
     if (R <= e->v_cap && e->d_voff) return GM_OK;
     uint32_t **bufs[] = {&e->d_vlen, &e->d_vstart, &e->d_voff, &e->d_vtmp};
     for (uint32_t **b : bufs) {
-        if (*b) hipFree(*b);
+        if (*b) (void)hipFree(*b);
         *b = nullptr;
     }
     e->v_cap = 0;
@@ -213,7 +244,7 @@ gm_status ensure_level1(gm_engine *e, size_t R) {
     if (h == hipSuccess) h = hipMalloc(reinterpret_cast<void **>(&e->d_vtmp), (want / 4096 + 2) * 4);
     if (h != hipSuccess) {
         for (uint32_t **b : bufs) {
-            if (*b) hipFree(*b);
+            if (*b) (void)hipFree(*b);
             *b = nullptr;
         }
         return e->fail(GM_ERR_NOMEM, "device allocation of the level-1 pool failed");
@@ -223,47 +254,47 @@ gm_status ensure_level1(gm_engine *e, size_t R) {
 }
 
 // Room for ns work-item streams on the device.
-gm_status ensure_streams(gm_engine *e, size_t ns) {
-    if (ns <= e->streams_cap && e->d_streams) return GM_OK;
-    if (e->d_streams) hipFree(e->d_streams);
-    e->d_streams = nullptr;
-    e->streams_cap = 0;
+gm_status ensure_streams(gm_engine *e, LaunchCtx &c, size_t ns) {
+    if (ns <= c.streams_cap && c.d_streams) return GM_OK;
+    if (c.d_streams) (void)hipFree(c.d_streams);
+    c.d_streams = nullptr;
+    c.streams_cap = 0;
     const size_t want = std::max<size_t>(ns, 64);
-    if (hipMalloc(reinterpret_cast<void **>(&e->d_streams), want * sizeof(gm::StreamCtl)) != hipSuccess) {
-        e->d_streams = nullptr;
+    if (hipMalloc(reinterpret_cast<void **>(&c.d_streams), want * sizeof(gm::StreamCtl)) != hipSuccess) {
+        c.d_streams = nullptr;
         return e->fail(GM_ERR_NOMEM, "device allocation of work streams failed");
     }
-    e->streams_cap = want;
+    c.streams_cap = want;
     return GM_OK;
 }
 
 // Room for nq plans and per-query result blocks on the device.
-gm_status ensure_query_slots(gm_engine *e, size_t nq) {
-    if (nq <= e->plans_cap && e->d_plans && e->d_qctl) return GM_OK;
-    if (e->d_plans) hipFree(e->d_plans);
-    if (e->d_qctl) hipFree(e->d_qctl);
-    e->d_plans = nullptr;
-    e->d_qctl = nullptr;
-    e->plans_cap = 0;
+gm_status ensure_query_slots(gm_engine *e, LaunchCtx &c, size_t nq) {
+    if (nq <= c.plans_cap && c.d_plans && c.d_qctl) return GM_OK;
+    if (c.d_plans) (void)hipFree(c.d_plans);
+    if (c.d_qctl) (void)hipFree(c.d_qctl);
+    c.d_plans = nullptr;
+    c.d_qctl = nullptr;
+    c.plans_cap = 0;
     const size_t want = std::max<size_t>(nq, 64);
-    hipError_t h = hipMalloc(reinterpret_cast<void **>(&e->d_plans), want * sizeof(Plan));
-    if (h == hipSuccess) h = hipMalloc(reinterpret_cast<void **>(&e->d_qctl), want * sizeof(gm::QCtl));
+    hipError_t h = hipMalloc(reinterpret_cast<void **>(&c.d_plans), want * sizeof(Plan));
+    if (h == hipSuccess) h = hipMalloc(reinterpret_cast<void **>(&c.d_qctl), want * sizeof(gm::QCtl));
     if (h != hipSuccess) {
-        if (e->d_plans) hipFree(e->d_plans);
-        e->d_plans = nullptr;
-        e->d_qctl = nullptr;
+        if (c.d_plans) (void)hipFree(c.d_plans);
+        c.d_plans = nullptr;
+        c.d_qctl = nullptr;
         return e->fail(GM_ERR_NOMEM, "device allocation of query plans failed");
     }
-    e->plans_cap = want;
+    c.plans_cap = want;
     return GM_OK;
 }
 
 void free_graph(gm_engine *e) {
-    if (e->d_vinfo) hipFree(e->d_vinfo);
-    if (e->d_lcol && e->d_lcol != e->d_col) hipFree(e->d_lcol);
-    if (e->d_col) hipFree(e->d_col);
-    if (e->d_loff) hipFree(e->d_loff);
-    if (e->d_bylabel) hipFree(e->d_bylabel);
+    if (e->d_vinfo) (void)hipFree(e->d_vinfo);
+    if (e->d_lcol && e->d_lcol != e->d_col) (void)hipFree(e->d_lcol);
+    if (e->d_col) (void)hipFree(e->d_col);
+    if (e->d_loff) (void)hipFree(e->d_loff);
+    if (e->d_bylabel) (void)hipFree(e->d_bylabel);
     e->d_bylabel = nullptr;
     e->lab_start.clear();
     e->bylabel_deg.clear();
@@ -336,18 +367,18 @@ gm_status get_query(const gm_engine *e, int32_t qid, const QueryRec **q) {
     return GM_OK;
 }
 
-gm_status read_ctl(gm_engine *e, Control *host) {
-    HIP_TRY(e, hipMemcpyAsync(host, e->d_ctl, sizeof(Control), hipMemcpyDeviceToHost, e->stream));
-    HIP_TRY(e, hipStreamSynchronize(e->stream));
+gm_status read_ctl(gm_engine *e, LaunchCtx &c, Control *host) {
+    HIP_TRY(e, hipMemcpyAsync(host, c.d_ctl, sizeof(Control), hipMemcpyDeviceToHost, c.stream));
+    HIP_TRY(e, hipStreamSynchronize(c.stream));
     return GM_OK;
 }
 
 // Empty idle bitmap and mailboxes, zero busy and idle counts before a launch that steals.
-gm_status reset_stealing(gm_engine *e, const SearchArgs &a) {
+gm_status reset_stealing(gm_engine *e, LaunchCtx &c, const SearchArgs &a) {
     if (!a.mail) return GM_OK;
-    HIP_TRY(e, hipMemsetAsync(&e->d_ctl->busy, 0, sizeof(int), e->stream));
-    HIP_TRY(e, hipMemsetAsync(&e->d_ctl->idle_count, 0, sizeof(int), e->stream));
-    HIP_TRY(e, gm::launch_steal_init(a.mail, a.idle_bits, a.steal_slots, e->stream));
+    HIP_TRY(e, hipMemsetAsync(&c.d_ctl->busy, 0, sizeof(int), c.stream));
+    HIP_TRY(e, hipMemsetAsync(&c.d_ctl->idle_count, 0, sizeof(int), c.stream));
+    HIP_TRY(e, gm::launch_steal_init(a.mail, a.idle_bits, a.steal_slots, c.stream));
     return GM_OK;
 }
 
@@ -383,43 +414,43 @@ unsigned long long flush_for_cap(const gm_engine *e, uint64_t cap) {
 }
 
 // Mailboxes and idle bitmap for work stealing (allocated on first use).
-gm_status attach_stealing(gm_engine *e, SearchArgs &a) {
+gm_status attach_stealing(gm_engine *e, LaunchCtx &c, SearchArgs &a) {
     a.mail = nullptr;
     a.idle_bits = nullptr;
     a.steal_slots = 0;
     a.steal_threshold = e->opt.steal_threshold > 0 ? e->opt.steal_threshold : 128;
     if (e->opt.disable_stealing) return GM_OK;
-    if (!e->d_mail) {
+    if (!c.d_mail) {
         // one mailbox per wavefront that can be resident (at most 32 per CU)
         const int32_t slots = e->num_cu * 32;
-        hipError_t h = hipMalloc(reinterpret_cast<void **>(&e->d_mail), sizeof(gm::Mailbox) * slots);
+        hipError_t h = hipMalloc(reinterpret_cast<void **>(&c.d_mail), sizeof(gm::Mailbox) * slots);
         if (h == hipSuccess)
-            h = hipMalloc(reinterpret_cast<void **>(&e->d_idle_bits), sizeof(unsigned long long) * ((slots + 63) / 64));
+            h = hipMalloc(reinterpret_cast<void **>(&c.d_idle_bits), sizeof(unsigned long long) * ((slots + 63) / 64));
         if (h != hipSuccess) {
-            if (e->d_mail) hipFree(e->d_mail);
-            e->d_mail = nullptr;
-            e->d_idle_bits = nullptr;
+            if (c.d_mail) (void)hipFree(c.d_mail);
+            c.d_mail = nullptr;
+            c.d_idle_bits = nullptr;
             return e->fail(GM_ERR_NOMEM, "work-stealing mailbox allocation failed");
         }
-        e->steal_slots = slots;
+        c.steal_slots = slots;
     }
-    a.mail = e->d_mail;
-    a.idle_bits = e->d_idle_bits;
-    a.steal_slots = e->steal_slots;
+    a.mail = c.d_mail;
+    a.idle_bits = c.d_idle_bits;
+    a.steal_slots = c.steal_slots;
     return GM_OK;
 }
 
-SearchArgs graph_args(const gm_engine *e) {
+SearchArgs graph_args(const gm_engine *e, const LaunchCtx &c) {
     SearchArgs a{};
     a.vinfo = e->d_vinfo;
     a.col = e->d_col;
     a.lcol = e->d_lcol;
     a.loff = e->d_loff;
     a.loff_stride = e->loff_stride;
-    a.ctl = e->d_ctl;
-    a.plans = e->d_plans;
-    a.qctl = e->d_qctl;
-    a.streams = e->d_streams;
+    a.ctl = c.d_ctl;
+    a.plans = c.d_plans;
+    a.qctl = c.d_qctl;
+    a.streams = c.d_streams;
     return a;
 }
 
@@ -494,8 +525,8 @@ gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, ui
         out->outcome = cap && R >= cap ? GM_CAPPED : GM_DONE;
         if (enumerate && out->count) {
             HIP_TRY(e, hipMemcpyAsync(rows, e->d_bylabel + row0, out->count * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                      e->stream));
-            HIP_TRY(e, hipStreamSynchronize(e->stream));
+                                      e->lc.stream));
+            HIP_TRY(e, hipStreamSynchronize(e->lc.stream));
             out->rows = out->count;
         }
         std::chrono::duration<double, std::milli> ms = std::chrono::steady_clock::now() - t_start;
@@ -503,8 +534,8 @@ gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, ui
         return GM_OK;
     }
     if (R >= (1ull << 31)) return e->fail(GM_ERR_GRAPH, "more than 2^31 candidates for the first query vertex");
-    gm_status st = ensure_query_slots(e, 2);
-    if (!st) st = ensure_streams(e, 1);
+    gm_status st = ensure_query_slots(e, e->lc, 2);
+    if (!st) st = ensure_streams(e, e->lc, 1);
     if (!st) st = ensure_level1(e, R);
     if (!st && enumerate) st = ensure_buffer(e, &e->d_rows, &e->rows_cap, static_cast<size_t>(cap) * q->k);
     if (st) return st;
@@ -521,23 +552,23 @@ gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, ui
     p.vrow0 = 0;
     p.perm_mul = root_order(R);
     p.item_split = items_of(R);
-    e->h_plans.assign(1, p);
-    e->h_streams.assign(1, gm::StreamCtl{});
-    e->h_streams[0].plan0 = 0;
-    e->h_streams[0].plan1 = 1;
-    HIP_TRY(e, hipMemsetAsync(e->d_ctl, 0, sizeof(Control), e->stream));
-    HIP_TRY(e, hipMemsetAsync(e->d_qctl, 0, 2 * sizeof(gm::QCtl), e->stream));
-    HIP_TRY(e, hipMemcpyAsync(e->d_plans, e->h_plans.data(), sizeof(Plan), hipMemcpyHostToDevice, e->stream));
-    HIP_TRY(e, hipMemcpyAsync(e->d_streams, e->h_streams.data(), sizeof(gm::StreamCtl), hipMemcpyHostToDevice,
-                              e->stream));
-    HIP_TRY(e, gm::launch_start_clock(e->d_ctl, e->stream));
+    e->lc.h_plans.assign(1, p);
+    e->lc.h_streams.assign(1, gm::StreamCtl{});
+    e->lc.h_streams[0].plan0 = 0;
+    e->lc.h_streams[0].plan1 = 1;
+    HIP_TRY(e, hipMemsetAsync(e->lc.d_ctl, 0, sizeof(Control), e->lc.stream));
+    HIP_TRY(e, hipMemsetAsync(e->lc.d_qctl, 0, 2 * sizeof(gm::QCtl), e->lc.stream));
+    HIP_TRY(e, hipMemcpyAsync(e->lc.d_plans, e->lc.h_plans.data(), sizeof(Plan), hipMemcpyHostToDevice, e->lc.stream));
+    HIP_TRY(e, hipMemcpyAsync(e->lc.d_streams, e->lc.h_streams.data(), sizeof(gm::StreamCtl), hipMemcpyHostToDevice,
+                              e->lc.stream));
+    HIP_TRY(e, gm::launch_start_clock(e->lc.d_ctl, e->lc.stream));
     // the second phase's scanned candidates go to the second slot
     const int32_t lab1 = e->loff_stride > 1 ? p.lab[1] : 0;
     const bool slim = use_slim(e, q->k);
     HIP_TRY(e, gm::launch_level1(e->d_bylabel + row0, static_cast<int32_t>(R), p.perm_mul, p.hub_cut, e->d_loff,
-                                 e->loff_stride, lab1, e->d_vlen, e->d_vstart, e->d_voff, e->d_vtmp, e->d_qctl + 1,
-                                 e->d_plans, e->d_streams, e->num_cu, e->stream));
-    SearchArgs a = graph_args(e);
+                                 e->loff_stride, lab1, e->d_vlen, e->d_vstart, e->d_voff, e->d_vtmp, e->lc.d_qctl + 1,
+                                 e->lc.d_plans, e->lc.d_streams, e->num_cu, e->lc.stream));
+    SearchArgs a = graph_args(e, e->lc);
     a.nq = 1;
     a.nstreams = 1;
     a.levels = q->k;
@@ -551,22 +582,22 @@ gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, ui
                    : 0ull;
     a.out = enumerate ? e->d_rows : nullptr;
     a.out_cap = enumerate ? cap : 0;
-    st = attach_stealing(e, a);
-    if (!st) st = reset_stealing(e, a);
+    st = attach_stealing(e, e->lc, a);
+    if (!st) st = reset_stealing(e, e->lc, a);
     if (st) return st;
     int grid_waves = 0;
     float kernel_ms = 0.f;
-    HIP_TRY(e, hipEventRecord(e->ev0, e->stream));
-    HIP_TRY(e, gm::launch_search(a, enumerate, e->num_cu, e->opt.waves_per_cu, e->stream, &grid_waves));
-    HIP_TRY(e, hipEventRecord(e->ev1, e->stream));
+    HIP_TRY(e, hipEventRecord(e->lc.ev0, e->lc.stream));
+    HIP_TRY(e, gm::launch_search(a, enumerate, e->num_cu, e->opt.waves_per_cu, e->lc.stream, &grid_waves));
+    HIP_TRY(e, hipEventRecord(e->lc.ev1, e->lc.stream));
     gm::QCtl qc[2];
     gm::StreamCtl sc{};
     Control c{};
-    HIP_TRY(e, hipMemcpyAsync(qc, e->d_qctl, 2 * sizeof(gm::QCtl), hipMemcpyDeviceToHost, e->stream));
-    HIP_TRY(e, hipMemcpyAsync(&sc, e->d_streams, sizeof(gm::StreamCtl), hipMemcpyDeviceToHost, e->stream));
-    st = read_ctl(e, &c);
+    HIP_TRY(e, hipMemcpyAsync(qc, e->lc.d_qctl, 2 * sizeof(gm::QCtl), hipMemcpyDeviceToHost, e->lc.stream));
+    HIP_TRY(e, hipMemcpyAsync(&sc, e->lc.d_streams, sizeof(gm::StreamCtl), hipMemcpyDeviceToHost, e->lc.stream));
+    st = read_ctl(e, e->lc, &c);
     if (st) return st;
-    HIP_TRY(e, hipEventElapsedTime(&kernel_ms, e->ev0, e->ev1));
+    HIP_TRY(e, hipEventElapsedTime(&kernel_ms, e->lc.ev0, e->lc.ev1));
 
     const gm::QCtl &k0 = qc[0], &l1 = qc[1];
     if (cap && k0.count >= cap) {
@@ -595,8 +626,8 @@ gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, ui
         const uint64_t nrows = std::min<uint64_t>(out->count, std::min<uint64_t>(c.out_rows, cap));
         if (nrows) {
             HIP_TRY(e, hipMemcpyAsync(rows, e->d_rows, nrows * q->k * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                      e->stream));
-            HIP_TRY(e, hipStreamSynchronize(e->stream));
+                                      e->lc.stream));
+            HIP_TRY(e, hipStreamSynchronize(e->lc.stream));
         }
         out->rows = nrows;
     }
@@ -625,8 +656,8 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
         return GM_OK;
     }
     if (e->opt.tau == 0) return run_virtual(e, q, base_plan, cap, time_limit_s, rows, out);
-    st = ensure_query_slots(e, 1);
-    if (!st) st = ensure_streams(e, 1);
+    st = ensure_query_slots(e, e->lc, 1);
+    if (!st) st = ensure_streams(e, e->lc, 1);
     if (st) return st;
 
     const auto t_start = std::chrono::steady_clock::now();
@@ -638,29 +669,29 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
         return el.count() > time_limit_s;
     };
 
-    HIP_TRY(e, hipMemsetAsync(e->d_ctl, 0, sizeof(Control), e->stream));
-    HIP_TRY(e, hipMemsetAsync(e->d_qctl, 0, sizeof(gm::QCtl), e->stream));
+    HIP_TRY(e, hipMemsetAsync(e->lc.d_ctl, 0, sizeof(Control), e->lc.stream));
+    HIP_TRY(e, hipMemsetAsync(e->lc.d_qctl, 0, sizeof(gm::QCtl), e->lc.stream));
     st = ensure_buffer(e, &e->d_pool[0], &e->pool_cap[0], static_cast<size_t>(e->n));
     if (st) return st;
     // the root scan also bounds the next level: each root's label slice for position 1
     const int32_t lab1 = q->k >= 2 ? (e->loff_stride > 1 ? base_plan.lab[1] : 0) : -1;
     HIP_TRY(e, gm::launch_root_scan(e->d_vinfo, e->n, base_plan.lab[0], base_plan.qdeg[0], e->d_pool[0], e->d_loff,
-                                    e->loff_stride, lab1, e->d_ctl, e->num_cu, e->stream));
+                                    e->loff_stride, lab1, e->lc.d_ctl, e->num_cu, e->lc.stream));
     Control c{};
-    st = read_ctl(e, &c);
+    st = read_ctl(e, e->lc, &c);
     if (st) return st;
     uint64_t pool_rows = c.out_rows;
     uint64_t bound = c.measure;  // upper bound on the rows of the next level
     int cur = 0;
     int32_t depth = 1;
 
-    SearchArgs a = graph_args(e);
+    SearchArgs a = graph_args(e, e->lc);
     a.nq = 1;
     a.nstreams = 1;
     a.levels = q->k;
     a.budget = static_cast<unsigned long long>(budget_ticks);
     a.slim = use_slim(e, q->k) ? 1 : 0;
-    st = attach_stealing(e, a);
+    st = attach_stealing(e, e->lc, a);
     if (st) return st;
 
     if (q->k == 1) {
@@ -672,8 +703,8 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
         out->pool_depth = 1;
         if (enumerate && out->count) {
             HIP_TRY(e, hipMemcpyAsync(rows, e->d_pool[0], out->count * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                      e->stream));
-            HIP_TRY(e, hipStreamSynchronize(e->stream));
+                                      e->lc.stream));
+            HIP_TRY(e, hipStreamSynchronize(e->lc.stream));
             out->rows = out->count;
         }
         std::chrono::duration<double, std::milli> ms = std::chrono::steady_clock::now() - t_start;
@@ -683,8 +714,8 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
 
     // Plan 0 with the current pool level as its share (one query, items from 0).
     auto upload_plan = [&](int32_t d, uint64_t nrows, unsigned long long flush) -> gm_status {
-        e->h_plans.assign(1, base_plan);
-        Plan &p = e->h_plans[0];
+        e->lc.h_plans.assign(1, base_plan);
+        Plan &p = e->lc.h_plans[0];
         p.depth = d;
         p.cap = cap;
         p.flush = flush;
@@ -692,22 +723,22 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
         p.rows = nrows;
         p.item0 = 0;
         p.item_end = items_of(nrows);
-        e->h_streams.assign(1, gm::StreamCtl{});
-        e->h_streams[0].items = p.item_end;
-        e->h_streams[0].plan0 = 0;
-        e->h_streams[0].plan1 = 1;
-        HIP_TRY(e, hipMemcpyAsync(e->d_plans, &p, sizeof(Plan), hipMemcpyHostToDevice, e->stream));
-        HIP_TRY(e, hipMemcpyAsync(e->d_streams, e->h_streams.data(), sizeof(gm::StreamCtl), hipMemcpyHostToDevice,
-                                  e->stream));
-        HIP_TRY(e, hipMemsetAsync(&e->d_ctl->out_rows, 0, sizeof(unsigned long long), e->stream));
+        e->lc.h_streams.assign(1, gm::StreamCtl{});
+        e->lc.h_streams[0].items = p.item_end;
+        e->lc.h_streams[0].plan0 = 0;
+        e->lc.h_streams[0].plan1 = 1;
+        HIP_TRY(e, hipMemcpyAsync(e->lc.d_plans, &p, sizeof(Plan), hipMemcpyHostToDevice, e->lc.stream));
+        HIP_TRY(e, hipMemcpyAsync(e->lc.d_streams, e->lc.h_streams.data(), sizeof(gm::StreamCtl), hipMemcpyHostToDevice,
+                                  e->lc.stream));
+        HIP_TRY(e, hipMemsetAsync(&e->lc.d_ctl->out_rows, 0, sizeof(unsigned long long), e->lc.stream));
         return GM_OK;
     };
     gm::QCtl qc{};
     gm::StreamCtl sc{};
     auto read_results = [&]() -> gm_status {
-        HIP_TRY(e, hipMemcpyAsync(&qc, e->d_qctl, sizeof(gm::QCtl), hipMemcpyDeviceToHost, e->stream));
-        HIP_TRY(e, hipMemcpyAsync(&sc, e->d_streams, sizeof(gm::StreamCtl), hipMemcpyDeviceToHost, e->stream));
-        return read_ctl(e, &c);
+        HIP_TRY(e, hipMemcpyAsync(&qc, e->lc.d_qctl, sizeof(gm::QCtl), hipMemcpyDeviceToHost, e->lc.stream));
+        HIP_TRY(e, hipMemcpyAsync(&sc, e->lc.d_streams, sizeof(gm::StreamCtl), hipMemcpyDeviceToHost, e->lc.stream));
+        return read_ctl(e, e->lc, &c);
     };
 
     // Initialisation phase (Sec. 4.3): breadth-first levels until >= tau rows.
@@ -720,14 +751,14 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
         if (st) return st;
         st = upload_plan(depth, pool_rows, ~0ull);
         if (st) return st;
-        HIP_TRY(e, hipMemsetAsync(&e->d_ctl->measure, 0, sizeof(unsigned long long), e->stream));
+        HIP_TRY(e, hipMemsetAsync(&e->lc.d_ctl->measure, 0, sizeof(unsigned long long), e->lc.stream));
         a.pool = e->d_pool[cur];
         a.out = e->d_pool[cur ^ 1];
         a.out_cap = bound;
         a.measure_next = depth + 1 < q->k - 1 ? 1 : 0;  // bound of the level after this one
-        st = reset_stealing(e, a);
+        st = reset_stealing(e, e->lc, a);
         if (st) return st;
-        HIP_TRY(e, gm::launch_expand(a, e->num_cu, e->stream));
+        HIP_TRY(e, gm::launch_expand(a, e->num_cu, e->lc.stream));
         st = read_results();
         if (st) return st;
         if (c.abort != gm::kAbortNone || timed_out_host()) {
@@ -755,15 +786,15 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
         a.out = enumerate ? e->d_rows : nullptr;
         a.out_cap = enumerate ? cap : 0;
         a.measure_next = 0;
-        st = reset_stealing(e, a);
+        st = reset_stealing(e, e->lc, a);
         if (st) return st;
-        HIP_TRY(e, hipEventRecord(e->ev0, e->stream));
-        HIP_TRY(e, gm::launch_search(a, enumerate, e->num_cu, e->opt.waves_per_cu, e->stream, &grid_waves));
-        HIP_TRY(e, hipEventRecord(e->ev1, e->stream));
+        HIP_TRY(e, hipEventRecord(e->lc.ev0, e->lc.stream));
+        HIP_TRY(e, gm::launch_search(a, enumerate, e->num_cu, e->opt.waves_per_cu, e->lc.stream, &grid_waves));
+        HIP_TRY(e, hipEventRecord(e->lc.ev1, e->lc.stream));
         st = read_results();
         if (st) return st;
-        HIP_TRY(e, hipEventElapsedTime(&kernel_ms, e->ev0, e->ev1));
-        finished = query_finished(e->h_plans[0], qc, sc);
+        HIP_TRY(e, hipEventElapsedTime(&kernel_ms, e->lc.ev0, e->lc.ev1));
+        finished = query_finished(e->lc.h_plans[0], qc, sc);
     }
 
     const uint64_t total = qc.count;
@@ -794,8 +825,8 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
         const uint64_t nrows = std::min<uint64_t>(out->count, std::min<uint64_t>(c.out_rows, cap));
         if (nrows) {
             HIP_TRY(e, hipMemcpyAsync(rows, e->d_rows, nrows * q->k * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                      e->stream));
-            HIP_TRY(e, hipStreamSynchronize(e->stream));
+                                      e->lc.stream));
+            HIP_TRY(e, hipStreamSynchronize(e->lc.stream));
         }
         out->rows = nrows;
     }
@@ -811,6 +842,122 @@ int residency(const gm_engine *e, int32_t k) {
 
 // Work-item streams of a batched launch: the option, else 64 (queries in flight).
 int32_t batch_streams(const gm_engine *e) { return e->opt.batch_streams > 0 ? e->opt.batch_streams : 64; }
+
+// One persistent launch of a group of queries on a launch context.  Plans are
+// laid out stream by stream (member j of the group goes to stream j mod ns);
+// pos[] maps each plan slot back to the caller's index.
+struct GroupLaunch {
+    std::vector<int32_t> pos;
+    int32_t nq = 0;
+    int32_t ns = 0;
+    int grid_waves = 0;
+    bool launched = false;  // false: no query of the group has any work item
+};
+
+// Lays out the group plans[members[0 .. g)] and queues its launch on c.stream
+// (nothing waits for it).  Levels = the largest query of the group.
+gm_status launch_group(gm_engine *e, LaunchCtx &c, const std::vector<Plan> &plans, const int32_t *members, int32_t g,
+                       int32_t nstreams, int waves_per_cu, GroupLaunch &gl) {
+    int32_t levels = 0;
+    for (int32_t j = 0; j < g; ++j) levels = std::max(levels, plans[members[j]].k);
+    const int32_t ns = std::max(1, std::min(g, nstreams));
+    gl = GroupLaunch{};
+    gl.nq = g;
+    gl.ns = ns;
+    c.h_plans.clear();
+    c.h_streams.assign(static_cast<size_t>(ns), gm::StreamCtl{});
+    unsigned long long items = 0;
+    for (int32_t sidx = 0; sidx < ns; ++sidx) {
+        gm::StreamCtl &sc = c.h_streams[sidx];
+        sc.plan0 = static_cast<int32_t>(c.h_plans.size());
+        unsigned long long local = 0;
+        for (int32_t j = sidx; j < g; j += ns) {
+            Plan p = plans[members[j]];
+            p.item0 = local;
+            local += items_of(p.rows);
+            p.item_end = local;
+            c.h_plans.push_back(p);
+            gl.pos.push_back(members[j]);
+        }
+        sc.plan1 = static_cast<int32_t>(c.h_plans.size());
+        sc.items = local;
+        items += local;
+    }
+    if (items == 0) return GM_OK;
+    gm_status st = ensure_query_slots(e, c, static_cast<size_t>(g));
+    if (!st) st = ensure_streams(e, c, static_cast<size_t>(ns));
+    if (st) return st;
+    HIP_TRY(e, hipMemsetAsync(c.d_ctl, 0, sizeof(Control), c.stream));
+    HIP_TRY(e, hipMemsetAsync(c.d_qctl, 0, sizeof(gm::QCtl) * static_cast<size_t>(g), c.stream));
+    HIP_TRY(e, hipMemcpyAsync(c.d_plans, c.h_plans.data(), sizeof(Plan) * static_cast<size_t>(g),
+                              hipMemcpyHostToDevice, c.stream));
+    HIP_TRY(e, hipMemcpyAsync(c.d_streams, c.h_streams.data(), sizeof(gm::StreamCtl) * static_cast<size_t>(ns),
+                              hipMemcpyHostToDevice, c.stream));
+    SearchArgs a = graph_args(e, c);
+    a.nq = g;
+    a.nstreams = ns;
+    a.levels = levels;
+    a.pool = e->d_bylabel;
+    a.slim = use_slim(e, levels) ? 1 : 0;
+    a.budget = 0;  // limits are per query (plan budgets)
+    st = attach_stealing(e, c, a);
+    if (!st) st = reset_stealing(e, c, a);
+    if (st) return st;
+    HIP_TRY(e, gm::launch_start_clock(c.d_ctl, c.stream));
+    HIP_TRY(e, hipEventRecord(c.ev0, c.stream));
+    HIP_TRY(e, gm::launch_search(a, false, e->num_cu, waves_per_cu, c.stream, &gl.grid_waves));
+    HIP_TRY(e, hipEventRecord(c.ev1, c.stream));
+    gl.launched = true;
+    return GM_OK;
+}
+
+// Waits for a launched group and writes each query's result to out[pos[j]]
+// (gm_count's rules with the plan's own cap); adds to *sum if not null.
+gm_status harvest_group(gm_engine *e, LaunchCtx &c, const GroupLaunch &gl, gm_result *out, gm_batch_info *sum) {
+    c.h_qctl.resize(static_cast<size_t>(gl.nq));
+    HIP_TRY(e, hipMemcpyAsync(c.h_qctl.data(), c.d_qctl, sizeof(gm::QCtl) * static_cast<size_t>(gl.nq),
+                              hipMemcpyDeviceToHost, c.stream));
+    HIP_TRY(e, hipMemcpyAsync(c.h_streams.data(), c.d_streams, sizeof(gm::StreamCtl) * static_cast<size_t>(gl.ns),
+                              hipMemcpyDeviceToHost, c.stream));
+    Control ctl{};
+    gm_status st = read_ctl(e, c, &ctl);
+    if (st) return st;
+    float kernel_ms = 0.f;
+    HIP_TRY(e, hipEventElapsedTime(&kernel_ms, c.ev0, c.ev1));
+    if (sum) {
+        sum->kernel_ms += kernel_ms;
+        sum->launches += 1;
+        sum->grid_waves = std::max(sum->grid_waves, gl.grid_waves);
+    }
+    for (int32_t sidx = 0; sidx < gl.ns; ++sidx) {
+        const gm::StreamCtl &sc = c.h_streams[sidx];
+        for (int32_t j = sc.plan0; j < sc.plan1; ++j) {
+            const Plan &p = c.h_plans[j];
+            const gm::QCtl &qc = c.h_qctl[j];
+            gm_result &r = out[gl.pos[j]];
+            if (p.cap && qc.count >= p.cap) {
+                r.count = p.cap;
+                r.outcome = GM_CAPPED;
+            } else {
+                r.count = qc.count;
+                const bool done = p.rows == 0 || (qc.abort != gm::kAbortTime && query_finished(p, qc, sc));
+                r.outcome = done ? GM_DONE : GM_TIMEOUT;
+            }
+            r.groups = r.kernel_groups = qc.groups;
+            r.tasks = r.kernel_tasks = qc.tasks;
+            r.lanes_active = qc.lanes_active;
+            r.lanes_issued = qc.lanes_issued;
+            r.probes = r.kernel_probes = qc.probes;
+            r.steals = qc.steals;
+            r.scanned = r.kernel_scanned = qc.scanned;
+            r.kernel_lookups = qc.lookups;
+            r.kernel_ms = kernel_ms;
+            r.grid_waves = gl.grid_waves;
+            if (sum) sum->lookups += qc.lookups;
+        }
+    }
+    return GM_OK;
+}
 
 // Several queries in shared persistent launches: every query's first-vertex
 // candidates (a prefix of its label's bucket, highest degree first) are its
@@ -873,101 +1020,12 @@ gm_status run_batch(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t cap,
 
     for (size_t g0 = 0; g0 < idx.size();) {
         size_t g1 = g0;
-        int32_t levels = 0;
-        while (g1 < idx.size() && key[idx[g1]] == key[idx[g0]]) levels = std::max(levels, plans[idx[g1++]].k);
-        const int32_t g = static_cast<int32_t>(g1 - g0);
-        // streams: member j of the group goes to stream j mod ns; plans are laid
-        // out stream by stream, pos[] maps a plan back to its place in the batch
-        const int32_t ns = std::max(1, std::min(g, batch_streams(e)));
-        e->h_plans.clear();
-        e->h_streams.assign(static_cast<size_t>(ns), gm::StreamCtl{});
-        std::vector<int32_t> pos;
-        unsigned long long items = 0;
-        for (int32_t sidx = 0; sidx < ns; ++sidx) {
-            gm::StreamCtl &sc = e->h_streams[sidx];
-            sc.plan0 = static_cast<int32_t>(e->h_plans.size());
-            unsigned long long local = 0;
-            for (int32_t j = sidx; j < g; j += ns) {
-                Plan p = plans[idx[g0 + j]];
-                p.item0 = local;
-                local += items_of(p.rows);
-                p.item_end = local;
-                e->h_plans.push_back(p);
-                pos.push_back(idx[g0 + j]);
-            }
-            sc.plan1 = static_cast<int32_t>(e->h_plans.size());
-            sc.items = local;
-            items += local;
-        }
-        if (items == 0) {
-            g0 = g1;
-            continue;
-        }
-        gm_status st = ensure_query_slots(e, static_cast<size_t>(g));
-        if (!st) st = ensure_streams(e, static_cast<size_t>(ns));
+        while (g1 < idx.size() && key[idx[g1]] == key[idx[g0]]) ++g1;
+        GroupLaunch gl;
+        gm_status st = launch_group(e, e->lc, plans, idx.data() + g0, static_cast<int32_t>(g1 - g0), batch_streams(e),
+                                    e->opt.waves_per_cu, gl);
+        if (!st && gl.launched) st = harvest_group(e, e->lc, gl, out, &sum);
         if (st) return st;
-        HIP_TRY(e, hipMemsetAsync(e->d_ctl, 0, sizeof(Control), e->stream));
-        HIP_TRY(e, hipMemsetAsync(e->d_qctl, 0, sizeof(gm::QCtl) * static_cast<size_t>(g), e->stream));
-        HIP_TRY(e, hipMemcpyAsync(e->d_plans, e->h_plans.data(), sizeof(Plan) * static_cast<size_t>(g),
-                                  hipMemcpyHostToDevice, e->stream));
-        HIP_TRY(e, hipMemcpyAsync(e->d_streams, e->h_streams.data(), sizeof(gm::StreamCtl) * static_cast<size_t>(ns),
-                                  hipMemcpyHostToDevice, e->stream));
-        SearchArgs a = graph_args(e);
-        a.nq = g;
-        a.nstreams = ns;
-        a.levels = levels;
-        a.pool = e->d_bylabel;
-        a.slim = use_slim(e, levels) ? 1 : 0;
-        a.budget = 0;  // limits are per query (plan budgets)
-        st = attach_stealing(e, a);
-        if (st) return st;
-        st = reset_stealing(e, a);
-        if (st) return st;
-        int grid_waves = 0;
-        float kernel_ms = 0.f;
-        HIP_TRY(e, gm::launch_start_clock(e->d_ctl, e->stream));
-        HIP_TRY(e, hipEventRecord(e->ev0, e->stream));
-        HIP_TRY(e, gm::launch_search(a, false, e->num_cu, e->opt.waves_per_cu, e->stream, &grid_waves));
-        HIP_TRY(e, hipEventRecord(e->ev1, e->stream));
-        e->h_qctl.resize(static_cast<size_t>(g));
-        HIP_TRY(e, hipMemcpyAsync(e->h_qctl.data(), e->d_qctl, sizeof(gm::QCtl) * static_cast<size_t>(g),
-                                  hipMemcpyDeviceToHost, e->stream));
-        HIP_TRY(e, hipMemcpyAsync(e->h_streams.data(), e->d_streams, sizeof(gm::StreamCtl) * static_cast<size_t>(ns),
-                                  hipMemcpyDeviceToHost, e->stream));
-        Control c{};
-        st = read_ctl(e, &c);
-        if (st) return st;
-        HIP_TRY(e, hipEventElapsedTime(&kernel_ms, e->ev0, e->ev1));
-        sum.kernel_ms += kernel_ms;
-        sum.launches += 1;
-        sum.grid_waves = std::max(sum.grid_waves, grid_waves);
-        for (int32_t sidx = 0; sidx < ns; ++sidx) {
-            const gm::StreamCtl &sc = e->h_streams[sidx];
-            for (int32_t j = sc.plan0; j < sc.plan1; ++j) {
-                const Plan &p = e->h_plans[j];
-                const gm::QCtl &qc = e->h_qctl[j];
-                gm_result &r = out[pos[j]];
-                if (cap && qc.count >= cap) {
-                    r.count = cap;
-                    r.outcome = GM_CAPPED;
-                } else {
-                    r.count = qc.count;
-                    const bool done = p.rows == 0 || (qc.abort != gm::kAbortTime && query_finished(p, qc, sc));
-                    r.outcome = done ? GM_DONE : GM_TIMEOUT;
-                }
-                r.groups = r.kernel_groups = qc.groups;
-                r.tasks = r.kernel_tasks = qc.tasks;
-                r.lanes_active = qc.lanes_active;
-                r.lanes_issued = qc.lanes_issued;
-                r.probes = r.kernel_probes = qc.probes;
-                r.steals = qc.steals;
-                r.scanned = r.kernel_scanned = qc.scanned;
-                r.kernel_lookups = qc.lookups;
-                r.kernel_ms = kernel_ms;
-                r.grid_waves = grid_waves;
-                sum.lookups += qc.lookups;
-            }
-        }
         g0 = g1;
     }
     const double total_ms = elapsed_s() * 1000.0;
@@ -1055,6 +1113,148 @@ gm_status run_tune(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t cap, 
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Serving: a worker thread runs continuous batching over `slots` launch contexts.
+// ---------------------------------------------------------------------------
+struct gm_server {
+    struct Request {
+        uint64_t ticket = 0;
+        int32_t qid = 0;
+        Plan plan{};
+        double submit_ms = 0;
+    };
+    struct Slot {
+        LaunchCtx c;
+        GroupLaunch gl;
+        bool busy = false;
+        std::vector<Request> reqs;
+        std::vector<Plan> plans;
+        std::vector<int32_t> members;
+        std::vector<gm_result> res;
+        double start_ms = 0;
+    };
+
+    gm_engine *e = nullptr;
+    gm_serve_options opt{};
+    std::vector<Slot> slots;
+    std::mutex mu;
+    std::condition_variable wake;  // new requests, or stop
+    std::condition_variable ready_cv;
+    std::deque<Request> pending;
+    std::deque<gm_serve_result> ready;
+    int64_t running = 0;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    gm_status error = GM_OK;
+    std::string err;
+    std::thread worker;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+    double now_ms() const {
+        std::chrono::duration<double, std::milli> d = std::chrono::steady_clock::now() - t0;
+        return d.count();
+    }
+};
+
+namespace {
+
+// Results of a slot's finished (or empty) launch into the ready queue.
+void publish(gm_server *s, gm_server::Slot &sl, double done_ms, int32_t slot_id) {
+    for (size_t j = 0; j < sl.reqs.size(); ++j) {
+        gm_serve_result r{};
+        r.ticket = sl.reqs[j].ticket;
+        r.qid = sl.reqs[j].qid;
+        r.slot = slot_id;
+        r.submit_ms = sl.reqs[j].submit_ms;
+        r.start_ms = sl.start_ms;
+        r.done_ms = done_ms;
+        r.result = sl.res[j];
+        r.result.search_ms = done_ms - sl.start_ms;
+        s->ready.push_back(r);
+    }
+    s->running -= static_cast<int64_t>(sl.reqs.size());
+    sl.reqs.clear();
+    sl.busy = false;
+}
+
+void serve_loop(gm_server *s) {
+    gm_engine *e = s->e;
+    (void)hipSetDevice(e->device);
+    const int32_t nslots = static_cast<int32_t>(s->slots.size());
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        bool progress = false;
+        // harvest finished launches
+        for (int32_t i = 0; i < nslots; ++i) {
+            gm_server::Slot &sl = s->slots[i];
+            if (!sl.busy || hipEventQuery(sl.c.ev1) != hipSuccess) continue;
+            lk.unlock();
+            const gm_status st = harvest_group(e, sl.c, sl.gl, sl.res.data(), nullptr);
+            lk.lock();
+            if (st && !s->error) {
+                s->error = st;
+                s->err = e->err;
+            }
+            publish(s, sl, s->now_ms(), i);
+            progress = true;
+        }
+        if (progress) s->ready_cv.notify_all();
+        // admit queued requests into free slots, oldest first
+        for (int32_t i = 0; i < nslots && !s->pending.empty() && !s->error; ++i) {
+            gm_server::Slot &sl = s->slots[i];
+            if (sl.busy) continue;
+            const size_t g = std::min<size_t>(s->pending.size(), static_cast<size_t>(s->opt.max_batch));
+            sl.reqs.assign(s->pending.begin(), s->pending.begin() + static_cast<long>(g));
+            s->pending.erase(s->pending.begin(), s->pending.begin() + static_cast<long>(g));
+            s->running += static_cast<int64_t>(g);
+            sl.busy = true;
+            sl.start_ms = s->now_ms();
+            lk.unlock();
+            sl.plans.resize(g);
+            sl.members.resize(g);
+            sl.res.assign(g, gm_result{});
+            int32_t levels = 0;
+            for (size_t j = 0; j < g; ++j) {
+                sl.plans[j] = sl.reqs[j].plan;
+                sl.members[j] = static_cast<int32_t>(j);
+                levels = std::max(levels, sl.plans[j].k);
+                gm_result &r = sl.res[j];
+                r.pool_depth = 1;
+                r.pool_rows = sl.plans[j].rows;
+                r.outcome = GM_DONE;
+            }
+            int32_t wpc = s->opt.waves_per_cu;
+            if (wpc <= 0) wpc = std::max(1, residency(e, levels) / std::max(1, e->num_cu) / nslots);
+            const int32_t streams = s->opt.batch_streams > 0 ? s->opt.batch_streams : batch_streams(e);
+            const gm_status st = launch_group(e, sl.c, sl.plans, sl.members.data(), static_cast<int32_t>(g), streams,
+                                              wpc, sl.gl);
+            lk.lock();
+            if (st && !s->error) {
+                s->error = st;
+                s->err = e->err;
+            }
+            if (st || !sl.gl.launched) {  // nothing to run (or a failure): results as they stand
+                publish(s, sl, s->now_ms(), i);
+                s->ready_cv.notify_all();
+            }
+            progress = true;
+        }
+        bool busy = false;
+        for (const gm_server::Slot &sl : s->slots) busy |= sl.busy;
+        if (s->stop && s->pending.empty() && !busy) break;
+        if (s->error && !busy) {  // fail what is still queued
+            while (!s->pending.empty()) s->pending.pop_front();
+            if (s->stop) break;
+        }
+        if (!progress) {
+            if (busy) s->wake.wait_for(lk, std::chrono::microseconds(20));
+            else s->wake.wait_for(lk, std::chrono::milliseconds(5));
+        }
+    }
+}
+
+}  // namespace
+
 extern "C" {
 
 gm_status gm_create(int32_t device, const gm_options *opt, gm_engine **out) {
@@ -1095,9 +1295,7 @@ gm_status gm_create(int32_t device, const gm_options *opt, gm_engine **out) {
         int khz = 0;
         if ((h = hipSetDevice(device)) != hipSuccess || (h = hipGetDeviceProperties(&prop, device)) != hipSuccess ||
             (h = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device)) != hipSuccess ||
-            (h = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking)) != hipSuccess ||
-            (h = hipEventCreate(&e->ev0)) != hipSuccess || (h = hipEventCreate(&e->ev1)) != hipSuccess ||
-            (h = hipMalloc(reinterpret_cast<void **>(&e->d_ctl), sizeof(Control))) != hipSuccess) {
+            (h = ctx_create(e->lc)) != hipSuccess) {
             g_create_error = std::string("HIP setup failed: ") + hipGetErrorString(h);
             gm_destroy(e);
             return GM_ERR_DEVICE;
@@ -1112,23 +1310,14 @@ gm_status gm_create(int32_t device, const gm_options *opt, gm_engine **out) {
 void gm_destroy(gm_engine *e) {
     if (!e) return;
     if (e->device >= 0) {
-        hipSetDevice(e->device);
-        if (e->stream) hipStreamSynchronize(e->stream);
+        (void)hipSetDevice(e->device);
+        ctx_destroy(e->lc);
         free_graph(e);
         for (int i = 0; i < 2; ++i)
-            if (e->d_pool[i]) hipFree(e->d_pool[i]);
-        if (e->d_rows) hipFree(e->d_rows);
-        if (e->d_plans) hipFree(e->d_plans);
-        if (e->d_qctl) hipFree(e->d_qctl);
-        if (e->d_streams) hipFree(e->d_streams);
+            if (e->d_pool[i]) (void)hipFree(e->d_pool[i]);
+        if (e->d_rows) (void)hipFree(e->d_rows);
         for (uint32_t *b : {e->d_vlen, e->d_vstart, e->d_voff, e->d_vtmp})
-            if (b) hipFree(b);
-        if (e->d_ctl) hipFree(e->d_ctl);
-        if (e->d_mail) hipFree(e->d_mail);
-        if (e->d_idle_bits) hipFree(e->d_idle_bits);
-        if (e->ev0) hipEventDestroy(e->ev0);
-        if (e->ev1) hipEventDestroy(e->ev1);
-        if (e->stream) hipStreamDestroy(e->stream);
+            if (b) (void)hipFree(b);
     }
     delete e;
 }
@@ -1139,6 +1328,7 @@ gm_status gm_load_graph(gm_engine *e, int32_t n, const int64_t *row_ptr, const i
     std::lock_guard<std::mutex> lk(e->mu);
     if (n < 0) return e->fail(GM_ERR_ARG, "n must be >= 0");
     if (!row_ptr || (n > 0 && !labels)) return e->fail(GM_ERR_ARG, "row_ptr and labels must not be null");
+    if (e->servers.load() > 0) return e->fail(GM_ERR_STATE, "a server is open on this engine");
     gm_status st = check_graph(e, n, row_ptr, col, e->opt.skip_symmetry_check == 0);
     if (st) return st;
     std::unordered_map<int32_t, int32_t> ids;
@@ -1333,6 +1523,7 @@ gm_status gm_tune_batch(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t 
     if (!e) return GM_ERR_ARG;
     std::lock_guard<std::mutex> lk(e->mu);
     if (!out) return e->fail(GM_ERR_ARG, "out is null");
+    if (e->servers.load() > 0) return e->fail(GM_ERR_STATE, "a server is open on this engine");
     return run_tune(e, nq, qids, cap, time_limit_s, out);
 }
 
@@ -1342,6 +1533,119 @@ gm_status gm_get_options(const gm_engine *e, gm_options *out) {
     if (!out) return e->fail(GM_ERR_ARG, "out is null");
     *out = e->opt;
     return GM_OK;
+}
+
+gm_status gm_serve_open(gm_engine *e, const gm_serve_options *opt, gm_server **out) {
+    if (!e) return GM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (!out) return e->fail(GM_ERR_ARG, "out is null");
+    *out = nullptr;
+    gm_serve_options o{};
+    if (opt) o = *opt;
+    if (o.slots < 0 || o.slots > 16 || o.max_batch < 0 || o.waves_per_cu < 0 || o.batch_streams < 0 ||
+        o.max_pending < 0)
+        return e->fail(GM_ERR_ARG, "serve option out of range");
+    if (!e->has_graph) return e->fail(GM_ERR_STATE, "no data graph loaded");
+    if (e->device < 0) return e->fail(GM_ERR_DEVICE, "host-only engine (created with device -1) cannot serve");
+    if (o.slots == 0) o.slots = 2;
+    if (o.max_batch == 0) o.max_batch = 256;
+    HIP_TRY(e, hipSetDevice(e->device));
+    gm_server *s = new (std::nothrow) gm_server();
+    if (!s) return e->fail(GM_ERR_NOMEM, "out of host memory");
+    s->e = e;
+    s->opt = o;
+    s->slots.resize(static_cast<size_t>(o.slots));
+    for (gm_server::Slot &sl : s->slots) {
+        const hipError_t h = ctx_create(sl.c);
+        if (h != hipSuccess) {
+            for (gm_server::Slot &x : s->slots) ctx_destroy(x.c);
+            delete s;
+            return hip_fail(e, h, "server slot setup");
+        }
+    }
+    e->servers.fetch_add(1);
+    s->worker = std::thread(serve_loop, s);
+    *out = s;
+    return GM_OK;
+}
+
+gm_status gm_serve_submit(gm_server *s, int32_t qid, uint64_t cap, double time_limit_s, uint64_t *ticket) {
+    if (!s) return GM_ERR_ARG;
+    gm_engine *e = s->e;
+    if (!ticket) return e->fail(GM_ERR_ARG, "ticket is null");
+    gm_server::Request r;
+    r.qid = qid;
+    {
+        std::lock_guard<std::mutex> lk(e->mu);
+        const QueryRec *q = nullptr;
+        gm_status st = get_query(e, qid, &q);
+        if (st) return st;
+        bool missing = false;
+        Plan p = make_plan(e, *q, &missing);
+        p.cap = cap;
+        p.flush = flush_for_cap(e, cap);
+        p.depth = 1;
+        if (time_limit_s > 0)
+            p.budget = std::max<unsigned long long>(
+                1, static_cast<unsigned long long>(time_limit_s * 1000.0 * static_cast<double>(e->wall_khz)));
+        if (!missing) root_share(e, p, &p.row0, &p.rows);
+        p.perm_mul = root_order(p.rows);
+        r.plan = p;
+    }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->error) return e->fail(s->error, "server failed earlier: " + s->err);
+        if (s->opt.max_pending && static_cast<int64_t>(s->pending.size()) >= s->opt.max_pending)
+            return e->fail(GM_ERR_BUFFER, "server queue is full");
+        r.ticket = s->next_ticket++;
+        r.submit_ms = s->now_ms();
+        *ticket = r.ticket;
+        s->pending.push_back(r);
+    }
+    s->wake.notify_one();
+    return GM_OK;
+}
+
+gm_status gm_serve_poll(gm_server *s, gm_serve_result *out, int32_t max_results, double wait_s, int32_t *n_out) {
+    if (!s) return GM_ERR_ARG;
+    if (!n_out || max_results < 0 || (max_results > 0 && !out)) return s->e->fail(GM_ERR_ARG, "bad poll arguments");
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->ready.empty() && wait_s > 0)
+        s->ready_cv.wait_for(lk, std::chrono::duration<double>(wait_s), [s] { return !s->ready.empty() || s->error; });
+    int32_t n = 0;
+    while (n < max_results && !s->ready.empty()) {
+        out[n++] = s->ready.front();
+        s->ready.pop_front();
+    }
+    *n_out = n;
+    if (s->error && n == 0) return s->e->fail(s->error, "server failed: " + s->err);
+    return GM_OK;
+}
+
+gm_status gm_serve_stats(gm_server *s, int64_t *pending, int64_t *running, int64_t *ready) {
+    if (!s) return GM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (pending) *pending = static_cast<int64_t>(s->pending.size());
+    if (running) *running = s->running;
+    if (ready) *ready = static_cast<int64_t>(s->ready.size());
+    return GM_OK;
+}
+
+gm_status gm_serve_close(gm_server *s) {
+    if (!s) return GM_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->wake.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    gm_engine *e = s->e;
+    (void)hipSetDevice(e->device);
+    for (gm_server::Slot &sl : s->slots) ctx_destroy(sl.c);
+    const gm_status st = s->error;
+    e->servers.fetch_sub(1);
+    delete s;
+    return st;
 }
 
 gm_status gm_free_query(gm_engine *e, int32_t qid) {

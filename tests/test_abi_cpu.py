@@ -38,13 +38,17 @@ def test_struct_layout_matches_header(tmp_path):
                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gm_options),'
                    ' sizeof(gm_result), offsetof(gm_result, kernel_ms), offsetof(gm_options, stack_layout),'
                    ' offsetof(gm_result, rows), offsetof(gm_options, batch_single_launch),'
-                   ' sizeof(gm_batch_info), offsetof(gm_batch_info, count), sizeof(gm_tuning));return 0;}\n')
+                   ' sizeof(gm_batch_info), offsetof(gm_batch_info, count), sizeof(gm_tuning));'
+                   'printf("%zu %zu %zu %zu\\n", sizeof(gm_serve_options), offsetof(gm_serve_options, max_pending),'
+                   ' sizeof(gm_serve_result), offsetof(gm_serve_result, result));return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
     vals = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     assert vals == [ctypes.sizeof(gm.Options), ctypes.sizeof(gm._CResult), gm._CResult.kernel_ms.offset,
                     gm.Options.stack_layout.offset, gm._CResult.rows.offset, gm.Options.batch_single_launch.offset,
-                    ctypes.sizeof(gm.BatchInfo), gm.BatchInfo.count.offset, ctypes.sizeof(gm.Tuning)]
+                    ctypes.sizeof(gm.BatchInfo), gm.BatchInfo.count.offset, ctypes.sizeof(gm.Tuning),
+                    ctypes.sizeof(gm.ServeOptions), gm.ServeOptions.max_pending.offset,
+                    ctypes.sizeof(gm._CServeResult), gm._CServeResult.result.offset]
 
 
 @pytest.fixture()
@@ -127,6 +131,8 @@ def test_host_engine_refuses_to_search(host_engine):
     expect(gm.GM_ERR_DEVICE, e.count_batch, [qid, qid])
     expect(gm.GM_ERR_STATE, e.count_batch, [qid, 999])
     expect(gm.GM_ERR_DEVICE, e.tune_batch, [qid])
+    expect(gm.GM_ERR_DEVICE, e.serve)                                           # no GPU: no server
+    expect(gm.GM_ERR_ARG, e.serve, 99)                                          # slots out of range
     res, info = e.count_batch([])                                                # empty batch: nothing to do
     assert res == [] and info.launches == 0
     o = e.options()

@@ -1,0 +1,144 @@
+"""Serving (gm_serve_*): continuous batching over a resident graph.
+
+Requests arrive while others run; every result must equal what the same query
+gets alone from gm_count with the same cap and time limit (counts, outcomes,
+and the work counters of finished searches)."""
+import time
+
+import numpy as np
+import pytest
+
+import paper_2604_10601_amd as gm
+from paper_2604_10601_amd import workloads as wl
+from tests.test_batch_gpu import mixed_er_case, rmat16_case, union
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def mixed_graph():
+    """An ER part (queries finish) and an R-MAT part with its own labels (queries
+    explode unless capped); the ER queries come first."""
+    ge, qe = mixed_er_case()
+    gr, qr = rmat16_case()
+    g = union(ge, gr, 8)
+    qr = [wl.Query(k=q.k, edges=q.edges, labels=q.labels + 8) for q in qr]
+    return g, qe + qr, len(qe)
+
+
+def requests(qids, n_light, rng, n):
+    """n requests: light queries with a cap of none, 1e3 or 1e6, explosive ones capped."""
+    out = []
+    for _ in range(n):
+        i = int(rng.integers(len(qids)))
+        caps = [0, 1000, 1_000_000] if i < n_light else [1000, 1_000_000]
+        out.append((int(qids[i]), caps[int(rng.integers(len(caps)))]))
+    return out
+
+
+def drain(srv, tickets, timeout_s=120.0):
+    got = {}
+    t0 = time.time()
+    while len(got) < len(tickets):
+        for r in srv.poll(wait_s=0.05):
+            assert r.ticket in tickets and r.ticket not in got
+            got[r.ticket] = r
+        assert time.time() - t0 < timeout_s, "results did not come back"
+    return got
+
+
+def check_same(e, req, res, alone_cache):
+    qid, cap = req
+    key = (qid, cap)
+    if key not in alone_cache:
+        alone_cache[key] = e.count(qid, cap=cap, time_limit_s=10.0)
+    a = alone_cache[key]
+    r = res.result
+    if a.outcome == gm.GM_TIMEOUT or r.outcome == gm.GM_TIMEOUT:
+        return
+    assert (r.count, r.outcome) == (a.count, a.outcome), (qid, cap)
+    if a.outcome == gm.GM_DONE:
+        assert (r.groups, r.tasks) == (a.groups, a.tasks), (qid, cap)
+
+
+@pytest.mark.parametrize("slots,max_batch", [(2, 256), (1, 1), (4, 7), (3, 64)])
+def test_results_equal_alone_with_arrivals_during_work(slots, max_batch):
+    g, qs, n_light = mixed_graph()
+    rng = np.random.default_rng(3100 + slots)
+    with gm.Engine(device=0) as e:
+        e.load(g)
+        qids = [e.add(q) for q in qs]
+        reqs = requests(qids, n_light, rng, 150)
+        with e.serve(slots=slots, max_batch=max_batch) as srv:
+            tickets = {}
+            for wave in range(3):  # three bursts: later ones arrive while earlier ones run
+                for req in reqs[wave * 50:(wave + 1) * 50]:
+                    tickets[srv.submit(req[0], cap=req[1], time_limit_s=10.0)] = req
+                time.sleep(0.002)
+            _say(f"slots={slots} max_batch={max_batch}: {len(tickets)} requests queued, stats {srv.stats()}")
+            got = drain(srv, tickets)
+            assert srv.stats() == (0, 0, 0)
+        alone = {}
+        for t, req in tickets.items():
+            r = got[t]
+            assert r.qid == req[0] and 0 <= r.slot < slots
+            assert r.submit_ms <= r.start_ms + 1e-6 <= r.done_ms + 2e-6
+            check_same(e, req, r, alone)
+
+
+def test_time_limits_in_the_mix():
+    """Explosive uncapped requests with a tight limit next to light ones: light
+    ones finish exactly; the explosive ones time out without holding the rest."""
+    g, qs, n_light = mixed_graph()
+    with gm.Engine(device=0) as e:
+        e.load(g)
+        qids = [e.add(q) for q in qs]
+        light = qids[:n_light]
+        heavy = [qid for qid, q in zip(qids[n_light:], qs[n_light:]) if q.k >= 16]
+        with e.serve(slots=2, max_batch=16) as srv:
+            tickets = {}
+            for i in range(60):
+                qid = heavy[i % len(heavy)] if i % 3 == 0 else light[i % len(light)]
+                limit = 0.005 if qid in heavy else 10.0
+                tickets[srv.submit(qid, time_limit_s=limit)] = (qid, limit)
+            got = drain(srv, tickets)
+        outcomes = [got[t].result.outcome for t in tickets]
+        assert gm.GM_TIMEOUT in outcomes and gm.GM_DONE in outcomes
+        alone = {}
+        for t, (qid, limit) in tickets.items():
+            r = got[t].result
+            if r.outcome == gm.GM_TIMEOUT:
+                assert qid in heavy
+                continue
+            if qid not in alone:
+                alone[qid] = e.count(qid, time_limit_s=10.0)
+            assert (r.count, r.outcome, r.groups, r.tasks) == (alone[qid].count, alone[qid].outcome,
+                                                               alone[qid].groups, alone[qid].tasks)
+
+
+def test_engine_state_while_serving_and_close_drains():
+    g, qs, _ = mixed_graph()
+    with gm.Engine(device=0) as e:
+        e.load(g)
+        qids = [e.add(q) for q in qs[:20]]
+        srv = e.serve(slots=2)
+        tickets = [srv.submit(q, cap=1000) for q in qids]
+        with pytest.raises(gm.GmError) as ei:
+            e.load(g)
+        assert ei.value.status == gm.GM_ERR_STATE
+        with pytest.raises(gm.GmError) as ei:
+            e.tune_batch(qids[:3])
+        assert ei.value.status == gm.GM_ERR_STATE
+        r = e.count(qids[0], cap=1000)              # engine calls still work beside the server
+        assert r.outcome in (gm.GM_DONE, gm.GM_CAPPED)
+        e.free_query(qids[1])                        # its request keeps its own plan
+        got = drain(srv, set(tickets))
+        assert len(got) == len(tickets)
+        t = srv.submit(qids[2])
+        srv.close()                                  # finishes the queued request
+        e.load(g)                                    # allowed again
+        with pytest.raises(gm.GmError):
+            e.serve(slots=99)
