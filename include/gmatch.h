@@ -302,6 +302,72 @@ gm_status gm_serve_stats(gm_server *server, int64_t *pending, int64_t *running, 
  * server; results not yet polled are dropped.  NULL is ignored. */
 gm_status gm_serve_close(gm_server *server);
 
+/* ------------------------------------------------------------------------
+ * Learned matching order.
+ *
+ * The matching order decides the size of the search space (Sec. 2.2; the
+ * paper takes RI's heuristic order, Sec. 3).  Any connected order gives the
+ * same matches, so an order can be chosen for speed alone: a cost model
+ * predicts the log2 search time of (query, order) pairs from features of the
+ * query and of the data graph, and the engine runs the candidate predicted
+ * cheapest, keeping the heuristic order unless another is predicted faster by
+ * a margin.  The model is trained on search times the engine itself measures.
+ * ------------------------------------------------------------------------ */
+
+/* Length of a feature vector. */
+#define GM_ORDER_FEATURES 192
+
+/* Features of query qid under `order` (NULL = its current order) into
+ * out[GM_ORDER_FEATURES]: for each position i < 32 of the order, five values
+ * at out[5 i ..] (zeros past k): log2(1 + candidates of the query vertex in
+ * G, by label and degree) / 24, its query degree / 8, its backward neighbours
+ * / 8, log2(1 + the smallest candidate count among its backward neighbours) /
+ * 24, and log2(1 + vertices of G with its label) / 24; then out[160] = k / 32,
+ * out[161] = edges / 64 and 30 zeros. */
+gm_status gm_order_features(gm_engine *engine, int32_t qid, const int32_t *order, float *out);
+
+/* Candidate orders of query qid into orders[max_orders * k], *n_out of them:
+ * the heuristic order first; then the connected order that always takes the
+ * vertex with the fewest candidates among those adjacent to the placed ones
+ * (starting from the fewest overall), if different; then random connected
+ * orders (seeded by `seed`), without duplicates. */
+gm_status gm_candidate_orders(gm_engine *engine, int32_t qid, int32_t max_orders, uint64_t seed, int32_t *orders,
+                              int32_t *n_out);
+
+/* The cost model: a perceptron with two hidden relu layers of `hidden` units
+ * (a multiple of 32) and one output, bf16 weights and fp32 accumulation on the
+ * matrix cores.  Inputs are padded to a multiple of 32.  Created on a HIP
+ * device with weights drawn from `seed` (He initialisation). */
+typedef struct gm_model gm_model;
+gm_status gm_model_create(int32_t device, int32_t in_dim, int32_t hidden, uint64_t seed, gm_model **out);
+void gm_model_destroy(gm_model *model);
+
+/* Predictions for n rows of `dim` features (x[n * dim], host) into y[n]. */
+gm_status gm_model_predict(gm_model *model, const float *x, int32_t n, int32_t dim, float *y);
+
+/* Adam on the mean squared error against t[n] (host arrays), `epochs` passes
+ * in shuffled minibatches of `batch` rows (seeded); *mean_loss (may be NULL)
+ * receives the last pass's mean squared error. */
+gm_status gm_model_train(gm_model *model, const float *x, const float *t, int32_t n, int32_t dim, int32_t epochs,
+                         int32_t batch, float lr, uint64_t seed, float *mean_loss);
+
+/* fp32 master weights: w1[in_dim_padded * hidden] (row-major, input-major),
+ * b1[hidden], w2[hidden * hidden], b2[hidden], w3[hidden], b3[1].  Setting them
+ * also resets the optimiser state. */
+gm_status gm_model_get_params(const gm_model *model, float *w1, float *b1, float *w2, float *b2, float *w3, float *b3);
+gm_status gm_model_set_params(gm_model *model, const float *w1, const float *b1, const float *w2, const float *b2,
+                              const float *w3, const float *b3);
+const char *gm_model_last_error(const gm_model *model);
+
+/* Choose the order of query qid with the model: predict every candidate of
+ * gm_candidate_orders(max_orders, seed); set the one predicted cheapest if its
+ * prediction is below the heuristic order's by more than `margin` (log2
+ * units), else keep the heuristic order.  *chosen receives the candidate's
+ * index (0 = heuristic) and predicted[max_orders] (may be NULL) the
+ * predictions. */
+gm_status gm_choose_order(gm_engine *engine, gm_model *model, int32_t qid, int32_t max_orders, uint64_t seed,
+                          float margin, int32_t *chosen, float *predicted);
+
 /* Forget a query; its id is not reused. */
 gm_status gm_free_query(gm_engine *engine, int32_t qid);
 

@@ -24,7 +24,12 @@ GM_DONE, GM_CAPPED, GM_TIMEOUT = 0, 1, 2
 ABI_FUNCTIONS = ("gm_create", "gm_destroy", "gm_load_graph", "gm_load_query", "gm_set_order",
                  "gm_get_order", "gm_count", "gm_enumerate", "gm_count_batch", "gm_tune_batch",
                  "gm_get_options", "gm_serve_open", "gm_serve_submit", "gm_serve_poll", "gm_serve_stats",
-                 "gm_serve_close", "gm_free_query", "gm_last_error")
+                 "gm_serve_close", "gm_order_features", "gm_candidate_orders", "gm_model_create",
+                 "gm_model_destroy", "gm_model_predict", "gm_model_train", "gm_model_get_params",
+                 "gm_model_set_params", "gm_model_last_error", "gm_choose_order", "gm_free_query",
+                 "gm_last_error")
+
+ORDER_FEATURES = 192
 
 
 class GmError(RuntimeError):
@@ -209,12 +214,26 @@ def load_library():
     lib.gm_serve_stats.argtypes = [p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_int64)]
     lib.gm_serve_close.argtypes = [p]
+    lib.gm_order_features.argtypes = [p, i32, p, p]
+    lib.gm_candidate_orders.argtypes = [p, i32, i32, u64, p, ctypes.POINTER(i32)]
+    lib.gm_model_create.argtypes = [i32, i32, i32, u64, ctypes.POINTER(p)]
+    lib.gm_model_destroy.argtypes = [p]
+    lib.gm_model_destroy.restype = None
+    lib.gm_model_predict.argtypes = [p, p, i32, i32, p]
+    lib.gm_model_train.argtypes = [p, p, p, i32, i32, i32, i32, ctypes.c_float, u64, ctypes.POINTER(ctypes.c_float)]
+    lib.gm_model_get_params.argtypes = [p, p, p, p, p, p, p]
+    lib.gm_model_set_params.argtypes = [p, p, p, p, p, p, p]
+    lib.gm_model_last_error.argtypes = [p]
+    lib.gm_model_last_error.restype = ctypes.c_char_p
+    lib.gm_choose_order.argtypes = [p, p, i32, i32, u64, ctypes.c_float, ctypes.POINTER(i32), p]
     lib.gm_free_query.argtypes = [p, i32]
     lib.gm_last_error.argtypes = [p]
     lib.gm_last_error.restype = ctypes.c_char_p
     for name in ("gm_create", "gm_load_graph", "gm_load_query", "gm_set_order", "gm_get_order", "gm_count",
                  "gm_enumerate", "gm_count_batch", "gm_tune_batch", "gm_get_options", "gm_serve_open",
-                 "gm_serve_submit", "gm_serve_poll", "gm_serve_stats", "gm_serve_close", "gm_free_query"):
+                 "gm_serve_submit", "gm_serve_poll", "gm_serve_stats", "gm_serve_close", "gm_order_features",
+                 "gm_candidate_orders", "gm_model_create", "gm_model_predict", "gm_model_train",
+                 "gm_model_get_params", "gm_model_set_params", "gm_choose_order", "gm_free_query"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -338,6 +357,27 @@ class Engine:
         self._check(self._lib.gm_get_options(self._h, ctypes.byref(o)))
         return o
 
+    def order_features(self, qid: int, order: Optional[Sequence[int]] = None) -> np.ndarray:
+        out = np.zeros(ORDER_FEATURES, dtype=np.float32)
+        o = None if order is None else np.ascontiguousarray(order, dtype=np.int32)
+        self._check(self._lib.gm_order_features(self._h, qid, _ptr(o), _ptr(out)))
+        return out
+
+    def candidate_orders(self, qid: int, max_orders: int = 8, seed: int = 0) -> List[np.ndarray]:
+        k = self._k.get(qid, 32)
+        buf = np.zeros((max_orders, k), dtype=np.int32)
+        n = ctypes.c_int32()
+        self._check(self._lib.gm_candidate_orders(self._h, qid, max_orders, seed, _ptr(buf), ctypes.byref(n)))
+        return [buf[i].copy() for i in range(n.value)]
+
+    def choose_order(self, model: "Model", qid: int, max_orders: int = 8, seed: int = 0, margin: float = 0.0):
+        """Let the model pick the order of qid; returns (chosen index, predictions)."""
+        chosen = ctypes.c_int32()
+        pred = np.zeros(max_orders, dtype=np.float32)
+        self._check(self._lib.gm_choose_order(self._h, model._h, qid, max_orders, seed, float(margin),
+                                              ctypes.byref(chosen), _ptr(pred)))
+        return chosen.value, pred
+
     def serve(self, slots: int = 0, max_batch: int = 0, waves_per_cu: int = 0, batch_streams: int = 0,
               max_pending: int = 0) -> "Server":
         """Open a continuous-batching server on this engine's resident graph."""
@@ -396,6 +436,69 @@ class Server:
         if getattr(self, "_h", None):
             h, self._h = self._h, None
             self._engine._check(self._lib.gm_serve_close(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Model:
+    """Order cost model (gm_model_*): a two-hidden-layer perceptron on the GPU."""
+
+    def __init__(self, in_dim: int = ORDER_FEATURES, hidden: int = 128, seed: int = 0, device: int = 0):
+        self._lib = load_library()
+        h = ctypes.c_void_p()
+        st = self._lib.gm_model_create(device, in_dim, hidden, seed, ctypes.byref(h))
+        if st != GM_OK:
+            raise GmError(st, "model creation failed")
+        self._h = h
+        self.in_dim = in_dim
+        self.padded = (in_dim + 31) // 32 * 32
+        self.hidden = hidden
+
+    def _check(self, st: int):
+        if st != GM_OK:
+            raise GmError(st, self._lib.gm_model_last_error(self._h).decode())
+
+    def predict(self, x) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.zeros(x.shape[0], dtype=np.float32)
+        self._check(self._lib.gm_model_predict(self._h, _ptr(x), x.shape[0], x.shape[1], _ptr(y)))
+        return y
+
+    def train(self, x, t, epochs: int = 10, batch: int = 256, lr: float = 1e-3, seed: int = 0) -> float:
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = np.ascontiguousarray(t, dtype=np.float32)
+        loss = ctypes.c_float()
+        self._check(self._lib.gm_model_train(self._h, _ptr(x), _ptr(t), x.shape[0], x.shape[1], epochs, batch,
+                                             float(lr), seed, ctypes.byref(loss)))
+        return float(loss.value)
+
+    def get_params(self):
+        D, H = self.padded, self.hidden
+        w1, b1 = np.zeros((D, H), np.float32), np.zeros(H, np.float32)
+        w2, b2 = np.zeros((H, H), np.float32), np.zeros(H, np.float32)
+        w3, b3 = np.zeros(H, np.float32), np.zeros(1, np.float32)
+        self._check(self._lib.gm_model_get_params(self._h, _ptr(w1), _ptr(b1), _ptr(w2), _ptr(b2), _ptr(w3),
+                                                  _ptr(b3)))
+        return w1, b1, w2, b2, w3, b3
+
+    def set_params(self, w1, b1, w2, b2, w3, b3) -> None:
+        arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (w1, b1, w2, b2, w3, b3)]
+        self._check(self._lib.gm_model_set_params(self._h, *[_ptr(a) for a in arrs]))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.gm_model_destroy(self._h)
+            self._h = None
 
     def __del__(self):
         try:

@@ -7,11 +7,13 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdio>
 #include <cstring>
 #include <deque>
 #include <mutex>
+#include <random>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -1111,6 +1113,97 @@ gm_status run_tune(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t cap, 
     return GM_OK;
 }
 
+// Candidates of a query vertex in G: vertices with its label and at least its
+// degree (0 when the label is absent from G); and G's vertices with its label.
+uint64_t vertex_candidates(const gm_engine *e, const QueryRec &q, int32_t u, uint64_t *with_label) {
+    *with_label = 0;
+    auto it = e->label_id.find(q.labels[u]);
+    if (it == e->label_id.end() || e->n == 0) return 0;
+    const int64_t b = e->lab_start[it->second], en = e->lab_start[it->second + 1];
+    *with_label = static_cast<uint64_t>(en - b);
+    const uint32_t need = static_cast<uint32_t>(popcount(q.adj[u]));
+    auto first = e->bylabel_deg.begin() + b;
+    auto pos = std::partition_point(first, e->bylabel_deg.begin() + en, [need](uint32_t d) { return d >= need; });
+    return static_cast<uint64_t>(pos - first);
+}
+
+void order_features(const gm_engine *e, const QueryRec &q, const int32_t *order, float *out) {
+    std::fill(out, out + GM_ORDER_FEATURES, 0.f);
+    uint64_t cand[kMaxK], lab[kMaxK];
+    for (int32_t u = 0; u < q.k; ++u) cand[u] = vertex_candidates(e, q, u, &lab[u]);
+    auto lg = [](uint64_t x) { return static_cast<float>(std::log2(1.0 + static_cast<double>(x))) / 24.f; };
+    uint32_t placed = 0;
+    int32_t edges = 0;
+    for (int32_t i = 0; i < q.k; ++i) {
+        const int32_t u = order[i];
+        const uint32_t back = q.adj[u] & placed;
+        uint64_t best = 0;
+        bool any = false;
+        for (uint32_t m = back; m; m &= m - 1) {
+            const uint64_t c = cand[__builtin_ctz(m)];
+            best = any ? std::min(best, c) : c;
+            any = true;
+        }
+        float *f = out + 5 * i;
+        f[0] = lg(cand[u]);
+        f[1] = static_cast<float>(popcount(q.adj[u])) / 8.f;
+        f[2] = static_cast<float>(popcount(back)) / 8.f;
+        f[3] = any ? lg(best) : 0.f;
+        f[4] = lg(lab[u]);
+        placed |= 1u << u;
+        edges += popcount(back);
+    }
+    out[160] = static_cast<float>(q.k) / 32.f;
+    out[161] = static_cast<float>(edges) / 64.f;
+}
+
+// Candidate orders: the heuristic order, the fewest-candidates greedy order,
+// then random connected orders, without duplicates.
+std::vector<std::vector<int32_t>> candidate_orders(const gm_engine *e, const QueryRec &q, int32_t max_orders,
+                                                   uint64_t seed) {
+    std::vector<std::vector<int32_t>> out;
+    if (max_orders < 1) return out;
+    auto add = [&](const std::vector<int32_t> &o) {
+        for (const auto &x : out)
+            if (x == o) return;
+        out.push_back(o);
+    };
+    add(ri_order(q.k, q.adj));
+    uint64_t cand[kMaxK], lab;
+    for (int32_t u = 0; u < q.k; ++u) cand[u] = vertex_candidates(e, q, u, &lab);
+    {
+        std::vector<int32_t> o;
+        uint32_t placed = 0;
+        for (int32_t i = 0; i < q.k; ++i) {
+            int32_t best = -1;
+            for (int32_t u = 0; u < q.k; ++u) {
+                if ((placed >> u) & 1u) continue;
+                if (i > 0 && (q.adj[u] & placed) == 0) continue;
+                if (best < 0 || cand[u] < cand[best]) best = u;
+            }
+            o.push_back(best);
+            placed |= 1u << best;
+        }
+        if (static_cast<int32_t>(out.size()) < max_orders) add(o);
+    }
+    std::mt19937_64 rng(seed ^ (0x9e3779b97f4a7c15ull * static_cast<uint64_t>(q.k + 1)));
+    for (int32_t tries = 0; static_cast<int32_t>(out.size()) < max_orders && tries < 8 * max_orders; ++tries) {
+        std::vector<int32_t> o;
+        uint32_t placed = 0;
+        for (int32_t i = 0; i < q.k; ++i) {
+            int32_t pick[kMaxK], np = 0;
+            for (int32_t u = 0; u < q.k; ++u)
+                if (!((placed >> u) & 1u) && (i == 0 || (q.adj[u] & placed))) pick[np++] = u;
+            const int32_t u = pick[rng() % static_cast<uint64_t>(np)];
+            o.push_back(u);
+            placed |= 1u << u;
+        }
+        add(o);
+    }
+    if (static_cast<int32_t>(out.size()) > max_orders) out.resize(static_cast<size_t>(max_orders));
+    return out;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1646,6 +1739,59 @@ gm_status gm_serve_close(gm_server *s) {
     e->servers.fetch_sub(1);
     delete s;
     return st;
+}
+
+gm_status gm_order_features(gm_engine *e, int32_t qid, const int32_t *order, float *out) {
+    if (!e) return GM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (!out) return e->fail(GM_ERR_ARG, "out is null");
+    const QueryRec *q = nullptr;
+    gm_status st = get_query(e, qid, &q);
+    if (st) return st;
+    if (!e->has_graph) return e->fail(GM_ERR_STATE, "no data graph loaded");
+    if (order && !connected_order(q->k, q->adj, order))
+        return e->fail(GM_ERR_ORDER, "order must be a connected permutation");
+    order_features(e, *q, order ? order : q->order.data(), out);
+    return GM_OK;
+}
+
+gm_status gm_candidate_orders(gm_engine *e, int32_t qid, int32_t max_orders, uint64_t seed, int32_t *orders,
+                              int32_t *n_out) {
+    if (!e) return GM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (!orders || !n_out || max_orders < 1) return e->fail(GM_ERR_ARG, "bad arguments");
+    const QueryRec *q = nullptr;
+    gm_status st = get_query(e, qid, &q);
+    if (st) return st;
+    if (!e->has_graph) return e->fail(GM_ERR_STATE, "no data graph loaded");
+    const auto cands = candidate_orders(e, *q, max_orders, seed);
+    for (size_t i = 0; i < cands.size(); ++i) std::copy(cands[i].begin(), cands[i].end(), orders + i * q->k);
+    *n_out = static_cast<int32_t>(cands.size());
+    return GM_OK;
+}
+
+gm_status gm_choose_order(gm_engine *e, gm_model *model, int32_t qid, int32_t max_orders, uint64_t seed, float margin,
+                          int32_t *chosen, float *predicted) {
+    if (!e) return GM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (!model || !chosen || max_orders < 1) return e->fail(GM_ERR_ARG, "bad arguments");
+    const QueryRec *q = nullptr;
+    gm_status st = get_query(e, qid, &q);
+    if (st) return st;
+    if (!e->has_graph) return e->fail(GM_ERR_STATE, "no data graph loaded");
+    const auto cands = candidate_orders(e, *q, max_orders, seed);
+    std::vector<float> x(cands.size() * GM_ORDER_FEATURES), y(cands.size());
+    for (size_t i = 0; i < cands.size(); ++i) order_features(e, *q, cands[i].data(), x.data() + i * GM_ORDER_FEATURES);
+    st = gm_model_predict(model, x.data(), static_cast<int32_t>(cands.size()), GM_ORDER_FEATURES, y.data());
+    if (st) return e->fail(st, std::string("model: ") + gm_model_last_error(model));
+    size_t best = 0;
+    for (size_t i = 1; i < cands.size(); ++i)
+        if (y[i] < y[best]) best = i;
+    if (!(y[best] < y[0] - margin)) best = 0;  // keep the heuristic order unless clearly beaten
+    e->queries[qid].order = cands[best];
+    *chosen = static_cast<int32_t>(best);
+    if (predicted) std::copy(y.begin(), y.end(), predicted);
+    return GM_OK;
 }
 
 gm_status gm_free_query(gm_engine *e, int32_t qid) {
