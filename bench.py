@@ -176,7 +176,16 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="medium", choices=["medium", "small", "large", "batch", "serve"],
+    ap.add_argument("--train-queries", type=int, default=6250,
+                    help="learned: training queries per run (8 candidate orders each, half on each graph)")
+    ap.add_argument("--eval-queries", type=int, default=1000, help="learned: held-out queries")
+    ap.add_argument("--eval-scale", type=int, default=24, choices=[20, 22, 24], help="learned: held-out graph")
+    ap.add_argument("--train-cap", type=int, default=1_000_000, help="learned: cap of the training runs")
+    ap.add_argument("--train-limit", type=float, default=0.05, help="learned: time limit of the training runs (s)")
+    ap.add_argument("--eval-cap", type=int, default=1_000_000, help="learned: cap of the evaluation runs")
+    ap.add_argument("--eval-limit", type=float, default=1.0, help="learned: time limit of the evaluation runs (s)")
+    ap.add_argument("--workload", default="medium",
+                    choices=["medium", "small", "large", "batch", "serve", "learned"],
                     help="batch = 10,000 mixed-size queries in shared launches (autotuned); "
                          "serve = the same queries as a Poisson request stream through the server")
     ap.add_argument("--load", type=float, default=0.7,
@@ -242,6 +251,8 @@ def main() -> int:
         return bench_batch(args, gm)
     if args.workload == "serve":
         return bench_serve(args, gm)
+    if args.workload == "learned":
+        return bench_learned(args, gm)
 
     t = time.time()
     w = make_workload(args.workload, args.queries, args.query_stride)
@@ -526,6 +537,109 @@ def bench_serve(args, gm) -> int:
         "tuning": tuning,
     }
     e.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_learned(args, gm) -> int:
+    """Learned matching order: (query, order) search times measured by the engine
+    on R-MAT scale-20 and scale-22 graphs train the cost model; held-out queries
+    on a larger graph then run with the heuristic order and with the order the
+    model picks.  Counts must not change; total time and p99 are compared."""
+    from paper_2604_10601_amd import workloads as wl
+    # training runs: a bad random order only needs to be seen as slow, so a short limit
+    train_cap, train_limit, cap, limit, n_orders = args.train_cap, args.train_limit, args.eval_cap, args.eval_limit, 8
+    xs, ys = [], []
+    half = max(1, args.train_queries // 2)
+    for scale, seed in ((20, 60), (22, 61)):
+        t = time.time()
+        g = wl.rmat20_graph() if scale == 20 else wl.rmat22_graph()
+        qs = wl.walk_queries(g, wl.order_sizes(half, seed), seed)
+        log(f"training graph scale {scale}: |E|={g.num_edges}, {len(qs)} queries ({time.time() - t:.1f} s)")
+        with gm.Engine(device=0) as e:
+            e.load(g)
+            t = time.time()
+            for i, q in enumerate(qs):
+                qid = e.add(q)
+                for o in e.candidate_orders(qid, max_orders=n_orders, seed=i):
+                    e.set_order(qid, o)
+                    r = e.count(qid, cap=train_cap, time_limit_s=train_limit)
+                    xs.append(e.order_features(qid))
+                    ys.append(np.log2(max(r.search_ms, 1e-3)))
+                e.free_query(qid)
+                if (i + 1) % 25 == 0:
+                    log(f"  scale {scale}: {i + 1} queries, {len(ys)} samples ({time.time() - t:.0f} s)")
+        del g
+    x = np.stack(xs).astype(np.float32)
+    y = np.asarray(ys, dtype=np.float32)
+    rng = np.random.default_rng(7)
+    perm = rng.permutation(len(y))
+    n_val = max(1, len(y) // 10)
+    val, tr = perm[:n_val], perm[n_val:]
+    model = gm.Model(gm.ORDER_FEATURES, 128, seed=1)
+    t = time.time()
+    loss = model.train(x[tr], y[tr], epochs=40, batch=256, lr=1e-3, seed=3)
+    pv = model.predict(x[val])
+    val_mse = float(np.mean((pv - y[val]) ** 2))
+    log(f"model: {len(tr)} training samples, last-epoch mse {loss:.3f}, held-out mse {val_mse:.3f} "
+        f"(target variance {float(np.var(y)):.3f}), {time.time() - t:.1f} s")
+    # held-out queries on the evaluation graph
+    t = time.time()
+    g = {20: wl.rmat20_graph, 22: wl.rmat22_graph, 24: wl.rmat24_graph}[args.eval_scale]()
+    qs = wl.walk_queries(g, wl.order_sizes(args.eval_queries, 62), 62)
+    log(f"evaluation graph scale {args.eval_scale}: |E|={g.num_edges}, {len(qs)} queries ({time.time() - t:.1f} s)")
+    plain, learned, chosen, same = [], [], 0, True
+    with gm.Engine(device=0) as e:
+        e.load(g)
+        for i, q in enumerate(qs):
+            qid = e.add(q)
+            heuristic = e.get_order(qid)
+            c, _ = e.choose_order(model, qid, max_orders=n_orders, seed=i, margin=0.25)
+            mine = e.get_order(qid)
+            # alternate which order runs first, so neither gains from the other's warm caches
+            runs = {}
+            for which in (("h", "l") if i % 2 == 0 else ("l", "h")):
+                e.set_order(qid, heuristic if which == "h" else mine)
+                runs[which] = e.count(qid, cap=cap, time_limit_s=limit)
+            a, b = runs["h"], runs["l"]
+            chosen += c != 0
+            if a.outcome != gm.GM_TIMEOUT and b.outcome != gm.GM_TIMEOUT:
+                same &= (a.count, a.outcome) == (b.count, b.outcome)
+            plain.append(a)
+            learned.append(b)
+            e.free_query(qid)
+            if (i + 1) % 25 == 0:
+                log(f"  evaluated {i + 1} queries ({time.time() - t:.0f} s)")
+    model.close()
+    lp = np.array([r.search_ms for r in plain])
+    ll = np.array([r.search_ms for r in learned])
+    out = {
+        "metric": "query-set time (ms), learned vs heuristic order",
+        "value": float(ll.sum()),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": float(ll.sum()),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32 search, bf16/fp32 model",
+        "data": "synthetic",
+        "config": {"workload": f"learned order: train R-MAT 20+22, evaluate R-MAT {args.eval_scale}",
+                   "train_queries": 2 * half, "orders_per_query": n_orders, "samples": int(len(y)),
+                   "train_cap": train_cap, "train_time_limit_s": train_limit, "eval_queries": len(qs), "cap": cap,
+                   "time_limit_s": limit, "margin_log2": 0.25},
+        "heuristic": {"total_ms": float(lp.sum()), "p50_ms": float(np.percentile(lp, 50)),
+                      "p99_ms": float(np.percentile(lp, 99)),
+                      "timeouts": int(sum(r.outcome == gm.GM_TIMEOUT for r in plain))},
+        "learned": {"total_ms": float(ll.sum()), "p50_ms": float(np.percentile(ll, 50)),
+                    "p99_ms": float(np.percentile(ll, 99)),
+                    "timeouts": int(sum(r.outcome == gm.GM_TIMEOUT for r in learned)),
+                    "queries_with_another_order": int(chosen)},
+        "model": {"train_mse": loss, "heldout_mse": val_mse, "target_variance": float(np.var(y))},
+        "same_counts": bool(same),
+    }
     print(json.dumps(out), flush=True)
     return 0
 

@@ -368,11 +368,24 @@ const char *gm_model_last_error(const gm_model *model);
 gm_status gm_choose_order(gm_engine *engine, gm_model *model, int32_t qid, int32_t max_orders, uint64_t seed,
                           float margin, int32_t *chosen, float *predicted);
 
+/* Opt-in symmetry breaking.  By default every injective map is counted (Def.
+ * 1).  The paper's comparison runs give all systems the same symmetry-breaking
+ * strategy (App. A); with enable = 1, query qid counts each class of matches
+ * that differ only by an automorphism of Q (a permutation of V(Q) keeping its
+ * labels and edges) once.  Conditions M(v) < M(u) chosen along a stabilizer
+ * chain (Grochow and Kellis 2007) keep exactly one map per class, so the
+ * count with it on times |Aut(Q)| is the count with it off (enumeration lists
+ * one representative per class).  *aut_size (may be NULL) receives |Aut(Q)|,
+ * saturating at 2^64 - 1.  GM_ERR_QUERY if the automorphism search of Q
+ * exceeds its budget (then the mode stays off). */
+gm_status gm_set_symmetry_breaking(gm_engine *engine, int32_t qid, int32_t enable, uint64_t *aut_size);
+
 /* Forget a query; its id is not reused. */
 gm_status gm_free_query(gm_engine *engine, int32_t qid);
 
 /* Message describing the last failed call on this engine (NULL: the last failed
- * gm_create on this thread).  The pointer stays valid until the next call. */
+ * gm_create on this thread).  The text is copied for the calling thread; the
+ * pointer stays valid until that thread calls gm_last_error again. */
 const char *gm_last_error(const gm_engine *engine);
 
 #ifdef __cplusplus

@@ -26,7 +26,7 @@ ABI_FUNCTIONS = ("gm_create", "gm_destroy", "gm_load_graph", "gm_load_query", "g
                  "gm_get_options", "gm_serve_open", "gm_serve_submit", "gm_serve_poll", "gm_serve_stats",
                  "gm_serve_close", "gm_order_features", "gm_candidate_orders", "gm_model_create",
                  "gm_model_destroy", "gm_model_predict", "gm_model_train", "gm_model_get_params",
-                 "gm_model_set_params", "gm_model_last_error", "gm_choose_order", "gm_free_query",
+                 "gm_model_set_params", "gm_model_last_error", "gm_choose_order", "gm_set_symmetry_breaking", "gm_free_query",
                  "gm_last_error")
 
 ORDER_FEATURES = 192
@@ -226,6 +226,7 @@ def load_library():
     lib.gm_model_last_error.argtypes = [p]
     lib.gm_model_last_error.restype = ctypes.c_char_p
     lib.gm_choose_order.argtypes = [p, p, i32, i32, u64, ctypes.c_float, ctypes.POINTER(i32), p]
+    lib.gm_set_symmetry_breaking.argtypes = [p, i32, i32, ctypes.POINTER(u64)]
     lib.gm_free_query.argtypes = [p, i32]
     lib.gm_last_error.argtypes = [p]
     lib.gm_last_error.restype = ctypes.c_char_p
@@ -233,7 +234,8 @@ def load_library():
                  "gm_enumerate", "gm_count_batch", "gm_tune_batch", "gm_get_options", "gm_serve_open",
                  "gm_serve_submit", "gm_serve_poll", "gm_serve_stats", "gm_serve_close", "gm_order_features",
                  "gm_candidate_orders", "gm_model_create", "gm_model_predict", "gm_model_train",
-                 "gm_model_get_params", "gm_model_set_params", "gm_choose_order", "gm_free_query"):
+                 "gm_model_get_params", "gm_model_set_params", "gm_choose_order", "gm_set_symmetry_breaking",
+                 "gm_free_query"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -377,6 +379,12 @@ class Engine:
         self._check(self._lib.gm_choose_order(self._h, model._h, qid, max_orders, seed, float(margin),
                                               ctypes.byref(chosen), _ptr(pred)))
         return chosen.value, pred
+
+    def set_symmetry_breaking(self, qid: int, enable: bool = True) -> int:
+        """Count one map per automorphism class of the query; returns |Aut(Q)|."""
+        aut = ctypes.c_uint64()
+        self._check(self._lib.gm_set_symmetry_breaking(self._h, qid, int(enable), ctypes.byref(aut)))
+        return aut.value
 
     def serve(self, slots: int = 0, max_batch: int = 0, waves_per_cu: int = 0, batch_streams: int = 0,
               max_pending: int = 0) -> "Server":

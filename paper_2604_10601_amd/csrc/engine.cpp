@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <mutex>
 #include <random>
 #include <string>
@@ -38,7 +39,92 @@ struct QueryRec {
     std::vector<int32_t> labels;
     uint32_t adj[kMaxK] = {};
     std::vector<int32_t> order;
+    // symmetry breaking (opt-in): bit u of less[v] requires M(v) < M(u)
+    bool sb = false;
+    uint32_t less[kMaxK] = {};
+    uint64_t aut = 1;  // |Aut(Q)| (saturating)
 };
+
+// Is there an automorphism of q (a permutation of its vertices preserving
+// labels and edges) that fixes every vertex in `fixed` and maps v to u?
+// Depth-first over the vertices in breadth-first order from v; `budget` bounds
+// the nodes searched (false with budget exhausted when it runs out).
+bool automorphism_exists(const QueryRec &q, uint32_t fixed, int32_t v, int32_t u, long long &budget) {
+    const int32_t k = q.k;
+    int32_t seq[kMaxK], n = 0;
+    uint32_t seen = 1u << v;
+    seq[n++] = v;
+    for (int32_t h = 0; h < n; ++h)
+        for (uint32_t m = q.adj[seq[h]] & ~seen; m; m &= m - 1) {
+            seen |= 1u << __builtin_ctz(m);
+            seq[n++] = __builtin_ctz(m);
+        }
+    for (int32_t x = 0; x < k; ++x)
+        if (!((seen >> x) & 1u)) seq[n++] = x;  // (q is connected: not reached)
+    int32_t img[kMaxK];
+    for (int32_t x = 0; x < k; ++x) img[x] = -1;
+    uint32_t used = 0;
+    auto fits = [&](int32_t x, int32_t y) {
+        if ((used >> y) & 1u) return false;
+        if (q.labels[x] != q.labels[y] || __builtin_popcount(q.adj[x]) != __builtin_popcount(q.adj[y])) return false;
+        if (((fixed >> x) & 1u) && x != y) return false;
+        if (((fixed >> y) & 1u) && x != y) return false;
+        for (int32_t z = 0; z < k; ++z)
+            if (img[z] >= 0 && (((q.adj[x] >> z) & 1u) != ((q.adj[y] >> img[z]) & 1u))) return false;
+        return true;
+    };
+    std::function<bool(int32_t)> go = [&](int32_t i) -> bool {
+        if (i == k) return true;
+        if (--budget < 0) return false;
+        const int32_t x = seq[i];
+        for (int32_t y = (i == 0 ? u : 0); y < (i == 0 ? u + 1 : k); ++y) {
+            if (!fits(x, y)) continue;
+            img[x] = y;
+            used |= 1u << y;
+            if (go(i + 1)) return true;
+            img[x] = -1;
+            used &= ~(1u << y);
+            if (budget < 0) return false;
+        }
+        return false;
+    };
+    return go(0);
+}
+
+// Symmetry-breaking conditions along a stabilizer chain (Grochow and Kellis
+// 2007): while the group fixing the chosen vertices is not trivial, take the
+// vertex with the largest orbit under it (the smallest id on ties), require it
+// to map below every other vertex of that orbit, and fix it.  Exactly one map
+// of every class {M o a : a in Aut(Q)} meets all conditions, and |Aut(Q)| is
+// the product of the orbit sizes.  Returns false if the search budget ran out.
+bool symmetry_conditions(QueryRec &q) {
+    long long budget = 20000000;
+    std::fill(q.less, q.less + kMaxK, 0u);
+    q.aut = 1;
+    uint32_t fixed = 0;
+    for (;;) {
+        int32_t best = -1;
+        uint32_t best_orbit = 0;
+        for (int32_t v = 0; v < q.k; ++v) {
+            if ((fixed >> v) & 1u) continue;
+            uint32_t orbit = 1u << v;
+            for (int32_t u = 0; u < q.k; ++u) {
+                if (u == v || ((fixed >> u) & 1u)) continue;
+                if (automorphism_exists(q, fixed, v, u, budget)) orbit |= 1u << u;
+                if (budget < 0) return false;
+            }
+            if (best < 0 || __builtin_popcount(orbit) > __builtin_popcount(best_orbit)) {
+                best = v;
+                best_orbit = orbit;
+            }
+        }
+        if (best < 0 || __builtin_popcount(best_orbit) == 1) return true;
+        q.less[best] |= best_orbit & ~(1u << best);
+        const uint64_t o = static_cast<uint64_t>(__builtin_popcount(best_orbit));
+        q.aut = q.aut > UINT64_MAX / o ? UINT64_MAX : q.aut * o;
+        fixed |= 1u << best;
+    }
+}
 
 int popcount(uint32_t x) { return __builtin_popcount(x); }
 
@@ -168,9 +254,16 @@ struct gm_engine {
     int num_cu = 0;
     long long wall_khz = 0;
 
+    // the message of the last failure; a server's worker thread may set it too
+    mutable std::mutex err_mu;
     gm_status fail(gm_status s, const std::string &msg) const {
+        std::lock_guard<std::mutex> lk(err_mu);
         err = msg;
         return s;
+    }
+    std::string last_error() const {
+        std::lock_guard<std::mutex> lk(err_mu);
+        return err;
     }
 };
 
@@ -403,6 +496,13 @@ Plan make_plan(const gm_engine *e, const QueryRec &q, bool *label_missing) {
         for (int32_t j = 0; j < i; ++j)
             if ((q.adj[u] >> q.order[j]) & 1u) b |= 1u << j;
         plan.bwd[i] = b;
+        if (q.sb) {
+            for (int32_t j = 0; j < i; ++j) {
+                const int32_t w = q.order[j];
+                if ((q.less[w] >> u) & 1u) plan.sb_lt[i] |= 1u << j;  // M(w) < M(u)
+                if ((q.less[u] >> w) & 1u) plan.sb_gt[i] |= 1u << j;  // M(u) < M(w)
+            }
+        }
     }
     return plan;
 }
@@ -1286,7 +1386,7 @@ void serve_loop(gm_server *s) {
             lk.lock();
             if (st && !s->error) {
                 s->error = st;
-                s->err = e->err;
+                s->err = e->last_error();
             }
             publish(s, sl, s->now_ms(), i);
             progress = true;
@@ -1324,7 +1424,7 @@ void serve_loop(gm_server *s) {
             lk.lock();
             if (st && !s->error) {
                 s->error = st;
-                s->err = e->err;
+                s->err = e->last_error();
             }
             if (st || !sl.gl.launched) {  // nothing to run (or a failure): results as they stand
                 publish(s, sl, s->now_ms(), i);
@@ -1794,6 +1894,23 @@ gm_status gm_choose_order(gm_engine *e, gm_model *model, int32_t qid, int32_t ma
     return GM_OK;
 }
 
+gm_status gm_set_symmetry_breaking(gm_engine *e, int32_t qid, int32_t enable, uint64_t *aut_size) {
+    if (!e) return GM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(e->mu);
+    const QueryRec *cq = nullptr;
+    gm_status st = get_query(e, qid, &cq);
+    if (st) return st;
+    QueryRec &q = e->queries[qid];
+    if (!symmetry_conditions(q)) {
+        q.sb = false;
+        std::fill(q.less, q.less + kMaxK, 0u);
+        return e->fail(GM_ERR_QUERY, "automorphism search of the query exceeded its budget");
+    }
+    q.sb = enable != 0;
+    if (aut_size) *aut_size = q.aut;
+    return GM_OK;
+}
+
 gm_status gm_free_query(gm_engine *e, int32_t qid) {
     if (!e) return GM_ERR_ARG;
     std::lock_guard<std::mutex> lk(e->mu);
@@ -1806,7 +1923,9 @@ gm_status gm_free_query(gm_engine *e, int32_t qid) {
 
 const char *gm_last_error(const gm_engine *e) {
     if (!e) return g_create_error.c_str();
-    return e->err.c_str();
+    thread_local std::string copy;  // valid until this thread's next call
+    copy = e->last_error();
+    return copy.c_str();
 }
 
 }  // extern "C"

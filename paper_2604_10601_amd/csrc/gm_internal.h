@@ -52,6 +52,10 @@ struct Plan {
     // order of a depth-1 share: root r is pool row row0 + (r * perm_mul) mod rows
     // (perm_mul coprime to rows; 0 = rows in stored order)
     unsigned long long perm_mul;
+    // symmetry breaking (opt-in): bit j of sb_lt[i] requires M(phi[j]) < M(phi[i]),
+    // bit j of sb_gt[i] requires M(phi[i]) < M(phi[j]), for j < i
+    uint32_t sb_lt[kMaxK];
+    uint32_t sb_gt[kMaxK];
 };
 
 // Per-query results of a launch.  The count (atomics from every wavefront on

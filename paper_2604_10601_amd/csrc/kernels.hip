@@ -430,6 +430,7 @@ __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanP
     ok = ok && vi_lab(vi) == static_cast<uint32_t>(P->lab[l]) && vi_deg(vi) >= static_cast<uint32_t>(P->qdeg[l]);
     if (ok) {
         const uint32_t bw = P->bwd[l];
+        const uint32_t sblt = P->sb_lt[l], sbgt = P->sb_gt[l];  // symmetry-breaking conditions (usually none)
         const uint32_t js = S.cl[l * kWave + r.owner] & 0xffu;
         const uint32_t lab = a.loff_stride > 1 ? static_cast<uint32_t>(P->lab[l]) : 0u;
         uint32_t lo[kLists] = {0u, 0u, 0u, 0u};
@@ -439,6 +440,10 @@ __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanP
         for (int i = l - 1; i >= 0; --i) {
             const int32_t w = S.v[i * kWave + q];
             if (w == r.v) {
+                ok = false;
+                break;
+            }
+            if ((sblt | sbgt) && ((((sblt >> i) & 1u) && !(w < r.v)) || (((sbgt >> i) & 1u) && !(r.v < w)))) {
                 ok = false;
                 break;
             }

@@ -303,16 +303,12 @@ def _walk_queries(args) -> List[Query]:
     return [induced_query(g, random_walk_vertices(g, int(k), rng)) for k in sizes]
 
 
-def batch_rmat20(num_queries: int = 10_000, seed: int = 40, g: Optional[Graph] = None,
-                 workers: int = 8) -> Workload:
-    """The R-MAT scale-20 graph with num_queries random-walk queries whose sizes are
-    uniform in 4..32 (labels copied from G, so they follow G's label frequencies).
-    Per query: cap 1e6 embeddings, 1 s time limit.  Queries are drawn in chunks of
-    500, chunk c with seed 1000 * seed + c, so the set does not depend on `workers`."""
+def walk_queries(g: Graph, sizes: Sequence[int], seed: int, workers: int = 8) -> List[Query]:
+    """Random-walk queries of the given sizes, drawn in chunks of 500 with seeds
+    1000 * seed + chunk (the set does not depend on `workers`)."""
     global _WALK_GRAPH
-    g = rmat20_graph() if g is None else g
-    sizes = _rng(seed).integers(4, 33, size=num_queries)
-    chunks = [(sizes[c:c + 500], 1000 * seed + c // 500) for c in range(0, num_queries, 500)]
+    sizes = np.asarray(sizes)
+    chunks = [(sizes[c:c + 500], 1000 * seed + c // 500) for c in range(0, sizes.shape[0], 500)]
     _WALK_GRAPH = g
     try:
         if workers > 1 and len(chunks) > 1:
@@ -323,5 +319,27 @@ def batch_rmat20(num_queries: int = 10_000, seed: int = 40, g: Optional[Graph] =
             parts = [_walk_queries(c) for c in chunks]
     finally:
         _WALK_GRAPH = None
-    qs = [q for part in parts for q in part]
+    return [q for part in parts for q in part]
+
+
+def rmat22_graph() -> Graph:
+    """R-MAT scale 22, edge factor 16, 16 Zipf(1.0) labels (the scale-20 recipe, larger)."""
+    row_ptr, col = rmat(22, 16, seed=52)
+    return Graph(row_ptr, col, zipf_labels(1 << 22, 16, 1.0, seed=53))
+
+
+def order_sizes(n: int, seed: int) -> np.ndarray:
+    """Sizes uniform in 8..32 for the learned-order query sets."""
+    return _rng(seed).integers(8, 33, size=n)
+
+
+def batch_rmat20(num_queries: int = 10_000, seed: int = 40, g: Optional[Graph] = None,
+                 workers: int = 8) -> Workload:
+    """The R-MAT scale-20 graph with num_queries random-walk queries whose sizes are
+    uniform in 4..32 (labels copied from G, so they follow G's label frequencies).
+    Per query: cap 1e6 embeddings, 1 s time limit.  Queries are drawn in chunks of
+    500, chunk c with seed 1000 * seed + c, so the set does not depend on `workers`."""
+    g = rmat20_graph() if g is None else g
+    sizes = _rng(seed).integers(4, 33, size=num_queries)
+    qs = walk_queries(g, sizes, seed, workers)
     return Workload("rmat20_ef16_zipf16_q4-32_mixed", g, qs, cap=1_000_000, time_limit_s=1.0)
