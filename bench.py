@@ -208,6 +208,7 @@ def main() -> int:
     ap.add_argument("--stack-layout", type=int, default=0, help="0 auto, 1 full, 2 slim")
     ap.add_argument("--steal-threshold", type=int, default=0)
     ap.add_argument("--hub-cut", type=int, default=0, help="first-phase tasks per root (0 = default 16)")
+    ap.add_argument("--no-hub-bitmaps", action="store_true", help="bisect hub lists instead of reading bitmaps")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB device-to-device (counter calibration)")
     ap.add_argument("--summarize-stats", metavar="DIR", help="print the kernel table of a rocprofv3 --stats run")
@@ -262,7 +263,8 @@ def main() -> int:
         f"({time.time() - t:.1f} s to generate)")
     e = gm.Engine(device=0, tau=args.tau, waves_per_cu=args.waves_per_cu,
                   disable_stealing=args.disable_stealing, steal_threshold=args.steal_threshold,
-                  stack_layout=args.stack_layout, pool_hub_cut=args.hub_cut)
+                  stack_layout=args.stack_layout, pool_hub_cut=args.hub_cut,
+                  disable_hub_bitmaps=args.no_hub_bitmaps)
     e.load(w.graph)
     qids = [e.add(q) for q in w.queries]
     phis = [e.get_order(qid) for qid in qids]

@@ -96,7 +96,12 @@ typedef struct {
      * in its first-phase work item; the rest of a hub's tasks go to the second
      * phase.  0 = default 16. */
     int32_t pool_hub_cut;
-    int32_t reserved[3];
+    /* 1 = no adjacency bitmaps.  By default gm_load_graph keeps one bit per
+     * vertex of G for each of the highest-degree vertices (at least 256
+     * neighbours; at most 4096 of them and 1 GiB in all), and a membership test
+     * in such a list (slim stack layout) reads one bit instead of bisecting. */
+    int32_t disable_hub_bitmaps;
+    int32_t reserved[2];
 } gm_options;
 
 /* Result of one count or enumerate call. */

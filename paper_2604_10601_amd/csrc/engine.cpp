@@ -33,6 +33,11 @@ namespace {
 
 thread_local std::string g_create_error;
 
+// Hub bitmaps: vertices with at least this many neighbours, at most this many, in this many bytes.
+constexpr int64_t kHubMinDegree = 256;
+constexpr int32_t kMaxHubs = 4096;
+constexpr uint64_t kHubBytes = 1ull << 30;
+
 struct QueryRec {
     bool live = false;
     int32_t k = 0;
@@ -235,6 +240,10 @@ struct gm_engine {
     // vertices grouped by label, by degree descending within a label: the
     // candidates of a first query vertex are a prefix of its label's bucket
     int32_t *d_bylabel = nullptr;
+    int32_t *d_hub_id = nullptr;          // adjacency bitmaps of the highest-degree vertices
+    uint32_t *d_hub_bits = nullptr;
+    uint64_t hub_words = 0;
+    int32_t hubs = 0;
     std::vector<int64_t> lab_start;       // [labels + 1] bucket bounds
     std::vector<uint32_t> bylabel_deg;    // degree of each bucket entry (host copy)
 
@@ -390,7 +399,13 @@ void free_graph(gm_engine *e) {
     if (e->d_col) (void)hipFree(e->d_col);
     if (e->d_loff) (void)hipFree(e->d_loff);
     if (e->d_bylabel) (void)hipFree(e->d_bylabel);
+    if (e->d_hub_id) (void)hipFree(e->d_hub_id);
+    if (e->d_hub_bits) (void)hipFree(e->d_hub_bits);
     e->d_bylabel = nullptr;
+    e->d_hub_id = nullptr;
+    e->d_hub_bits = nullptr;
+    e->hub_words = 0;
+    e->hubs = 0;
     e->lab_start.clear();
     e->bylabel_deg.clear();
     e->d_vinfo = nullptr;
@@ -549,6 +564,9 @@ SearchArgs graph_args(const gm_engine *e, const LaunchCtx &c) {
     a.lcol = e->d_lcol;
     a.loff = e->d_loff;
     a.loff_stride = e->loff_stride;
+    a.hub_id = e->d_hub_id;
+    a.hub_bits = e->d_hub_bits;
+    a.hub_words = e->hub_words;
     a.ctl = c.d_ctl;
     a.plans = c.d_plans;
     a.qctl = c.d_qctl;
@@ -557,6 +575,13 @@ SearchArgs graph_args(const gm_engine *e, const LaunchCtx &c) {
 }
 
 unsigned long long items_of(unsigned long long rows) { return (rows + gm::kWave - 1) / gm::kWave; }
+
+// Does a plan carry symmetry-breaking conditions (then its launch takes the kernel that checks them)?
+bool has_sb(const Plan &p) {
+    for (int32_t i = 0; i < p.k; ++i)
+        if (p.sb_lt[i] | p.sb_gt[i]) return true;
+    return false;
+}
 
 // Two-phase pool: tasks of position 1 a root keeps in its first-phase item (default).
 constexpr uint32_t kHubCut = 16;
@@ -678,6 +703,7 @@ gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, ui
     a.voff = e->d_voff;
     a.vstart = e->d_vstart;
     a.slim = slim ? 1 : 0;
+    a.sb = has_sb(p) ? 1 : 0;
     a.budget = time_limit_s > 0
                    ? std::max<unsigned long long>(
                          1, static_cast<unsigned long long>(time_limit_s * 1000.0 * static_cast<double>(e->wall_khz)))
@@ -793,6 +819,7 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
     a.levels = q->k;
     a.budget = static_cast<unsigned long long>(budget_ticks);
     a.slim = use_slim(e, q->k) ? 1 : 0;
+    a.sb = has_sb(base_plan) ? 1 : 0;
     st = attach_stealing(e, e->lc, a);
     if (st) return st;
 
@@ -1001,6 +1028,8 @@ gm_status launch_group(gm_engine *e, LaunchCtx &c, const std::vector<Plan> &plan
     a.levels = levels;
     a.pool = e->d_bylabel;
     a.slim = use_slim(e, levels) ? 1 : 0;
+    a.sb = 0;
+    for (const Plan &p : c.h_plans) a.sb |= has_sb(p) ? 1 : 0;
     a.budget = 0;  // limits are per query (plan budgets)
     st = attach_stealing(e, c, a);
     if (!st) st = reset_stealing(e, c, a);
@@ -1589,6 +1618,36 @@ gm_status gm_load_graph(gm_engine *e, int32_t n, const int64_t *row_ptr, const i
         });
     std::vector<uint32_t> bylabel_deg(static_cast<size_t>(n));
     for (int32_t i = 0; i < n; ++i) bylabel_deg[i] = vinfo[bylabel[i]].y >> 8;
+    // Adjacency bitmaps of the highest-degree vertices (at least kHubMinDegree
+    // neighbours; at most kMaxHubs, within kHubBytes): a membership test in a hub's
+    // long list becomes one bit read instead of a bisection.
+    std::vector<int32_t> hub_id;
+    std::vector<uint32_t> hub_bits;
+    const uint64_t words = (static_cast<uint64_t>(n) + 31) / 32;
+    int32_t hubs = 0;
+    if (e->device >= 0 && !e->opt.disable_hub_bitmaps && n > 0) {
+        std::vector<int32_t> big;
+        for (int32_t v = 0; v < n; ++v)
+            if (row_ptr[v + 1] - row_ptr[v] >= kHubMinDegree) big.push_back(v);
+        std::sort(big.begin(), big.end(), [&](int32_t x, int32_t y) {
+            const int64_t dx = row_ptr[x + 1] - row_ptr[x], dy = row_ptr[y + 1] - row_ptr[y];
+            return dx != dy ? dx > dy : x < y;
+        });
+        const uint64_t fit = kHubBytes / (words * 4);
+        hubs = static_cast<int32_t>(std::min<uint64_t>({big.size(), static_cast<uint64_t>(kMaxHubs), fit}));
+        if (hubs > 0) {
+            hub_id.assign(static_cast<size_t>(n), -1);
+            hub_bits.assign(static_cast<size_t>(hubs) * words, 0u);
+            for (int32_t h = 0; h < hubs; ++h) hub_id[big[h]] = h;
+            parallel_ranges(hubs, [&](int64_t b, int64_t en) {
+                for (int64_t h = b; h < en; ++h) {
+                    const int32_t v = big[h];
+                    uint32_t *bits = &hub_bits[static_cast<size_t>(h) * words];
+                    for (int64_t p = row_ptr[v]; p < row_ptr[v + 1]; ++p) bits[col[p] >> 5] |= 1u << (col[p] & 31);
+                }
+            });
+        }
+    }
     if (e->device >= 0) {
         HIP_TRY(e, hipSetDevice(e->device));
         free_graph(e);
@@ -1601,6 +1660,10 @@ gm_status gm_load_graph(gm_engine *e, int32_t n, const int64_t *row_ptr, const i
             h = hipMalloc(reinterpret_cast<void **>(&e->d_lcol), std::max<uint64_t>(nnz, 1) * sizeof(int32_t));
         if (h == hipSuccess)
             h = hipMalloc(reinterpret_cast<void **>(&e->d_bylabel), std::max<size_t>(n, 1) * sizeof(int32_t));
+        if (h == hipSuccess && hubs > 0)
+            h = hipMalloc(reinterpret_cast<void **>(&e->d_hub_id), static_cast<size_t>(n) * sizeof(int32_t));
+        if (h == hipSuccess && hubs > 0)
+            h = hipMalloc(reinterpret_cast<void **>(&e->d_hub_bits), hub_bits.size() * sizeof(uint32_t));
         if (h != hipSuccess) {
             free_graph(e);
             return e->fail(GM_ERR_NOMEM, std::string("graph upload: ") + hipGetErrorString(h));
@@ -1612,6 +1675,12 @@ gm_status gm_load_graph(gm_engine *e, int32_t n, const int64_t *row_ptr, const i
         HIP_TRY(e, hipMemcpy(e->d_loff, loff.data(), loff.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
         if (stride > 1 && nnz) HIP_TRY(e, hipMemcpy(e->d_lcol, lcol.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
         if (n) HIP_TRY(e, hipMemcpy(e->d_bylabel, bylabel.data(), static_cast<size_t>(n) * sizeof(int32_t), hipMemcpyHostToDevice));
+        if (hubs > 0) {
+            HIP_TRY(e, hipMemcpy(e->d_hub_id, hub_id.data(), static_cast<size_t>(n) * sizeof(int32_t), hipMemcpyHostToDevice));
+            HIP_TRY(e, hipMemcpy(e->d_hub_bits, hub_bits.data(), hub_bits.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+            e->hub_words = words;
+            e->hubs = hubs;
+        }
     } else {
         free_graph(e);
         e->loff_stride = stride;

@@ -142,6 +142,9 @@ struct SearchArgs {
     const uint32_t *loff;      // label slice bounds: N(v) with label c is
                                // lcol[loff[v*stride + c] .. loff[v*stride + c + 1])
     int32_t loff_stride;       // labels + 1, or 1 when lists are not partitioned (c = 0)
+    const int32_t *hub_id;     // [n] index of v's adjacency bitmap, -1 if none (null: no bitmaps)
+    const uint32_t *hub_bits;  // hub h's bitmap: bit u of hub_bits[h * hub_words ..] set iff u in N(v)
+    unsigned long long hub_words;
     const Plan *plans;         // [nq] device copies of the query plans
     QCtl *qctl;                // [nq] per-query results
     int32_t nq;                // queries in this launch
@@ -160,6 +163,7 @@ struct SearchArgs {
     int32_t steal_slots;       // number of mailboxes (>= wavefronts launched)
     int32_t steal_threshold;
     int32_t slim;              // 1: slim stack layout (membership tests on label slices)
+    int32_t sb;                // 1: some plan of the launch has symmetry-breaking conditions
     int32_t measure_next;      // expansion: add the next level's size bound to ctl->measure
 };
 

@@ -393,12 +393,15 @@ __device__ __forceinline__ bool test_lists(const SearchArgs &a, uint32_t lab, ui
                                            uint32_t (&n)[kLists], int32_t v, uint32_t &probes, uint32_t &lookups) {
     if (SLIM) {
         uint32_t b0[kLists], b1[kLists];
+        int32_t hub[kLists];
 #pragma unroll
         for (int t = 0; t < kLists; ++t) {
             const bool use = n[t] != 0u;
-            const uint32_t *o = a.loff + static_cast<unsigned long long>(use ? lo[t] : 0u) * a.loff_stride + lab;
+            const uint32_t w = use ? lo[t] : 0u;
+            const uint32_t *o = a.loff + static_cast<unsigned long long>(w) * a.loff_stride + lab;
             b0[t] = use ? o[0] : 0u;
             b1[t] = use ? o[1] : 0u;
+            hub[t] = use && a.hub_id ? a.hub_id[w] : -1;  // read in the same round as the bounds
             lookups += use ? 1u : 0u;
         }
         bool empty = false;
@@ -411,6 +414,19 @@ __device__ __forceinline__ bool test_lists(const SearchArgs &a, uint32_t lab, ui
             }
         }
         if (empty) return false;
+        // a hub's list is answered by one bit of its adjacency bitmap, not by bisection
+        bool miss = false;
+#pragma unroll
+        for (int t = 0; t < kLists; ++t) {
+            if (n[t] != 0u && hub[t] >= 0) {
+                const uint32_t word =
+                    a.hub_bits[static_cast<unsigned long long>(hub[t]) * a.hub_words + (static_cast<uint32_t>(v) >> 5)];
+                miss |= ((word >> (static_cast<uint32_t>(v) & 31u)) & 1u) == 0u;
+                ++probes;
+                n[t] = 0u;
+            }
+        }
+        if (miss) return false;
         return in_all_lists(a.lcol, lo, n, v, probes);
     }
     return in_all_lists(a.col, lo, n, v, probes);
@@ -421,7 +437,7 @@ __device__ __forceinline__ bool test_lists(const SearchArgs &a, uint32_t lab, ui
 // other than the one the candidate came from.  The lists are collected during
 // the walk (kLists at a time, the slot index being the same in every lane) and
 // tested together.
-template <bool SLIM>
+template <bool SLIM, bool SB>
 __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanPtr P, int l, const Round &r,
                                         uint32_t lane, VInfo &vi, uint32_t &probes, uint32_t &lookups) {
     bool ok = lane < r.ntask;
@@ -430,7 +446,8 @@ __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanP
     ok = ok && vi_lab(vi) == static_cast<uint32_t>(P->lab[l]) && vi_deg(vi) >= static_cast<uint32_t>(P->qdeg[l]);
     if (ok) {
         const uint32_t bw = P->bwd[l];
-        const uint32_t sblt = P->sb_lt[l], sbgt = P->sb_gt[l];  // symmetry-breaking conditions (usually none)
+        // symmetry-breaking conditions: only in launches that hold a query with them
+        const uint32_t sblt = SB ? P->sb_lt[l] : 0u, sbgt = SB ? P->sb_gt[l] : 0u;
         const uint32_t js = S.cl[l * kWave + r.owner] & 0xffu;
         const uint32_t lab = a.loff_stride > 1 ? static_cast<uint32_t>(P->lab[l]) : 0u;
         uint32_t lo[kLists] = {0u, 0u, 0u, 0u};
@@ -443,7 +460,7 @@ __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanP
                 ok = false;
                 break;
             }
-            if ((sblt | sbgt) && ((((sblt >> i) & 1u) && !(w < r.v)) || (((sbgt >> i) & 1u) && !(r.v < w)))) {
+            if (SB && ((((sblt >> i) & 1u) && !(w < r.v)) || (((sbgt >> i) & 1u) && !(r.v < w)))) {
                 ok = false;
                 break;
             }
@@ -751,7 +768,7 @@ __device__ __forceinline__ unsigned int load_word(unsigned int *p) {
     return read_lane(v, 0);
 }
 
-template <int MODE, bool SLIM>
+template <int MODE, bool SLIM, bool SB>
 __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     const int levels = a.levels;
@@ -842,7 +859,7 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
                 r1.owner = lane;
                 r1.v = v;
                 VInfo vi;
-                const bool ok = process<SLIM>(S, a, P, 1, r1, lane, vi, t.probes_run, t.lookups_run);
+                const bool ok = process<SLIM, SB>(S, a, P, 1, r1, lane, vi, t.probes_run, t.lookups_run);
                 const uint64_t m = ballot(ok);
                 t.active += ntask;
                 t.issued += kWave;
@@ -1001,7 +1018,7 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
             t.active += r.ntask;
             t.issued += kWave;
             VInfo vi;
-            const bool ok = process<SLIM>(S, a, P, l, r, lane, vi, t.probes_run, t.lookups_run);
+            const bool ok = process<SLIM, SB>(S, a, P, l, r, lane, vi, t.probes_run, t.lookups_run);
             const uint64_t m = ballot(ok);
             if (MODE == kExpand) {
                 if (m) {
@@ -1238,11 +1255,11 @@ __global__ __launch_bounds__(256) void root_scan_kernel(const VInfo *__restrict_
     }
 }
 
-template <int MODE, bool SLIM>
+template <int MODE, bool SLIM, bool SB>
 int blocks_per_cu(int levels, int waves_per_cu) {
     const size_t lds_bytes = wave_lds_bytes(levels, MODE == kExpand, SLIM) * kWavesPerBlock;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel<MODE, SLIM>, kBlock, lds_bytes) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel<MODE, SLIM, SB>, kBlock, lds_bytes) !=
             hipSuccess ||
         per_cu < 1)
         per_cu = 1;
@@ -1253,17 +1270,28 @@ int blocks_per_cu(int levels, int waves_per_cu) {
     return per_cu;
 }
 
-template <int MODE, bool SLIM>
+template <int MODE, bool SLIM, bool SB>
 hipError_t launch_persistent(const SearchArgs &a, int num_cu, int waves_per_cu, hipStream_t s, int *grid_waves) {
     if (a.levels < 1 || a.levels > kMaxK || a.nq < 1 || !a.plans || !a.qctl || a.nstreams < 1 || !a.streams)
         return hipErrorInvalidValue;
     const size_t lds_bytes = wave_lds_bytes(a.levels, MODE == kExpand, SLIM) * kWavesPerBlock;
-    int blocks = num_cu * blocks_per_cu<MODE, SLIM>(a.levels, waves_per_cu);
+    int blocks = num_cu * blocks_per_cu<MODE, SLIM, SB>(a.levels, waves_per_cu);
     if (a.mail && blocks * kWavesPerBlock > a.steal_slots) blocks = a.steal_slots / kWavesPerBlock;  // one mailbox each
     if (blocks < 1) blocks = 1;
     if (grid_waves) *grid_waves = blocks * kWavesPerBlock;
-    hipLaunchKernelGGL((search_kernel<MODE, SLIM>), dim3(blocks), dim3(kBlock), lds_bytes, s, a);
+    hipLaunchKernelGGL((search_kernel<MODE, SLIM, SB>), dim3(blocks), dim3(kBlock), lds_bytes, s, a);
     return hipGetLastError();
+}
+
+// One of the twelve instantiations: mode x stack layout x symmetry conditions.
+template <int MODE>
+hipError_t launch_mode(const SearchArgs &a, int num_cu, int waves_per_cu, hipStream_t s, int *grid_waves) {
+    if (a.slim) {
+        if (a.sb) return launch_persistent<MODE, true, true>(a, num_cu, waves_per_cu, s, grid_waves);
+        return launch_persistent<MODE, true, false>(a, num_cu, waves_per_cu, s, grid_waves);
+    }
+    if (a.sb) return launch_persistent<MODE, false, true>(a, num_cu, waves_per_cu, s, grid_waves);
+    return launch_persistent<MODE, false, false>(a, num_cu, waves_per_cu, s, grid_waves);
 }
 
 }  // namespace
@@ -1280,24 +1308,19 @@ hipError_t launch_root_scan(const VInfo *vinfo, int32_t n, int32_t lab0, int32_t
 }
 
 hipError_t launch_expand(const SearchArgs &a, int num_cu, hipStream_t s) {
-    if (a.slim) return launch_persistent<kExpand, true>(a, num_cu, 0, s, nullptr);
-    return launch_persistent<kExpand, false>(a, num_cu, 0, s, nullptr);
+    return launch_mode<kExpand>(a, num_cu, 0, s, nullptr);
 }
 
 int search_waves(int levels, int num_cu, int waves_per_cu, bool slim) {
-    const int per_cu = slim ? blocks_per_cu<kCount, true>(levels, waves_per_cu)
-                            : blocks_per_cu<kCount, false>(levels, waves_per_cu);
+    const int per_cu = slim ? blocks_per_cu<kCount, true, false>(levels, waves_per_cu)
+                            : blocks_per_cu<kCount, false, false>(levels, waves_per_cu);
     return num_cu * per_cu * kWavesPerBlock;
 }
 
 hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int waves_per_cu, hipStream_t s,
                          int *grid_waves_out) {
-    if (a.slim) {
-        if (enumerate) return launch_persistent<kEnumerate, true>(a, num_cu, waves_per_cu, s, grid_waves_out);
-        return launch_persistent<kCount, true>(a, num_cu, waves_per_cu, s, grid_waves_out);
-    }
-    if (enumerate) return launch_persistent<kEnumerate, false>(a, num_cu, waves_per_cu, s, grid_waves_out);
-    return launch_persistent<kCount, false>(a, num_cu, waves_per_cu, s, grid_waves_out);
+    if (enumerate) return launch_mode<kEnumerate>(a, num_cu, waves_per_cu, s, grid_waves_out);
+    return launch_mode<kCount>(a, num_cu, waves_per_cu, s, grid_waves_out);
 }
 
 hipError_t launch_level1(const int32_t *roots, int32_t R, unsigned long long perm_mul, uint32_t hub_cut,

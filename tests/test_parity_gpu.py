@@ -137,6 +137,33 @@ def test_first_vertex_lists_around_the_two_phase_cut(opts):
                     e.free_query(qid)
 
 
+@pytest.mark.parametrize("disable", [False, True])
+def test_hub_bitmaps(disable):
+    """Lists of 256+ neighbours are tested through adjacency bitmaps (unless
+    disabled): K_300 (every list a bitmap) against closed forms, and a dense
+    labelled random graph against the oracle under a cap."""
+    rng = np.random.default_rng(2024)
+    with gm.Engine(device=0, disable_hub_bitmaps=disable) as e:
+        g = S.complete(300)
+        e.load(g)
+        for k in (2, 3, 4):
+            for q in (S.clique_q(k), S.path_q(k), S.star_q(k - 1)):
+                _say(f"hub bitmaps disable={disable} K300 k={k} m={q.m}")
+                qid = e.add(q)
+                r = e.count(qid)
+                assert r.count == math.perm(300, k), (k, q.m)
+                groups = sum(math.perm(300, i) for i in range(1, k))
+                assert (r.groups, r.tasks) == (groups, 299 * groups)
+        g = S.gnp(700, 0.45, rng, 3)
+        e.load(g)
+        for trial in range(8):
+            q = S.random_connected_query(int(rng.integers(3, 6)), rng, extra_p=0.5, num_labels=3)
+            qid = e.add(q)
+            r = e.count(qid, cap=300000)
+            o = oracle.count(g, q, order=e.get_order(qid), cap=300000)
+            assert (r.count, r.outcome) == (o.count, o.outcome), trial
+
+
 def test_grid_closed_forms(engine):
     a, b = 40, 33
     g = S.grid(a, b)
