@@ -25,7 +25,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
-KERNEL_SRC = os.path.join(ROOT, "paper_2604_10601_amd", "csrc", "kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2604_10601_amd", "csrc", f)
+               for f in ("kernels.hip", "gm_internal.h", "engine.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_kernel_rmat20_q8_traffic.txt")
 
 
@@ -34,7 +35,11 @@ def log(msg: str) -> None:
 
 
 def kernel_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the sources that decide what the search kernel reads (kernels, layouts, graph upload)."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def algorithmic_bytes(pool_rows: int, depth: int, scanned: int, lookups: int, probes: int) -> int:
@@ -132,10 +137,10 @@ def _csvs(root: str, suffix: str):
 def kernel_key(name: str) -> str:
     """Short name of a dispatched kernel: search kernels by mode, copies, others by function name."""
     import re
-    m = re.search(r"search_kernel<(\d+), (true|false)>", name)
+    m = re.search(r"search_kernel<(\d+), (true|false), (true|false)>", name)
     if m:
         return {"0": "search", "1": "enumerate", "2": "expand"}[m.group(1)] + (
-            "<slim>" if m.group(2) == "true" else "<full>")
+            "<slim" if m.group(2) == "true" else "<full") + (",sb>" if m.group(3) == "true" else ">")
     if "copyBuffer" in name:
         return "copy"
     base = name[:-1].rsplit("(", 1)[0] if name.endswith(")") else name
@@ -209,6 +214,7 @@ def main() -> int:
     ap.add_argument("--steal-threshold", type=int, default=0)
     ap.add_argument("--hub-cut", type=int, default=0, help="first-phase tasks per root (0 = default 16)")
     ap.add_argument("--no-hub-bitmaps", action="store_true", help="bisect hub lists instead of reading bitmaps")
+    ap.add_argument("--hub-mib", type=int, default=0, help="device memory for hub bitmaps in MiB (0 = default)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB device-to-device (counter calibration)")
     ap.add_argument("--summarize-stats", metavar="DIR", help="print the kernel table of a rocprofv3 --stats run")
@@ -264,7 +270,7 @@ def main() -> int:
     e = gm.Engine(device=0, tau=args.tau, waves_per_cu=args.waves_per_cu,
                   disable_stealing=args.disable_stealing, steal_threshold=args.steal_threshold,
                   stack_layout=args.stack_layout, pool_hub_cut=args.hub_cut,
-                  disable_hub_bitmaps=args.no_hub_bitmaps)
+                  disable_hub_bitmaps=args.no_hub_bitmaps, hub_bitmap_mib=args.hub_mib)
     e.load(w.graph)
     qids = [e.add(q) for q in w.queries]
     phis = [e.get_order(qid) for qid in qids]

@@ -98,10 +98,14 @@ typedef struct {
     int32_t pool_hub_cut;
     /* 1 = no adjacency bitmaps.  By default gm_load_graph keeps one bit per
      * vertex of G for each of the highest-degree vertices (at least 256
-     * neighbours; at most 4096 of them and 1 GiB in all), and a membership test
-     * in such a list (slim stack layout) reads one bit instead of bisecting. */
+     * neighbours; at most 4096 of them and hub_bitmap_mib in all), and a
+     * membership test in such a list (slim stack layout) reads one bit instead
+     * of bisecting. */
     int32_t disable_hub_bitmaps;
-    int32_t reserved[2];
+    /* Device memory for the adjacency bitmaps, in MiB (each takes |V(G)| / 8
+     * bytes).  0 = default 1024. */
+    int32_t hub_bitmap_mib;
+    int32_t reserved[1];
 } gm_options;
 
 /* Result of one count or enumerate call. */

@@ -52,7 +52,8 @@ class Options(ctypes.Structure):
         ("batch_streams", ctypes.c_int32),
         ("pool_hub_cut", ctypes.c_int32),
         ("disable_hub_bitmaps", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("hub_bitmap_mib", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 
@@ -252,7 +253,8 @@ class Engine:
     def __init__(self, device: int = 0, tau: int = 0, pool_row_limit: int = 0, disable_stealing: bool = False,
                  steal_threshold: int = 0, waves_per_cu: int = 0, skip_symmetry_check: bool = False,
                  stack_layout: int = 0, disable_label_index: bool = False, batch_single_launch: bool = False,
-                 batch_streams: int = 0, pool_hub_cut: int = 0, disable_hub_bitmaps: bool = False):
+                 batch_streams: int = 0, pool_hub_cut: int = 0, disable_hub_bitmaps: bool = False,
+                 hub_bitmap_mib: int = 0):
         self._lib = load_library()
         opt = Options()
         opt.tau = tau
@@ -267,6 +269,7 @@ class Engine:
         opt.batch_streams = batch_streams
         opt.pool_hub_cut = pool_hub_cut
         opt.disable_hub_bitmaps = int(disable_hub_bitmaps)
+        opt.hub_bitmap_mib = hub_bitmap_mib
         h = ctypes.c_void_p()
         st = self._lib.gm_create(device, ctypes.byref(opt), ctypes.byref(h))
         if st != GM_OK:

@@ -36,7 +36,7 @@ thread_local std::string g_create_error;
 // Hub bitmaps: vertices with at least this many neighbours, at most this many, in this many bytes.
 constexpr int64_t kHubMinDegree = 256;
 constexpr int32_t kMaxHubs = 4096;
-constexpr uint64_t kHubBytes = 1ull << 30;
+constexpr int32_t kHubDefaultMiB = 1024;
 
 struct QueryRec {
     bool live = false;
@@ -1493,7 +1493,7 @@ gm_status gm_create(int32_t device, const gm_options *opt, gm_engine **out) {
     if (opt) o = *opt;
     if (o.stack_layout < 0 || o.stack_layout > 2 || o.steal_threshold < 0 || o.waves_per_cu < 0 ||
         o.pool_row_limit < 0 || o.batch_single_launch < 0 || o.batch_single_launch > 1 || o.batch_streams < 0 ||
-        o.pool_hub_cut < 0) {
+        o.pool_hub_cut < 0 || o.hub_bitmap_mib < 0) {
         g_create_error = "option out of range";
         return GM_ERR_ARG;
     }
@@ -1619,7 +1619,7 @@ gm_status gm_load_graph(gm_engine *e, int32_t n, const int64_t *row_ptr, const i
     std::vector<uint32_t> bylabel_deg(static_cast<size_t>(n));
     for (int32_t i = 0; i < n; ++i) bylabel_deg[i] = vinfo[bylabel[i]].y >> 8;
     // Adjacency bitmaps of the highest-degree vertices (at least kHubMinDegree
-    // neighbours; at most kMaxHubs, within kHubBytes): a membership test in a hub's
+    // neighbours; at most kMaxHubs, within the option's MiB): a membership test in a hub's
     // long list becomes one bit read instead of a bisection.
     std::vector<int32_t> hub_id;
     std::vector<uint32_t> hub_bits;
@@ -1633,7 +1633,8 @@ gm_status gm_load_graph(gm_engine *e, int32_t n, const int64_t *row_ptr, const i
             const int64_t dx = row_ptr[x + 1] - row_ptr[x], dy = row_ptr[y + 1] - row_ptr[y];
             return dx != dy ? dx > dy : x < y;
         });
-        const uint64_t fit = kHubBytes / (words * 4);
+        const uint64_t mib = e->opt.hub_bitmap_mib > 0 ? e->opt.hub_bitmap_mib : kHubDefaultMiB;
+        const uint64_t fit = (mib << 20) / (words * 4);
         hubs = static_cast<int32_t>(std::min<uint64_t>({big.size(), static_cast<uint64_t>(kMaxHubs), fit}));
         if (hubs > 0) {
             hub_id.assign(static_cast<size_t>(n), -1);
