@@ -137,10 +137,11 @@ def _csvs(root: str, suffix: str):
 def kernel_key(name: str) -> str:
     """Short name of a dispatched kernel: search kernels by mode, copies, others by function name."""
     import re
-    m = re.search(r"search_kernel<(\d+), (true|false), (true|false)>", name)
+    m = re.search(r"search_kernel<(\d+), (true|false), (true|false), (true|false)>", name)
     if m:
         return {"0": "search", "1": "enumerate", "2": "expand"}[m.group(1)] + (
-            "<slim" if m.group(2) == "true" else "<full") + (",sb>" if m.group(3) == "true" else ">")
+            "<slim" if m.group(2) == "true" else "<full") + (",sb" if m.group(3) == "true" else "") + (
+            ",cg>" if m.group(4) == "true" else ">")
     if "copyBuffer" in name:
         return "copy"
     base = name[:-1].rsplit("(", 1)[0] if name.endswith(")") else name
@@ -190,9 +191,11 @@ def main() -> int:
     ap.add_argument("--eval-cap", type=int, default=1_000_000, help="learned: cap of the evaluation runs")
     ap.add_argument("--eval-limit", type=float, default=1.0, help="learned: time limit of the evaluation runs (s)")
     ap.add_argument("--workload", default="medium",
-                    choices=["medium", "small", "large", "batch", "serve", "learned"],
+                    choices=["medium", "small", "large", "batch", "serve", "learned", "cg"],
                     help="batch = 10,000 mixed-size queries in shared launches (autotuned); "
-                         "serve = the same queries as a Poisson request stream through the server")
+                         "serve = the same queries as a Poisson request stream through the server; "
+                         "cg = large queries searched on G and on the candidate graph G'")
+    ap.add_argument("--cg-per-size", type=int, default=20, help="cg: queries of each size (16, 24, 32)")
     ap.add_argument("--load", type=float, default=0.7,
                     help="serve: offered rate as a fraction of the measured batched throughput")
     ap.add_argument("--slots", type=int, default=0, help="serve: concurrent launches (0 = default)")
@@ -260,6 +263,8 @@ def main() -> int:
         return bench_serve(args, gm)
     if args.workload == "learned":
         return bench_learned(args, gm)
+    if args.workload == "cg":
+        return bench_cg(args, gm)
 
     t = time.time()
     w = make_workload(args.workload, args.queries, args.query_stride)
@@ -646,6 +651,77 @@ def bench_learned(args, gm) -> int:
                     "timeouts": int(sum(r.outcome == gm.GM_TIMEOUT for r in learned)),
                     "queries_with_another_order": int(chosen)},
         "model": {"train_mse": loss, "heldout_mse": val_mse, "target_variance": float(np.var(y))},
+        "same_counts": bool(same),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_cg(args, gm) -> int:
+    """Candidate graph: the same large queries searched on G and on G' (built per
+    query on the device, its build inside each query's time).  Counts of queries
+    that finish in both modes must agree; total time and p50/p99 are compared."""
+    from paper_2604_10601_amd import workloads as wl
+    t = time.time()
+    w = wl.cg_rmat20(per_size=args.cg_per_size)
+    if args.time_limit >= 0:
+        w.time_limit_s = args.time_limit
+    log(f"workload {w.name}: n={w.graph.n} |E|={w.graph.num_edges} queries={len(w.queries)} "
+        f"({time.time() - t:.1f} s to generate)")
+    runs = {}
+    for mode in ("plain", "candidate_graph"):
+        with gm.Engine(device=0, candidate_graph=(mode == "candidate_graph")) as e:
+            e.load(w.graph)
+            qids = [e.add(q) for q in w.queries]
+            e.count(qids[0], cap=w.cap, time_limit_s=w.time_limit_s)  # warm-up
+            res = []
+            t = time.time()
+            for i, qid in enumerate(qids):
+                res.append(e.count(qid, cap=w.cap, time_limit_s=w.time_limit_s))
+                if (i + 1) % 10 == 0:
+                    log(f"  {mode}: {i + 1} queries ({time.time() - t:.1f} s)")
+            runs[mode] = res
+    plain, cg = runs["plain"], runs["candidate_graph"]
+    both_done = [(a, b) for a, b in zip(plain, cg) if a.outcome != gm.GM_TIMEOUT and b.outcome != gm.GM_TIMEOUT]
+    same = all((a.count, a.outcome) == (b.count, b.outcome) for a, b in both_done)
+
+    def summary(rs):
+        ms = np.array([r.search_ms for r in rs])
+        cnt = sum(r.count for r in rs)
+        return {"total_ms": float(ms.sum()), "p50_ms": float(np.percentile(ms, 50)),
+                "p99_ms": float(np.percentile(ms, 99)), "embeddings": int(cnt),
+                "embeddings_per_s": float(cnt / (ms.sum() / 1e3)) if ms.sum() > 0 else 0.0,
+                "outcomes": {"done": sum(r.outcome == gm.GM_DONE for r in rs),
+                             "capped": sum(r.outcome == gm.GM_CAPPED for r in rs),
+                             "timeout": sum(r.outcome == gm.GM_TIMEOUT for r in rs)}}
+
+    sp, sc = summary(plain), summary(cg)
+    sc["build_ms_total"] = float(sum(r.candidate_ms for r in cg))
+    sc["search_ms_without_build"] = sc["total_ms"] - sc["build_ms_total"]
+    sc["filter_sweeps_mean"] = float(np.mean([r.candidate_rounds for r in cg]))
+    sc["list_entries_mean"] = float(np.mean([r.candidate_edges for r in cg]))
+    sc["roots_mean"] = float(np.mean([r.pool_rows for r in cg]))
+    sp["roots_mean"] = float(np.mean([r.pool_rows for r in plain]))
+    out = {
+        "metric": "embeddings/s",
+        "value": sc["embeddings_per_s"],
+        "unit": "embeddings/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": sc["total_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "graph_vertices": int(w.graph.n), "graph_edges": int(w.graph.num_edges),
+                   "queries": len(w.queries), "query_sizes": sorted({int(q.k) for q in w.queries}),
+                   "cap": w.cap, "time_limit_s": w.time_limit_s, "order": "RI heuristic"},
+        "plain": sp,
+        "candidate_graph": sc,
+        "speedup_total_time": sp["total_ms"] / sc["total_ms"] if sc["total_ms"] > 0 else None,
+        "compared_queries": len(both_done),
         "same_counts": bool(same),
     }
     print(json.dumps(out), flush=True)

@@ -105,7 +105,20 @@ typedef struct {
     /* Device memory for the adjacency bitmaps, in MiB (each takes |V(G)| / 8
      * bytes).  0 = default 1024. */
     int32_t hub_bitmap_mib;
-    int32_t reserved[1];
+    /* 1 = search on a candidate graph G' (the paper does so when it compares
+     * with EGSM, whose G' it adopts: Sec. 6.1; App. C describes G' as built by
+     * a light filter over labels and query structure).  Each gm_count /
+     * gm_enumerate call first keeps, for every query vertex u, the largest set
+     * C(u) of vertices with u's label and at least u's degree in which every
+     * vertex has a neighbour in C(u') for each query neighbour u' of u, then
+     * lists, for each query edge, the neighbours of every candidate that lie in
+     * the other end's set; the search reads those lists instead of G's.
+     * Counts are the same as on G.  The build runs on the device (a few sweeps
+     * over G) and is part of the call's search_ms.  Requires tau = 0 and the
+     * slim stack layout (stack_layout 0 or 2); gm_count_batch, gm_tune_batch
+     * and gm_serve_open return GM_ERR_STATE while it is on.  Device memory:
+     * |E(Q)| * (|V(G)| + 1) * 4 bytes of list bounds plus the lists. */
+    int32_t candidate_graph;
 } gm_options;
 
 /* Result of one count or enumerate call. */
@@ -126,7 +139,7 @@ typedef struct {
     uint64_t rows;         /* enumerate: rows written */
     double kernel_ms;      /* device time of the depth-first search launch alone (HIP events) */
     int32_t grid_waves;    /* wavefronts in that launch */
-    int32_t reserved;
+    int32_t candidate_rounds; /* candidate graph: filter sweeps run (0 when off) */
     uint64_t kernel_tasks;  /* tasks, probes and matches of that launch alone (the pool */
     uint64_t kernel_probes; /* expansion before it is excluded) */
     uint64_t kernel_groups;
@@ -135,6 +148,8 @@ typedef struct {
                                 label is the query vertex's label (<= tasks) */
     uint64_t kernel_scanned; /* ... of the depth-first search launch alone */
     uint64_t kernel_lookups; /* label-slice bound lookups (8 B each) of that launch */
+    double candidate_ms;     /* candidate graph: host wall time of its build (inside search_ms) */
+    uint64_t candidate_edges; /* candidate graph: list entries, summed over query edges */
 } gm_result;
 
 /* Create an engine on HIP device `device` (>= 0).  device = -1 creates a
@@ -185,6 +200,16 @@ gm_status gm_count(gm_engine *engine, int32_t qid, uint64_t cap, double time_lim
  * gm_count's rules with this cap and out->rows equals min(count, cap). */
 gm_status gm_enumerate(gm_engine *engine, int32_t qid, int32_t *rows, uint64_t cap, double time_limit_s,
                        gm_result *out);
+
+/* The candidate sets of query qid (see gm_options.candidate_graph), built for
+ * its current order whether or not the option is on.  bits: host buffer of
+ * k * ((n + 31) / 32) words, n = |V(G)|; bit (v % 32) of bits[u * ((n + 31) /
+ * 32) + v / 32] is set iff v is in C(u), u a query vertex.  edges_out (may be
+ * NULL): list entries of G', summed over the query's edges.  rounds_out (may
+ * be NULL): filter sweeps run, the last one dropping nothing.  Errors:
+ * GM_ERR_STATE without a graph, GM_ERR_DEVICE on a host-only engine. */
+gm_status gm_candidate_sets(gm_engine *engine, int32_t qid, uint32_t *bits, uint64_t *edges_out,
+                            int32_t *rounds_out);
 
 /* Summary of one gm_count_batch call. */
 typedef struct {

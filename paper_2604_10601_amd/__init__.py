@@ -27,7 +27,7 @@ ABI_FUNCTIONS = ("gm_create", "gm_destroy", "gm_load_graph", "gm_load_query", "g
                  "gm_serve_close", "gm_order_features", "gm_candidate_orders", "gm_model_create",
                  "gm_model_destroy", "gm_model_predict", "gm_model_train", "gm_model_get_params",
                  "gm_model_set_params", "gm_model_last_error", "gm_choose_order", "gm_set_symmetry_breaking", "gm_free_query",
-                 "gm_last_error")
+                 "gm_candidate_sets", "gm_last_error")
 
 ORDER_FEATURES = 192
 
@@ -53,7 +53,7 @@ class Options(ctypes.Structure):
         ("pool_hub_cut", ctypes.c_int32),
         ("disable_hub_bitmaps", ctypes.c_int32),
         ("hub_bitmap_mib", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 1),
+        ("candidate_graph", ctypes.c_int32),
     ]
 
 
@@ -109,13 +109,15 @@ class _CResult(ctypes.Structure):
         ("rows", ctypes.c_uint64),
         ("kernel_ms", ctypes.c_double),
         ("grid_waves", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("candidate_rounds", ctypes.c_int32),
         ("kernel_tasks", ctypes.c_uint64),
         ("kernel_probes", ctypes.c_uint64),
         ("kernel_groups", ctypes.c_uint64),
         ("scanned", ctypes.c_uint64),
         ("kernel_scanned", ctypes.c_uint64),
         ("kernel_lookups", ctypes.c_uint64),
+        ("candidate_ms", ctypes.c_double),
+        ("candidate_edges", ctypes.c_uint64),
     ]
 
 
@@ -153,6 +155,9 @@ class Result:
     kernel_scanned: int = 0
     kernel_lookups: int = 0
     matches: Optional[np.ndarray] = None
+    candidate_rounds: int = 0
+    candidate_ms: float = 0.0
+    candidate_edges: int = 0
 
     @property
     def idle_rate(self) -> float:
@@ -230,6 +235,7 @@ def load_library():
     lib.gm_choose_order.argtypes = [p, p, i32, i32, u64, ctypes.c_float, ctypes.POINTER(i32), p]
     lib.gm_set_symmetry_breaking.argtypes = [p, i32, i32, ctypes.POINTER(u64)]
     lib.gm_free_query.argtypes = [p, i32]
+    lib.gm_candidate_sets.argtypes = [p, i32, p, ctypes.POINTER(u64), ctypes.POINTER(i32)]
     lib.gm_last_error.argtypes = [p]
     lib.gm_last_error.restype = ctypes.c_char_p
     for name in ("gm_create", "gm_load_graph", "gm_load_query", "gm_set_order", "gm_get_order", "gm_count",
@@ -237,7 +243,7 @@ def load_library():
                  "gm_serve_submit", "gm_serve_poll", "gm_serve_stats", "gm_serve_close", "gm_order_features",
                  "gm_candidate_orders", "gm_model_create", "gm_model_predict", "gm_model_train",
                  "gm_model_get_params", "gm_model_set_params", "gm_choose_order", "gm_set_symmetry_breaking",
-                 "gm_free_query"):
+                 "gm_free_query", "gm_candidate_sets"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -254,7 +260,7 @@ class Engine:
                  steal_threshold: int = 0, waves_per_cu: int = 0, skip_symmetry_check: bool = False,
                  stack_layout: int = 0, disable_label_index: bool = False, batch_single_launch: bool = False,
                  batch_streams: int = 0, pool_hub_cut: int = 0, disable_hub_bitmaps: bool = False,
-                 hub_bitmap_mib: int = 0):
+                 hub_bitmap_mib: int = 0, candidate_graph: bool = False):
         self._lib = load_library()
         opt = Options()
         opt.tau = tau
@@ -270,12 +276,14 @@ class Engine:
         opt.pool_hub_cut = pool_hub_cut
         opt.disable_hub_bitmaps = int(disable_hub_bitmaps)
         opt.hub_bitmap_mib = hub_bitmap_mib
+        opt.candidate_graph = int(candidate_graph)
         h = ctypes.c_void_p()
         st = self._lib.gm_create(device, ctypes.byref(opt), ctypes.byref(h))
         if st != GM_OK:
             raise GmError(st, self._lib.gm_last_error(None).decode())
         self._h = h
         self._k = {}
+        self._n = 0
 
     def close(self):
         if getattr(self, "_h", None):
@@ -303,6 +311,7 @@ class Engine:
         cl = np.ascontiguousarray(col, dtype=np.int32)
         lb = np.ascontiguousarray(labels, dtype=np.int32)
         self._check(self._lib.gm_load_graph(self._h, rp.shape[0] - 1, _ptr(rp), _ptr(cl), _ptr(lb)))
+        self._n = rp.shape[0] - 1
 
     def load_query(self, k: int, edges, labels) -> int:
         e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
@@ -327,7 +336,8 @@ class Engine:
                       int(r.groups), int(r.tasks), int(r.lanes_active), int(r.lanes_issued), int(r.probes),
                       int(r.steals), int(r.rows), float(r.kernel_ms), int(r.grid_waves), int(r.kernel_tasks),
                       int(r.kernel_probes), int(r.kernel_groups), int(r.scanned), int(r.kernel_scanned),
-                      int(r.kernel_lookups), matches)
+                      int(r.kernel_lookups), matches, int(r.candidate_rounds), float(r.candidate_ms),
+                      int(r.candidate_edges))
 
     def count(self, qid: int, cap: int = 0, time_limit_s: float = 0.0) -> Result:
         r = _CResult()
@@ -390,6 +400,16 @@ class Engine:
         aut = ctypes.c_uint64()
         self._check(self._lib.gm_set_symmetry_breaking(self._h, qid, int(enable), ctypes.byref(aut)))
         return aut.value
+
+    def candidate_sets(self, qid: int):
+        """Candidate sets of the query (boolean k x n, row u = C(u)), G' list entries, filter sweeps."""
+        k, n = self._k[qid], self._n
+        words = (n + 31) // 32
+        bits = np.zeros(max(k * words, 1), dtype=np.uint32)
+        edges, rounds = ctypes.c_uint64(), ctypes.c_int32()
+        self._check(self._lib.gm_candidate_sets(self._h, qid, _ptr(bits), ctypes.byref(edges), ctypes.byref(rounds)))
+        sets = np.unpackbits(bits[:k * words].view(np.uint8), bitorder="little").reshape(k, words * 32)[:, :n]
+        return sets.astype(bool), edges.value, rounds.value
 
     def serve(self, slots: int = 0, max_batch: int = 0, waves_per_cu: int = 0, batch_streams: int = 0,
               max_pending: int = 0) -> "Server":

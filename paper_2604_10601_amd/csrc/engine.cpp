@@ -258,6 +258,18 @@ struct gm_engine {
     uint32_t *d_voff = nullptr;
     uint32_t *d_vtmp = nullptr;    // chunk totals of the prefix sum
     size_t v_cap = 0;
+    // candidate graph of the query searched last (built per call, buffers kept)
+    int32_t *d_cbits = nullptr;    // C(l) bitmaps by position
+    int32_t *d_crank = nullptr;    // scratch: word ranks, then list lengths and offsets
+    int32_t *d_ctmp = nullptr;     // prefix-sum scratch
+    int32_t *d_clist = nullptr;    // candidates of every position, ids ascending
+    int32_t *d_cedges = nullptr;   // per query edge: gm::CandEdge
+    int32_t *d_gbounds = nullptr;  // list bounds per query edge and candidate
+    int32_t *d_gcol = nullptr;     // the lists
+    int32_t *d_cmisc = nullptr;    // [0] sweep flag, [2..3] list total, [8 ..] position bounds
+    size_t cbits_cap = 0, crank_cap = 0, ctmp_cap = 0, clist_cap = 0, cedges_cap = 0, gbounds_cap = 0, gcol_cap = 0,
+           cmisc_cap = 0;
+    std::vector<gm::CandEdge> h_cedges;
     LaunchCtx lc;                  // device state of the engine's own launches
     std::atomic<int> servers{0};   // open servers (the graph must stay as it is)
     int num_cu = 0;
@@ -627,6 +639,123 @@ void root_share(const gm_engine *e, const Plan &p, unsigned long long *row0, uns
     *rows = static_cast<unsigned long long>(it - first);
 }
 
+// Candidate graph G' of one query (the filtering pass that EGSM-style matchers
+// run first; the paper searches EGSM's G' when comparing with it, Sec. 6.1, and
+// App. C describes it).  C(l) starts as the vertices with position l's label
+// and at least its query degree, and sweeps drop a vertex while some query
+// neighbour's set holds none of its neighbours, until a sweep drops nothing
+// (the largest such family).  Then, for each query edge (i, l) with i before
+// l, the list of every v in C(i) is N(v) restricted to C(l).  The candidates
+// of position 0, ids ascending, are the roots.
+struct CandInfo {
+    const int32_t *roots = nullptr;
+    unsigned long long nroots = 0;
+    unsigned long long edges = 0;
+    int32_t rounds = 0;
+};
+
+// Vertices with label id c and degree >= d: a prefix of c's bucket.
+unsigned long long bucket_prefix(const gm_engine *e, int32_t c, int32_t d) {
+    if (c < 0 || c >= static_cast<int32_t>(e->lab_start.size()) - 1) return 0;
+    auto first = e->bylabel_deg.begin() + e->lab_start[c];
+    auto it = std::partition_point(first, e->bylabel_deg.begin() + e->lab_start[c + 1],
+                                   [d](uint32_t x) { return x >= static_cast<uint32_t>(d); });
+    return static_cast<unsigned long long>(it - first);
+}
+
+gm_status build_candidate_graph(gm_engine *e, const Plan &p, CandInfo *ci, uint32_t *gslot) {
+    hipStream_t s = e->lc.stream;
+    const int32_t n = e->n;
+    const int32_t k = p.k;
+    gm::CandQuery cq{};
+    cq.k = k;
+    std::vector<gm::CandEdge> edges;
+    unsigned long long c0[kMaxK] = {}, c0_all = 0;
+    for (int l = 0; l < k; ++l) {
+        cq.lab[l] = p.lab[l];
+        cq.qdeg[l] = p.qdeg[l];
+        cq.adj[l] |= p.bwd[l];
+        c0[l] = bucket_prefix(e, p.lab[l], p.qdeg[l]);  // C(l) is a subset of this prefix
+        c0_all += c0[l];
+        gslot[l] = static_cast<uint32_t>(edges.size());
+        for (int j = 0; j < l; ++j) {
+            if (!((p.bwd[l] >> j) & 1u)) continue;
+            cq.adj[j] |= 1u << l;
+            gm::CandEdge ed{};
+            ed.src = j;
+            ed.dst = l;
+            edges.push_back(ed);
+        }
+    }
+    const int32_t m = static_cast<int32_t>(edges.size());
+    unsigned long long t_most = 0;
+    for (const gm::CandEdge &ed : edges) t_most += c0[ed.src];
+    const unsigned long long wp = gm::cand_bitmap_words(n), words = wp * static_cast<unsigned long long>(k);
+    const unsigned long long bounds_bytes = 2ull * m * static_cast<unsigned long long>(n) * sizeof(uint32_t);
+    if (c0_all >= (1ull << 32) || t_most >= (1ull << 32) || bounds_bytes > (64ull << 30))
+        return e->fail(GM_ERR_NOMEM, "candidate graph too large for this graph and query");
+    *ci = CandInfo{};
+    gm_status st = ensure_buffer(e, &e->d_cbits, &e->cbits_cap, static_cast<size_t>(words));
+    if (!st) st = ensure_buffer(e, &e->d_cmisc, &e->cmisc_cap, 64);
+    if (!st) st = ensure_buffer(e, &e->d_crank, &e->crank_cap, static_cast<size_t>(std::max(words, t_most)));
+    if (!st) st = ensure_buffer(e, &e->d_ctmp, &e->ctmp_cap,
+                                static_cast<size_t>(gm::cand_scan_temp_words(std::max(words, t_most))));
+    if (!st) st = ensure_buffer(e, &e->d_clist, &e->clist_cap, static_cast<size_t>(std::max<unsigned long long>(c0_all, 1)));
+    if (!st && m > 0) st = ensure_buffer(e, &e->d_cedges, &e->cedges_cap, m * sizeof(gm::CandEdge) / sizeof(int32_t));
+    if (!st && m > 0)
+        st = ensure_buffer(e, &e->d_gbounds, &e->gbounds_cap, static_cast<size_t>(bounds_bytes / sizeof(int32_t)));
+    if (st) return st;
+    uint32_t *bits = reinterpret_cast<uint32_t *>(e->d_cbits);
+    uint32_t *flag = reinterpret_cast<uint32_t *>(e->d_cmisc);
+    auto *list_total = reinterpret_cast<unsigned long long *>(e->d_cmisc + 2);
+    uint32_t *bounds = reinterpret_cast<uint32_t *>(e->d_cmisc + 8);  // k + 1 words
+    uint32_t *scratch = reinterpret_cast<uint32_t *>(e->d_crank);
+    uint32_t *tmp = reinterpret_cast<uint32_t *>(e->d_ctmp);
+
+    HIP_TRY(e, gm::launch_cand_init(e->d_vinfo, n, cq, bits, e->num_cu, s));
+    for (;;) {
+        uint32_t changed = 0;
+        HIP_TRY(e, hipMemsetAsync(flag, 0, sizeof(uint32_t), s));
+        HIP_TRY(e, gm::launch_cand_refine(e->d_lcol, e->d_loff, e->loff_stride, n, cq, bits, flag, e->num_cu, s));
+        HIP_TRY(e, hipMemcpyAsync(&changed, flag, sizeof(changed), hipMemcpyDeviceToHost, s));
+        HIP_TRY(e, hipStreamSynchronize(s));
+        ++ci->rounds;
+        if (!changed) break;
+    }
+    uint32_t hb[kMaxK + 1] = {};
+    HIP_TRY(e, gm::launch_cand_lists(bits, n, k, scratch, tmp, e->d_clist, bounds, e->num_cu, s));
+    HIP_TRY(e, hipMemcpyAsync(hb, bounds, (k + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(e, hipStreamSynchronize(s));
+    ci->roots = e->d_clist + hb[0];
+    ci->nroots = hb[1] - hb[0];
+    if (m == 0) return GM_OK;
+    unsigned long long first = 0, most = 1;
+    for (gm::CandEdge &ed : edges) {
+        ed.start = hb[ed.src];
+        ed.len = hb[ed.src + 1] - hb[ed.src];
+        ed.first = static_cast<uint32_t>(first);
+        first += ed.len;
+        most = std::max<unsigned long long>(most, ed.len);
+    }
+    e->h_cedges = edges;  // kept until the upload below has completed
+    const gm::CandEdge *d_edges = reinterpret_cast<const gm::CandEdge *>(e->d_cedges);
+    unsigned long long total = 0;
+    HIP_TRY(e, hipMemcpyAsync(e->d_cedges, e->h_cedges.data(), m * sizeof(gm::CandEdge), hipMemcpyHostToDevice, s));
+    HIP_TRY(e, hipMemsetAsync(list_total, 0, sizeof(unsigned long long), s));
+    HIP_TRY(e, gm::launch_cand_count(e->d_lcol, e->d_loff, e->loff_stride, n, cq, bits, d_edges, m, most, e->d_clist,
+                                     scratch, list_total, e->num_cu, s));
+    HIP_TRY(e, hipMemcpyAsync(&total, list_total, sizeof(total), hipMemcpyDeviceToHost, s));
+    HIP_TRY(e, hipStreamSynchronize(s));
+    if (total >= (1ull << 32)) return e->fail(GM_ERR_NOMEM, "candidate graph holds 2^32 list entries or more");
+    ci->edges = total;
+    HIP_TRY(e, gm::launch_exclusive_scan(scratch, first, tmp, s));
+    st = ensure_buffer(e, &e->d_gcol, &e->gcol_cap, static_cast<size_t>(std::max<unsigned long long>(total, 1)));
+    if (st) return st;
+    HIP_TRY(e, gm::launch_cand_fill(e->d_lcol, e->d_loff, e->loff_stride, n, cq, bits, d_edges, m, most, e->d_clist,
+                                    scratch, e->d_gcol, reinterpret_cast<uint32_t *>(e->d_gbounds), e->num_cu, s));
+    return GM_OK;
+}
+
 // One search with the two-phase pool (the default).  The roots are a bucket
 // prefix, visited in a mixed order.  First-phase items hold 64 roots each, every
 // root with at most its first kHubCut tasks of position 1, so every root is
@@ -661,6 +790,28 @@ gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, ui
         return GM_OK;
     }
     if (R >= (1ull << 31)) return e->fail(GM_ERR_GRAPH, "more than 2^31 candidates for the first query vertex");
+    // candidate graph: the roots become C(phi[0]) and every list is read from G'
+    const bool cg = e->opt.candidate_graph != 0;
+    const int32_t *pool = e->d_bylabel;
+    if (cg) {
+        CandInfo ci;
+        const auto t_cg = std::chrono::steady_clock::now();
+        gm_status cst = build_candidate_graph(e, p, &ci, p.gslot);
+        if (cst) return cst;
+        std::chrono::duration<double, std::milli> cg_ms = std::chrono::steady_clock::now() - t_cg;
+        out->candidate_ms = cg_ms.count();
+        out->candidate_rounds = ci.rounds;
+        out->candidate_edges = ci.edges;
+        pool = ci.roots;
+        row0 = 0;
+        R = ci.nroots;
+        out->pool_rows = R;
+        if (R == 0) {
+            std::chrono::duration<double, std::milli> ms = std::chrono::steady_clock::now() - t_start;
+            out->search_ms = ms.count();
+            return GM_OK;
+        }
+    }
     gm_status st = ensure_query_slots(e, e->lc, 2);
     if (!st) st = ensure_streams(e, e->lc, 1);
     if (!st) st = ensure_level1(e, R);
@@ -690,16 +841,26 @@ gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, ui
                               e->lc.stream));
     HIP_TRY(e, gm::launch_start_clock(e->lc.d_ctl, e->lc.stream));
     // the second phase's scanned candidates go to the second slot
-    const int32_t lab1 = e->loff_stride > 1 ? p.lab[1] : 0;
-    const bool slim = use_slim(e, q->k);
-    HIP_TRY(e, gm::launch_level1(e->d_bylabel + row0, static_cast<int32_t>(R), p.perm_mul, p.hub_cut, e->d_loff,
-                                 e->loff_stride, lab1, e->d_vlen, e->d_vstart, e->d_voff, e->d_vtmp, e->lc.d_qctl + 1,
-                                 e->lc.d_plans, e->lc.d_streams, e->num_cu, e->lc.stream));
+    // (on G' position 1's lists are those of the query edge (0, 1))
+    const int32_t lab1 = cg ? 0 : (e->loff_stride > 1 ? p.lab[1] : 0);
+    const uint32_t *loff1 = cg ? reinterpret_cast<const uint32_t *>(e->d_gbounds) +
+                                     2ull * static_cast<unsigned long long>(p.gslot[1]) * static_cast<unsigned long long>(e->n)
+                               : e->d_loff;
+    const bool slim = cg || use_slim(e, q->k);
+    HIP_TRY(e, gm::launch_level1(pool + row0, static_cast<int32_t>(R), p.perm_mul, p.hub_cut, loff1,
+                                 cg ? 2 : e->loff_stride, lab1, e->d_vlen, e->d_vstart, e->d_voff, e->d_vtmp,
+                                 e->lc.d_qctl + 1, e->lc.d_plans, e->lc.d_streams, e->num_cu, e->lc.stream));
     SearchArgs a = graph_args(e, e->lc);
     a.nq = 1;
     a.nstreams = 1;
     a.levels = q->k;
-    a.pool = e->d_bylabel;
+    a.pool = pool;
+    if (cg) {
+        a.cg = 1;
+        a.lcol = e->d_gcol;
+        a.gbounds = reinterpret_cast<const uint32_t *>(e->d_gbounds);
+        a.gn = static_cast<unsigned long long>(e->n);
+    }
     a.voff = e->d_voff;
     a.vstart = e->d_vstart;
     a.slim = slim ? 1 : 0;
@@ -1493,8 +1654,12 @@ gm_status gm_create(int32_t device, const gm_options *opt, gm_engine **out) {
     if (opt) o = *opt;
     if (o.stack_layout < 0 || o.stack_layout > 2 || o.steal_threshold < 0 || o.waves_per_cu < 0 ||
         o.pool_row_limit < 0 || o.batch_single_launch < 0 || o.batch_single_launch > 1 || o.batch_streams < 0 ||
-        o.pool_hub_cut < 0 || o.hub_bitmap_mib < 0) {
+        o.pool_hub_cut < 0 || o.hub_bitmap_mib < 0 || o.candidate_graph < 0 || o.candidate_graph > 1) {
         g_create_error = "option out of range";
+        return GM_ERR_ARG;
+    }
+    if (o.candidate_graph && (o.tau != 0 || o.stack_layout == 1)) {
+        g_create_error = "the candidate graph needs tau = 0 and the slim stack layout";
         return GM_ERR_ARG;
     }
     gm_engine *e = new (std::nothrow) gm_engine();
@@ -1539,6 +1704,9 @@ void gm_destroy(gm_engine *e) {
             if (e->d_pool[i]) (void)hipFree(e->d_pool[i]);
         if (e->d_rows) (void)hipFree(e->d_rows);
         for (uint32_t *b : {e->d_vlen, e->d_vstart, e->d_voff, e->d_vtmp})
+            if (b) (void)hipFree(b);
+        for (int32_t *b : {e->d_cbits, e->d_crank, e->d_ctmp, e->d_clist, e->d_cedges, e->d_gbounds, e->d_gcol,
+                           e->d_cmisc})
             if (b) (void)hipFree(b);
     }
     delete e;
@@ -1778,6 +1946,8 @@ gm_status gm_count_batch(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t
                          gm_result *out, gm_batch_info *info) {
     if (!e) return GM_ERR_ARG;
     std::lock_guard<std::mutex> lk(e->mu);
+    if (e->opt.candidate_graph)
+        return e->fail(GM_ERR_STATE, "the candidate graph is built per query: use gm_count or gm_enumerate");
     return run_batch(e, nq, qids, cap, time_limit_s, out, info);
 }
 
@@ -1787,7 +1957,39 @@ gm_status gm_tune_batch(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t 
     std::lock_guard<std::mutex> lk(e->mu);
     if (!out) return e->fail(GM_ERR_ARG, "out is null");
     if (e->servers.load() > 0) return e->fail(GM_ERR_STATE, "a server is open on this engine");
+    if (e->opt.candidate_graph)
+        return e->fail(GM_ERR_STATE, "the candidate graph is built per query: use gm_count or gm_enumerate");
     return run_tune(e, nq, qids, cap, time_limit_s, out);
+}
+
+gm_status gm_candidate_sets(gm_engine *e, int32_t qid, uint32_t *bits, uint64_t *edges_out, int32_t *rounds_out) {
+    if (!e) return GM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (!bits) return e->fail(GM_ERR_ARG, "bits is null");
+    const QueryRec *q = nullptr;
+    gm_status st = get_query(e, qid, &q);
+    if (st) return st;
+    if (!e->has_graph) return e->fail(GM_ERR_STATE, "no data graph loaded");
+    if (e->device < 0) return e->fail(GM_ERR_DEVICE, "host-only engine (created with device -1) cannot search");
+    HIP_TRY(e, hipSetDevice(e->device));
+    const size_t W = (static_cast<size_t>(e->n) + 31) / 32;
+    std::memset(bits, 0, W * q->k * sizeof(uint32_t));
+    if (edges_out) *edges_out = 0;
+    if (rounds_out) *rounds_out = 0;
+    bool label_missing = false;
+    Plan p = make_plan(e, *q, &label_missing);
+    if (e->n == 0 || label_missing) return GM_OK;  // some query label is not in G: every set is empty
+    CandInfo ci;
+    st = build_candidate_graph(e, p, &ci, p.gslot);
+    if (st) return st;
+    const unsigned long long wp = gm::cand_bitmap_words(e->n);
+    for (int l = 0; l < q->k; ++l)
+        HIP_TRY(e, hipMemcpyAsync(bits + static_cast<size_t>(p.phi[l]) * W, e->d_cbits + static_cast<size_t>(l) * wp,
+                                  W * sizeof(uint32_t), hipMemcpyDeviceToHost, e->lc.stream));
+    HIP_TRY(e, hipStreamSynchronize(e->lc.stream));
+    if (edges_out) *edges_out = ci.edges;
+    if (rounds_out) *rounds_out = ci.rounds;
+    return GM_OK;
 }
 
 gm_status gm_get_options(const gm_engine *e, gm_options *out) {
@@ -1810,6 +2012,8 @@ gm_status gm_serve_open(gm_engine *e, const gm_serve_options *opt, gm_server **o
         return e->fail(GM_ERR_ARG, "serve option out of range");
     if (!e->has_graph) return e->fail(GM_ERR_STATE, "no data graph loaded");
     if (e->device < 0) return e->fail(GM_ERR_DEVICE, "host-only engine (created with device -1) cannot serve");
+    if (e->opt.candidate_graph)
+        return e->fail(GM_ERR_STATE, "the candidate graph is built per query: use gm_count or gm_enumerate");
     if (o.slots == 0) o.slots = 2;
     if (o.max_batch == 0) o.max_batch = 256;
     HIP_TRY(e, hipSetDevice(e->device));

@@ -56,6 +56,10 @@ struct Plan {
     // bit j of sb_gt[i] requires M(phi[i]) < M(phi[j]), for j < i
     uint32_t sb_lt[kMaxK];
     uint32_t sb_gt[kMaxK];
+    // candidate graph (opt-in): the query edge from position i to position l
+    // (i a backward neighbour) is list gslot[l] + (backward neighbours of l
+    // before i) of SearchArgs::gbounds
+    uint32_t gslot[kMaxK];
 };
 
 // Per-query results of a launch.  The count (atomics from every wavefront on
@@ -164,8 +168,66 @@ struct SearchArgs {
     int32_t steal_threshold;
     int32_t slim;              // 1: slim stack layout (membership tests on label slices)
     int32_t sb;                // 1: some plan of the launch has symmetry-breaking conditions
+    int32_t cg;                // 1: search the candidate graph: lcol holds its lists, and the list of
+                               // query edge e for vertex v is lcol[gbounds[2 * (e * gn + v)] ..
+                               // gbounds[2 * (e * gn + v) + 1])
+    const uint32_t *gbounds;
+    unsigned long long gn;     // |V(G)|
     int32_t measure_next;      // expansion: add the next level's size bound to ctl->measure
 };
+
+// Candidate graph of one query (candidate.hip).  Positions follow the
+// matching order; adj[l] bit j: positions l and j are adjacent in Q.
+struct CandQuery {
+    int32_t k;
+    int32_t lab[kMaxK];
+    int32_t qdeg[kMaxK];
+    uint32_t adj[kMaxK];
+};
+
+constexpr int kMaxCandEdges = kMaxK * (kMaxK - 1) / 2;
+
+// Query edge e = (src, dst), src before dst in the order: its lists belong to
+// the candidates clist[start .. start + len) of src, and their lengths and
+// offsets sit at first .. first + len - 1 of the per-edge arrays.  One entry
+// per query edge in a small device table.
+struct CandEdge {
+    int32_t src, dst;
+    uint32_t start, len;
+    uint32_t first;
+    uint32_t pad[3];
+};
+
+// Words of one position's bitmap (a multiple of two: 64 vertices per wavefront).
+unsigned long long cand_bitmap_words(int32_t n);
+// Scratch words launch_exclusive_scan needs for m values.
+unsigned long long cand_scan_temp_words(unsigned long long m);
+// C0 of every position into bits (q.k rows of cand_bitmap_words(n) words).
+hipError_t launch_cand_init(const VInfo *vinfo, int32_t n, const CandQuery &q, uint32_t *bits, int num_cu,
+                            hipStream_t s);
+// One sweep of the support filter; sets *changed to 1 if it cleared a bit.
+hipError_t launch_cand_refine(const int32_t *lcol, const uint32_t *loff, int32_t stride, int32_t n,
+                              const CandQuery &q, uint32_t *bits, uint32_t *changed, int num_cu, hipStream_t s);
+// Candidate lists of all k positions, ids ascending, into clist; bounds[l] ..
+// bounds[l + 1] is position l's (k + 1 words).  rank: k * cand_bitmap_words(n)
+// words of scratch; tmp: prefix-sum scratch for as many values.
+hipError_t launch_cand_lists(const uint32_t *bits, int32_t n, int32_t k, uint32_t *rank, uint32_t *tmp,
+                             int32_t *clist, uint32_t *bounds, int num_cu, hipStream_t s);
+// List lengths of the m query edges into cnt (most = the largest len) and their
+// sum (added to *total).
+hipError_t launch_cand_count(const int32_t *lcol, const uint32_t *loff, int32_t stride, int32_t n,
+                             const CandQuery &q, const uint32_t *bits, const CandEdge *edges, int32_t m,
+                             unsigned long long most, const int32_t *clist, uint32_t *cnt, unsigned long long *total,
+                             int num_cu, hipStream_t s);
+// The lists at offsets offs (the exclusive prefix sum of the lengths) and their
+// bounds in gbounds (2 words per edge and vertex, m * n * 2 in all).
+hipError_t launch_cand_fill(const int32_t *lcol, const uint32_t *loff, int32_t stride, int32_t n,
+                            const CandQuery &q, const uint32_t *bits, const CandEdge *edges, int32_t m,
+                            unsigned long long most, const int32_t *clist, const uint32_t *offs, int32_t *gcol,
+                            uint32_t *gbounds, int num_cu, hipStream_t s);
+// In-place exclusive prefix sum of m uint32 values whose total fits 32 bits;
+// tmp holds cand_scan_temp_words(m) words.
+hipError_t launch_exclusive_scan(uint32_t *x, unsigned long long m, uint32_t *tmp, hipStream_t s);
 
 // Launchers implemented in kernels.hip.  All return hipSuccess or the launch error.
 // measure_lab >= 0: also add up the candidates' label slices for position 1

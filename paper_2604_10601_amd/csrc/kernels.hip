@@ -226,6 +226,13 @@ __device__ __forceinline__ void push_entry(WaveStack &S, int i, uint32_t lane, i
     }
 }
 
+// Candidate-graph list of the query edge from position i (a backward neighbour
+// of l) to position l: the edges of position l are numbered from gslot[l] in
+// the order of their backward positions.
+__device__ __forceinline__ uint32_t cg_slot(PlanPtr P, int l, uint32_t bw, int i) {
+    return P->gslot[l] + static_cast<uint32_t>(__builtin_popcount(bw & ((1u << i) - 1u)));
+}
+
 struct Gen {
     uint32_t tasks;    // |C^L| by the paper's rule: the smallest backward list
     uint32_t scanned;  // length of the label slice that is actually scanned
@@ -239,7 +246,7 @@ struct Gen {
 // lists only the slice of candidates labelled L(phi[l]) can pass the label
 // check, so the smallest such slice is scanned instead (earliest position on
 // ties); it yields exactly the same valid extensions.
-template <bool SLIM>
+template <bool SLIM, bool CG = false>
 __device__ __forceinline__ Gen generate_tasks(WaveStack &S, const SearchArgs &a, PlanPtr P, int l, uint64_t F,
                                               uint32_t lane) {
     Gen g{0u, 0u, 0u};
@@ -255,7 +262,16 @@ __device__ __forceinline__ Gen generate_tasks(WaveStack &S, const SearchArgs &a,
         for (int i = l - 1; i >= lowest; --i) {
             if ((bw >> i) & 1u) {
                 uint32_t d, sa, sn;
-                if (SLIM) {
+                if (CG) {
+                    // candidate graph: N(w) restricted to C(phi[l]), one list per query edge
+                    const uint32_t *o =
+                        a.gbounds + 2ull * (static_cast<unsigned long long>(cg_slot(P, l, bw, i)) * a.gn +
+                                            static_cast<uint32_t>(S.v[i * kWave + q]));
+                    sa = o[0];
+                    sn = o[1] - sa;
+                    d = sn;
+                    ++g.lookups;
+                } else if (SLIM) {
                     const uint32_t *o = a.loff + static_cast<unsigned long long>(S.v[i * kWave + q]) * stride;
                     const uint32_t row0 = o[0];
                     d = o[stride - 1 + (sliced ? 0 : 1)] - row0;  // whole list: first to last bound
@@ -387,8 +403,9 @@ __device__ __forceinline__ Round scatter(WaveStack &S, const int32_t *__restrict
 // Test the collected lists (lo[t], n[t]); n[t] == 0 marks an unused slot.  In
 // the slim layout lo[t] holds the list's vertex w and n[t] = 1 until the bounds
 // of w's slice with the candidate's label are read here, for all slots at once;
-// an empty slice means v is not a neighbour of w.
-template <bool SLIM>
+// an empty slice means v is not a neighbour of w.  On the candidate graph n[t]
+// carries the list's query edge + 1 and the bounds come from G' instead.
+template <bool SLIM, bool CG = false>
 __device__ __forceinline__ bool test_lists(const SearchArgs &a, uint32_t lab, uint32_t (&lo)[kLists],
                                            uint32_t (&n)[kLists], int32_t v, uint32_t &probes, uint32_t &lookups) {
     if (SLIM) {
@@ -398,7 +415,10 @@ __device__ __forceinline__ bool test_lists(const SearchArgs &a, uint32_t lab, ui
         for (int t = 0; t < kLists; ++t) {
             const bool use = n[t] != 0u;
             const uint32_t w = use ? lo[t] : 0u;
-            const uint32_t *o = a.loff + static_cast<unsigned long long>(w) * a.loff_stride + lab;
+            // candidate graph: n[t] - 1 is the list's query edge, and the
+            // candidate is in C(phi[l]), so N(w) restricted to C(phi[l]) answers
+            const uint32_t *o = CG ? a.gbounds + 2ull * (static_cast<unsigned long long>(use ? n[t] - 1u : 0u) * a.gn + w)
+                                   : a.loff + static_cast<unsigned long long>(w) * a.loff_stride + lab;
             b0[t] = use ? o[0] : 0u;
             b1[t] = use ? o[1] : 0u;
             hub[t] = use && a.hub_id ? a.hub_id[w] : -1;  // read in the same round as the bounds
@@ -437,7 +457,7 @@ __device__ __forceinline__ bool test_lists(const SearchArgs &a, uint32_t lab, ui
 // other than the one the candidate came from.  The lists are collected during
 // the walk (kLists at a time, the slot index being the same in every lane) and
 // tested together.
-template <bool SLIM, bool SB>
+template <bool SLIM, bool SB, bool CG = false>
 __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanPtr P, int l, const Round &r,
                                         uint32_t lane, VInfo &vi, uint32_t &probes, uint32_t &lookups) {
     bool ok = lane < r.ntask;
@@ -467,13 +487,13 @@ __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanP
             if ((bw >> i) & 1u) {
                 const bool skip = static_cast<uint32_t>(i) == js;
                 const uint32_t st = SLIM ? static_cast<uint32_t>(w) : S.st[i * kWave + q];
-                const uint32_t len = skip ? 0u : (SLIM ? 1u : ent_deg(S, i, q));
+                const uint32_t len = skip ? 0u : (CG ? cg_slot(P, l, bw, i) + 1u : (SLIM ? 1u : ent_deg(S, i, q)));
                 if (used == 0) { lo[0] = st; n[0] = len; }
                 else if (used == 1) { lo[1] = st; n[1] = len; }
                 else if (used == 2) { lo[2] = st; n[2] = len; }
                 else { lo[3] = st; n[3] = len; }
                 if (++used == kLists) {
-                    if (!test_lists<SLIM>(a, lab, lo, n, r.v, probes, lookups)) {
+                    if (!test_lists<SLIM, CG>(a, lab, lo, n, r.v, probes, lookups)) {
                         ok = false;
                         break;
                     }
@@ -483,7 +503,7 @@ __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanP
             }
             q = ent_pid<SLIM>(S, i, q);
         }
-        if (ok && used > 0) ok = test_lists<SLIM>(a, lab, lo, n, r.v, probes, lookups);
+        if (ok && used > 0) ok = test_lists<SLIM, CG>(a, lab, lo, n, r.v, probes, lookups);
     }
     return ok;
 }
@@ -768,8 +788,9 @@ __device__ __forceinline__ unsigned int load_word(unsigned int *p) {
     return read_lane(v, 0);
 }
 
-template <int MODE, bool SLIM, bool SB>
+template <int MODE, bool SLIM, bool SB, bool CG>
 __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
+    static_assert(!CG || (SLIM && MODE != kExpand), "the candidate graph runs the slim depth-first search");
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     const int levels = a.levels;
     uint8_t *mine = lds + (threadIdx.x / kWave) * wave_lds_bytes(levels, MODE == kExpand, SLIM);
@@ -859,7 +880,7 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
                 r1.owner = lane;
                 r1.v = v;
                 VInfo vi;
-                const bool ok = process<SLIM, SB>(S, a, P, 1, r1, lane, vi, t.probes_run, t.lookups_run);
+                const bool ok = process<SLIM, SB, CG>(S, a, P, 1, r1, lane, vi, t.probes_run, t.lookups_run);
                 const uint64_t m = ballot(ok);
                 t.active += ntask;
                 t.issued += kWave;
@@ -880,7 +901,7 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
                 if (!m) continue;
                 lane0_add(&a.qctl[cq].live, 1);
                 push_entry<SLIM>(S, 1, lane, v, vi, lane);
-                const Gen g = generate_tasks<SLIM>(S, a, P, 2, m, lane);
+                const Gen g = generate_tasks<SLIM, CG>(S, a, P, 2, m, lane);
                 t.tasks += g.tasks;
                 t.scanned += g.scanned;
                 t.lookups += g.lookups;
@@ -913,7 +934,7 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
                 continue;
             }
             lane0_add(&a.qctl[cq].live, 1);
-            Gen g = generate_tasks<SLIM>(S, a, P, d, F0, lane);
+            Gen g = generate_tasks<SLIM, CG>(S, a, P, d, F0, lane);
             if (P->vmode) {  // first phase: each root's first hub_cut tasks only
                 first_phase_cut(S, P, lane);
                 g.scanned = g.scanned < P->hub_cut ? g.scanned : P->hub_cut;
@@ -987,7 +1008,7 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
                 }
                 push_entry<SLIM>(S, i, lane, v, vi, lane);
             }
-            generate_tasks<SLIM>(S, a, P, L, lanes, lane);  // already counted by the donor
+            generate_tasks<SLIM, CG>(S, a, P, L, lanes, lane);  // already counted by the donor
             // position 1 is donated only by first-phase items of a two-phase pool: keep their cut
             if (P->vmode && L == 1) first_phase_cut(S, P, lane);
             if (lane == 0) {
@@ -1018,7 +1039,7 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
             t.active += r.ntask;
             t.issued += kWave;
             VInfo vi;
-            const bool ok = process<SLIM, SB>(S, a, P, l, r, lane, vi, t.probes_run, t.lookups_run);
+            const bool ok = process<SLIM, SB, CG>(S, a, P, l, r, lane, vi, t.probes_run, t.lookups_run);
             const uint64_t m = ballot(ok);
             if (MODE == kExpand) {
                 if (m) {
@@ -1060,7 +1081,7 @@ __global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
                 t.count += __popcll(m);
             } else if (m) {
                 push_entry<SLIM>(S, l, lane, r.v, vi, r.owner);
-                const Gen g = generate_tasks<SLIM>(S, a, P, l + 1, m, lane);
+                const Gen g = generate_tasks<SLIM, CG>(S, a, P, l + 1, m, lane);
                 t.tasks += g.tasks;
                 t.scanned += g.scanned;
                 t.lookups += g.lookups;
@@ -1255,11 +1276,11 @@ __global__ __launch_bounds__(256) void root_scan_kernel(const VInfo *__restrict_
     }
 }
 
-template <int MODE, bool SLIM, bool SB>
+template <int MODE, bool SLIM, bool SB, bool CG>
 int blocks_per_cu(int levels, int waves_per_cu) {
     const size_t lds_bytes = wave_lds_bytes(levels, MODE == kExpand, SLIM) * kWavesPerBlock;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel<MODE, SLIM, SB>, kBlock, lds_bytes) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel<MODE, SLIM, SB, CG>, kBlock, lds_bytes) !=
             hipSuccess ||
         per_cu < 1)
         per_cu = 1;
@@ -1270,28 +1291,38 @@ int blocks_per_cu(int levels, int waves_per_cu) {
     return per_cu;
 }
 
-template <int MODE, bool SLIM, bool SB>
+template <int MODE, bool SLIM, bool SB, bool CG>
 hipError_t launch_persistent(const SearchArgs &a, int num_cu, int waves_per_cu, hipStream_t s, int *grid_waves) {
     if (a.levels < 1 || a.levels > kMaxK || a.nq < 1 || !a.plans || !a.qctl || a.nstreams < 1 || !a.streams)
         return hipErrorInvalidValue;
+    if (CG && (!a.gbounds || a.gn < 1)) return hipErrorInvalidValue;
     const size_t lds_bytes = wave_lds_bytes(a.levels, MODE == kExpand, SLIM) * kWavesPerBlock;
-    int blocks = num_cu * blocks_per_cu<MODE, SLIM, SB>(a.levels, waves_per_cu);
+    int blocks = num_cu * blocks_per_cu<MODE, SLIM, SB, CG>(a.levels, waves_per_cu);
     if (a.mail && blocks * kWavesPerBlock > a.steal_slots) blocks = a.steal_slots / kWavesPerBlock;  // one mailbox each
     if (blocks < 1) blocks = 1;
     if (grid_waves) *grid_waves = blocks * kWavesPerBlock;
-    hipLaunchKernelGGL((search_kernel<MODE, SLIM, SB>), dim3(blocks), dim3(kBlock), lds_bytes, s, a);
+    hipLaunchKernelGGL((search_kernel<MODE, SLIM, SB, CG>), dim3(blocks), dim3(kBlock), lds_bytes, s, a);
     return hipGetLastError();
 }
 
-// One of the twelve instantiations: mode x stack layout x symmetry conditions.
+// One of the instantiations: mode x stack layout x symmetry conditions, and the
+// candidate graph (slim layout, count and enumerate only).
 template <int MODE>
 hipError_t launch_mode(const SearchArgs &a, int num_cu, int waves_per_cu, hipStream_t s, int *grid_waves) {
-    if (a.slim) {
-        if (a.sb) return launch_persistent<MODE, true, true>(a, num_cu, waves_per_cu, s, grid_waves);
-        return launch_persistent<MODE, true, false>(a, num_cu, waves_per_cu, s, grid_waves);
+    if constexpr (MODE != kExpand) {
+        if (a.cg) {
+            if (a.sb) return launch_persistent<MODE, true, true, true>(a, num_cu, waves_per_cu, s, grid_waves);
+            return launch_persistent<MODE, true, false, true>(a, num_cu, waves_per_cu, s, grid_waves);
+        }
+    } else {
+        if (a.cg) return hipErrorInvalidValue;
     }
-    if (a.sb) return launch_persistent<MODE, false, true>(a, num_cu, waves_per_cu, s, grid_waves);
-    return launch_persistent<MODE, false, false>(a, num_cu, waves_per_cu, s, grid_waves);
+    if (a.slim) {
+        if (a.sb) return launch_persistent<MODE, true, true, false>(a, num_cu, waves_per_cu, s, grid_waves);
+        return launch_persistent<MODE, true, false, false>(a, num_cu, waves_per_cu, s, grid_waves);
+    }
+    if (a.sb) return launch_persistent<MODE, false, true, false>(a, num_cu, waves_per_cu, s, grid_waves);
+    return launch_persistent<MODE, false, false, false>(a, num_cu, waves_per_cu, s, grid_waves);
 }
 
 }  // namespace
@@ -1312,8 +1343,8 @@ hipError_t launch_expand(const SearchArgs &a, int num_cu, hipStream_t s) {
 }
 
 int search_waves(int levels, int num_cu, int waves_per_cu, bool slim) {
-    const int per_cu = slim ? blocks_per_cu<kCount, true, false>(levels, waves_per_cu)
-                            : blocks_per_cu<kCount, false, false>(levels, waves_per_cu);
+    const int per_cu = slim ? blocks_per_cu<kCount, true, false, false>(levels, waves_per_cu)
+                            : blocks_per_cu<kCount, false, false, false>(levels, waves_per_cu);
     return num_cu * per_cu * kWavesPerBlock;
 }
 

@@ -343,3 +343,17 @@ def batch_rmat20(num_queries: int = 10_000, seed: int = 40, g: Optional[Graph] =
     sizes = _rng(seed).integers(4, 33, size=num_queries)
     qs = walk_queries(g, sizes, seed, workers)
     return Workload("rmat20_ef16_zipf16_q4-32_mixed", g, qs, cap=1_000_000, time_limit_s=1.0)
+
+
+def cg_rmat20(per_size: int = 20, sizes: Sequence[int] = (16, 24, 32), g: Optional[Graph] = None) -> Workload:
+    """Large queries over a labelled graph, the workload class the paper searches
+    on a candidate graph: the scale-20 R-MAT edges with 16 labels drawn uniformly
+    at random (how the paper labels its graphs for large queries), and per_size
+    random-walk queries of each size (induced edges kept, labels copied).
+    Cap 1e9 per query and a 5 s limit, as for the large queries on scale 24."""
+    if g is None:
+        row_ptr, col = rmat(20, 16, seed=20)
+        g = Graph(row_ptr, col, uniform_labels(1 << 20, 16, seed=70))
+    qs = walk_queries(g, np.repeat(np.asarray(sizes), per_size), seed=71)
+    return Workload("rmat20_ef16_uniform16_q16-32", g, qs, cap=1_000_000_000, time_limit_s=5.0)
+

@@ -150,3 +150,26 @@ def test_bad_options():
     with pytest.raises(gm.GmError) as ei:
         gm.Engine(device=-2)
     assert ei.value.status == gm.GM_ERR_ARG
+    # the candidate graph runs on the two-phase pool with the slim stack only
+    for bad in (dict(tau=1000), dict(tau=-1), dict(stack_layout=1)):
+        with pytest.raises(gm.GmError) as ei:
+            gm.Engine(device=-1, candidate_graph=True, **bad)
+        assert ei.value.status == gm.GM_ERR_ARG, bad
+    with pytest.raises(gm.GmError) as ei:
+        gm.Engine(device=-1, hub_bitmap_mib=-1)
+    assert ei.value.status == gm.GM_ERR_ARG
+    opt = gm.Options()
+    opt.candidate_graph = 2
+    assert gm.load_library().gm_create(-1, ctypes.byref(opt), ctypes.byref(h)) == gm.GM_ERR_ARG
+
+
+def test_candidate_graph_host_checks():
+    with gm.Engine(device=-1, candidate_graph=True) as e:
+        qid = e.add(S.path_q(3))
+        expect(gm.GM_ERR_STATE, e.candidate_sets, qid)                              # no graph yet
+        e.load(S.complete(5))
+        expect(gm.GM_ERR_DEVICE, e.candidate_sets, qid)
+        expect(gm.GM_ERR_STATE, e.count_batch, [qid])                               # built per query
+        expect(gm.GM_ERR_STATE, e.tune_batch, [qid])
+        expect(gm.GM_ERR_DEVICE, e.count, qid)
+        assert e.options().candidate_graph == 1
