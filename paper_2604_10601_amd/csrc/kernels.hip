@@ -461,9 +461,15 @@ template <bool SLIM, bool SB, bool CG = false>
 __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanPtr P, int l, const Round &r,
                                         uint32_t lane, VInfo &vi, uint32_t &probes, uint32_t &lookups) {
     bool ok = lane < r.ntask;
+    // The vertex record serves the filters only (the slim stack keeps no copy of
+    // it), and often they hold already: a label slice holds that label alone,
+    // every candidate neighbours a matched vertex (degree >= 1), and a
+    // candidate-graph list holds only vertices that passed both filters.
+    const bool need = !SLIM || (!CG && (a.loff_stride <= 1 || P->qdeg[l] > 1));
     vi = make_uint2(0u, 0u);
-    if (ok) vi = a.vinfo[r.v];
-    ok = ok && vi_lab(vi) == static_cast<uint32_t>(P->lab[l]) && vi_deg(vi) >= static_cast<uint32_t>(P->qdeg[l]);
+    if (ok && need) vi = a.vinfo[r.v];
+    if (need)
+        ok = ok && vi_lab(vi) == static_cast<uint32_t>(P->lab[l]) && vi_deg(vi) >= static_cast<uint32_t>(P->qdeg[l]);
     if (ok) {
         const uint32_t bw = P->bwd[l];
         // symmetry-breaking conditions: only in launches that hold a query with them
