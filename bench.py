@@ -137,11 +137,11 @@ def _csvs(root: str, suffix: str):
 def kernel_key(name: str) -> str:
     """Short name of a dispatched kernel: search kernels by mode, copies, others by function name."""
     import re
-    m = re.search(r"search_kernel<(\d+), (true|false), (true|false), (true|false)>", name)
+    m = re.search(r"search_kernel<(\d+), (true|false), (true|false), (true|false), (\d+)>", name)
     if m:
         return {"0": "search", "1": "enumerate", "2": "expand"}[m.group(1)] + (
             "<slim" if m.group(2) == "true" else "<full") + (",sb" if m.group(3) == "true" else "") + (
-            ",cg>" if m.group(4) == "true" else ">")
+            ",cg" if m.group(4) == "true" else "") + (",5w>" if m.group(5) == "5" else ">")
     if "copyBuffer" in name:
         return "copy"
     base = name[:-1].rsplit("(", 1)[0] if name.endswith(")") else name

@@ -794,8 +794,10 @@ __device__ __forceinline__ unsigned int load_word(unsigned int *p) {
     return read_lane(v, 0);
 }
 
-template <int MODE, bool SLIM, bool SB, bool CG>
-__global__ __launch_bounds__(kBlock, 4) void search_kernel(SearchArgs a) {
+// OCC is the number of wavefronts per SIMD the registers are budgeted for:
+// 4 (up to 128 VGPRs, no spills) or 5 (96 VGPRs, a few spilled to scratch).
+template <int MODE, bool SLIM, bool SB, bool CG, int OCC>
+__global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
     static_assert(!CG || (SLIM && MODE != kExpand), "the candidate graph runs the slim depth-first search");
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     const int levels = a.levels;
@@ -1282,12 +1284,12 @@ __global__ __launch_bounds__(256) void root_scan_kernel(const VInfo *__restrict_
     }
 }
 
-template <int MODE, bool SLIM, bool SB, bool CG>
+template <int MODE, bool SLIM, bool SB, bool CG, int OCC>
 int blocks_per_cu(int levels, int waves_per_cu) {
     const size_t lds_bytes = wave_lds_bytes(levels, MODE == kExpand, SLIM) * kWavesPerBlock;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel<MODE, SLIM, SB, CG>, kBlock, lds_bytes) !=
-            hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel<MODE, SLIM, SB, CG, OCC>, kBlock,
+                                                     lds_bytes) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     if (waves_per_cu > 0) {
@@ -1297,38 +1299,58 @@ int blocks_per_cu(int levels, int waves_per_cu) {
     return per_cu;
 }
 
-template <int MODE, bool SLIM, bool SB, bool CG>
+template <int MODE, bool SLIM, bool SB, bool CG, int OCC>
 hipError_t launch_persistent(const SearchArgs &a, int num_cu, int waves_per_cu, hipStream_t s, int *grid_waves) {
     if (a.levels < 1 || a.levels > kMaxK || a.nq < 1 || !a.plans || !a.qctl || a.nstreams < 1 || !a.streams)
         return hipErrorInvalidValue;
     if (CG && (!a.gbounds || a.gn < 1)) return hipErrorInvalidValue;
     const size_t lds_bytes = wave_lds_bytes(a.levels, MODE == kExpand, SLIM) * kWavesPerBlock;
-    int blocks = num_cu * blocks_per_cu<MODE, SLIM, SB, CG>(a.levels, waves_per_cu);
+    int blocks = num_cu * blocks_per_cu<MODE, SLIM, SB, CG, OCC>(a.levels, waves_per_cu);
     if (a.mail && blocks * kWavesPerBlock > a.steal_slots) blocks = a.steal_slots / kWavesPerBlock;  // one mailbox each
     if (blocks < 1) blocks = 1;
     if (grid_waves) *grid_waves = blocks * kWavesPerBlock;
-    hipLaunchKernelGGL((search_kernel<MODE, SLIM, SB, CG>), dim3(blocks), dim3(kBlock), lds_bytes, s, a);
+    hipLaunchKernelGGL((search_kernel<MODE, SLIM, SB, CG, OCC>), dim3(blocks), dim3(kBlock), lds_bytes, s, a);
     return hipGetLastError();
 }
 
-// One of the instantiations: mode x stack layout x symmetry conditions, and the
-// candidate graph (slim layout, count and enumerate only).
+// The slim plain-graph kernels also exist with the register budget of five
+// wavefronts per SIMD.  Their spills cost more than the extra wavefront brings
+// where LDS cannot hold five stacks per SIMD anyway (queries of 10+ vertices),
+// so they run only where the occupancy calculator says they fit more.
+template <int MODE, bool SB>
+bool five_waves_fit(int levels, int waves_per_cu) {
+    return blocks_per_cu<MODE, true, SB, false, 5>(levels, waves_per_cu) >
+           blocks_per_cu<MODE, true, SB, false, 4>(levels, waves_per_cu);
+}
+
+// One of the instantiations: mode x stack layout x symmetry conditions x
+// candidate graph (slim layout, count and enumerate only) x register budget.
 template <int MODE>
 hipError_t launch_mode(const SearchArgs &a, int num_cu, int waves_per_cu, hipStream_t s, int *grid_waves) {
     if constexpr (MODE != kExpand) {
         if (a.cg) {
-            if (a.sb) return launch_persistent<MODE, true, true, true>(a, num_cu, waves_per_cu, s, grid_waves);
-            return launch_persistent<MODE, true, false, true>(a, num_cu, waves_per_cu, s, grid_waves);
+            if (a.sb) return launch_persistent<MODE, true, true, true, 4>(a, num_cu, waves_per_cu, s, grid_waves);
+            return launch_persistent<MODE, true, false, true, 4>(a, num_cu, waves_per_cu, s, grid_waves);
+        }
+        if (a.slim) {
+            if (a.sb) {
+                if (five_waves_fit<MODE, true>(a.levels, waves_per_cu))
+                    return launch_persistent<MODE, true, true, false, 5>(a, num_cu, waves_per_cu, s, grid_waves);
+                return launch_persistent<MODE, true, true, false, 4>(a, num_cu, waves_per_cu, s, grid_waves);
+            }
+            if (five_waves_fit<MODE, false>(a.levels, waves_per_cu))
+                return launch_persistent<MODE, true, false, false, 5>(a, num_cu, waves_per_cu, s, grid_waves);
+            return launch_persistent<MODE, true, false, false, 4>(a, num_cu, waves_per_cu, s, grid_waves);
         }
     } else {
         if (a.cg) return hipErrorInvalidValue;
+        if (a.slim) {
+            if (a.sb) return launch_persistent<MODE, true, true, false, 4>(a, num_cu, waves_per_cu, s, grid_waves);
+            return launch_persistent<MODE, true, false, false, 4>(a, num_cu, waves_per_cu, s, grid_waves);
+        }
     }
-    if (a.slim) {
-        if (a.sb) return launch_persistent<MODE, true, true, false>(a, num_cu, waves_per_cu, s, grid_waves);
-        return launch_persistent<MODE, true, false, false>(a, num_cu, waves_per_cu, s, grid_waves);
-    }
-    if (a.sb) return launch_persistent<MODE, false, true, false>(a, num_cu, waves_per_cu, s, grid_waves);
-    return launch_persistent<MODE, false, false, false>(a, num_cu, waves_per_cu, s, grid_waves);
+    if (a.sb) return launch_persistent<MODE, false, true, false, 4>(a, num_cu, waves_per_cu, s, grid_waves);
+    return launch_persistent<MODE, false, false, false, 4>(a, num_cu, waves_per_cu, s, grid_waves);
 }
 
 }  // namespace
@@ -1349,8 +1371,10 @@ hipError_t launch_expand(const SearchArgs &a, int num_cu, hipStream_t s) {
 }
 
 int search_waves(int levels, int num_cu, int waves_per_cu, bool slim) {
-    const int per_cu = slim ? blocks_per_cu<kCount, true, false, false>(levels, waves_per_cu)
-                            : blocks_per_cu<kCount, false, false, false>(levels, waves_per_cu);
+    int per_cu = slim ? blocks_per_cu<kCount, true, false, false, 4>(levels, waves_per_cu)
+                      : blocks_per_cu<kCount, false, false, false, 4>(levels, waves_per_cu);
+    if (slim && five_waves_fit<kCount, false>(levels, waves_per_cu))
+        per_cu = blocks_per_cu<kCount, true, false, false, 5>(levels, waves_per_cu);
     return num_cu * per_cu * kWavesPerBlock;
 }
 
