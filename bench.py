@@ -196,6 +196,8 @@ def main() -> int:
                          "serve = the same queries as a Poisson request stream through the server; "
                          "cg = large queries searched on G and on the candidate graph G'")
     ap.add_argument("--cg-per-size", type=int, default=20, help="cg: queries of each size (16, 24, 32)")
+    ap.add_argument("--cg-graph", default="rmat", choices=["rmat", "er"],
+                    help="cg: R-MAT scale 20 (hubs) or G(n, M) with 2^20 vertices and average degree 16")
     ap.add_argument("--load", type=float, default=0.7,
                     help="serve: offered rate as a fraction of the measured batched throughput")
     ap.add_argument("--slots", type=int, default=0, help="serve: concurrent launches (0 = default)")
@@ -218,6 +220,8 @@ def main() -> int:
     ap.add_argument("--hub-cut", type=int, default=0, help="first-phase tasks per root (0 = default 16)")
     ap.add_argument("--no-hub-bitmaps", action="store_true", help="bisect hub lists instead of reading bitmaps")
     ap.add_argument("--hub-mib", type=int, default=0, help="device memory for hub bitmaps in MiB (0 = default)")
+    ap.add_argument("--roots-per-item", type=int, default=0,
+                    help="first-vertex candidates per first-phase work item, 1..64 (0 = automatic)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB device-to-device (counter calibration)")
     ap.add_argument("--summarize-stats", metavar="DIR", help="print the kernel table of a rocprofv3 --stats run")
@@ -275,7 +279,8 @@ def main() -> int:
     e = gm.Engine(device=0, tau=args.tau, waves_per_cu=args.waves_per_cu,
                   disable_stealing=args.disable_stealing, steal_threshold=args.steal_threshold,
                   stack_layout=args.stack_layout, pool_hub_cut=args.hub_cut,
-                  disable_hub_bitmaps=args.no_hub_bitmaps, hub_bitmap_mib=args.hub_mib)
+                  disable_hub_bitmaps=args.no_hub_bitmaps, hub_bitmap_mib=args.hub_mib,
+                  pool_roots_per_item=args.roots_per_item)
     e.load(w.graph)
     qids = [e.add(q) for q in w.queries]
     phis = [e.get_order(qid) for qid in qids]
@@ -663,14 +668,15 @@ def bench_cg(args, gm) -> int:
     that finish in both modes must agree; total time and p50/p99 are compared."""
     from paper_2604_10601_amd import workloads as wl
     t = time.time()
-    w = wl.cg_rmat20(per_size=args.cg_per_size)
+    w = wl.cg_rmat20(per_size=args.cg_per_size) if args.cg_graph == "rmat" else wl.cg_er20(per_size=args.cg_per_size)
     if args.time_limit >= 0:
         w.time_limit_s = args.time_limit
     log(f"workload {w.name}: n={w.graph.n} |E|={w.graph.num_edges} queries={len(w.queries)} "
         f"({time.time() - t:.1f} s to generate)")
     runs = {}
     for mode in ("plain", "candidate_graph"):
-        with gm.Engine(device=0, candidate_graph=(mode == "candidate_graph")) as e:
+        with gm.Engine(device=0, candidate_graph=(mode == "candidate_graph"),
+                       pool_roots_per_item=args.roots_per_item) as e:
             e.load(w.graph)
             qids = [e.add(q) for q in w.queries]
             e.count(qids[0], cap=w.cap, time_limit_s=w.time_limit_s)  # warm-up

@@ -119,6 +119,12 @@ typedef struct {
      * and gm_serve_open return GM_ERR_STATE while it is on.  Device memory:
      * |E(Q)| * (|V(G)| + 1) * 4 bytes of list bounds plus the lists. */
     int32_t candidate_graph;
+    /* Default pool (tau = 0): first-vertex candidates per first-phase work
+     * item, 1..64.  0 = automatic: 1 when a query has fewer candidates than
+     * the launch has resident wavefronts (each starts on a root of its own),
+     * else 64. */
+    int32_t pool_roots_per_item;
+    int32_t reserved[3];
 } gm_options;
 
 /* Result of one count or enumerate call. */
@@ -139,7 +145,8 @@ typedef struct {
     uint64_t rows;         /* enumerate: rows written */
     double kernel_ms;      /* device time of the depth-first search launch alone (HIP events) */
     int32_t grid_waves;    /* wavefronts in that launch */
-    int32_t candidate_rounds; /* candidate graph: filter sweeps run (0 when off) */
+    int32_t candidate_rounds; /* candidate graph: filter sweeps up to the first that dropped
+                                 nothing (0 when off) */
     uint64_t kernel_tasks;  /* tasks, probes and matches of that launch alone (the pool */
     uint64_t kernel_probes; /* expansion before it is excluded) */
     uint64_t kernel_groups;
@@ -206,7 +213,7 @@ gm_status gm_enumerate(gm_engine *engine, int32_t qid, int32_t *rows, uint64_t c
  * k * ((n + 31) / 32) words, n = |V(G)|; bit (v % 32) of bits[u * ((n + 31) /
  * 32) + v / 32] is set iff v is in C(u), u a query vertex.  edges_out (may be
  * NULL): list entries of G', summed over the query's edges.  rounds_out (may
- * be NULL): filter sweeps run, the last one dropping nothing.  Errors:
+ * be NULL): filter sweeps up to the first one that dropped nothing.  Errors:
  * GM_ERR_STATE without a graph, GM_ERR_DEVICE on a host-only engine. */
 gm_status gm_candidate_sets(gm_engine *engine, int32_t qid, uint32_t *bits, uint64_t *edges_out,
                             int32_t *rounds_out);

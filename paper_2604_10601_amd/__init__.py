@@ -54,6 +54,8 @@ class Options(ctypes.Structure):
         ("disable_hub_bitmaps", ctypes.c_int32),
         ("hub_bitmap_mib", ctypes.c_int32),
         ("candidate_graph", ctypes.c_int32),
+        ("pool_roots_per_item", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -260,7 +262,7 @@ class Engine:
                  steal_threshold: int = 0, waves_per_cu: int = 0, skip_symmetry_check: bool = False,
                  stack_layout: int = 0, disable_label_index: bool = False, batch_single_launch: bool = False,
                  batch_streams: int = 0, pool_hub_cut: int = 0, disable_hub_bitmaps: bool = False,
-                 hub_bitmap_mib: int = 0, candidate_graph: bool = False):
+                 hub_bitmap_mib: int = 0, candidate_graph: bool = False, pool_roots_per_item: int = 0):
         self._lib = load_library()
         opt = Options()
         opt.tau = tau
@@ -277,6 +279,7 @@ class Engine:
         opt.disable_hub_bitmaps = int(disable_hub_bitmaps)
         opt.hub_bitmap_mib = hub_bitmap_mib
         opt.candidate_graph = int(candidate_graph)
+        opt.pool_roots_per_item = pool_roots_per_item
         h = ctypes.c_void_p()
         st = self._lib.gm_create(device, ctypes.byref(opt), ctypes.byref(h))
         if st != GM_OK:

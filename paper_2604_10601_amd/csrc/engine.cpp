@@ -266,7 +266,7 @@ struct gm_engine {
     int32_t *d_cedges = nullptr;   // per query edge: gm::CandEdge
     int32_t *d_gbounds = nullptr;  // list bounds per query edge and candidate
     int32_t *d_gcol = nullptr;     // the lists
-    int32_t *d_cmisc = nullptr;    // [0] sweep flag, [2..3] list total, [8 ..] position bounds
+    int32_t *d_cmisc = nullptr;    // [0..3] sweep flags, [4..5] list total, [8 ..] position bounds
     size_t cbits_cap = 0, crank_cap = 0, ctmp_cap = 0, clist_cap = 0, cedges_cap = 0, gbounds_cap = 0, gcol_cap = 0,
            cmisc_cap = 0;
     std::vector<gm::CandEdge> h_cedges;
@@ -707,20 +707,27 @@ gm_status build_candidate_graph(gm_engine *e, const Plan &p, CandInfo *ci, uint3
     if (st) return st;
     uint32_t *bits = reinterpret_cast<uint32_t *>(e->d_cbits);
     uint32_t *flag = reinterpret_cast<uint32_t *>(e->d_cmisc);
-    auto *list_total = reinterpret_cast<unsigned long long *>(e->d_cmisc + 2);
+    auto *list_total = reinterpret_cast<unsigned long long *>(e->d_cmisc + 4);
     uint32_t *bounds = reinterpret_cast<uint32_t *>(e->d_cmisc + 8);  // k + 1 words
     uint32_t *scratch = reinterpret_cast<uint32_t *>(e->d_crank);
     uint32_t *tmp = reinterpret_cast<uint32_t *>(e->d_ctmp);
 
     HIP_TRY(e, gm::launch_cand_init(e->d_vinfo, n, cq, bits, e->num_cu, s));
-    for (;;) {
-        uint32_t changed = 0;
-        HIP_TRY(e, hipMemsetAsync(flag, 0, sizeof(uint32_t), s));
-        HIP_TRY(e, gm::launch_cand_refine(e->d_lcol, e->d_loff, e->loff_stride, n, cq, bits, flag, e->num_cu, s));
-        HIP_TRY(e, hipMemcpyAsync(&changed, flag, sizeof(changed), hipMemcpyDeviceToHost, s));
+    // Sweeps go kSweeps at a time, each with its own flag, and one read-back
+    // per group: a sweep after the fixed point clears nothing and costs one
+    // pass, where a host round trip per sweep would cost more.
+    constexpr int kSweeps = 4;
+    for (bool done = false; !done;) {
+        uint32_t changed[kSweeps] = {};
+        HIP_TRY(e, hipMemsetAsync(flag, 0, sizeof(changed), s));
+        for (int r = 0; r < kSweeps; ++r)
+            HIP_TRY(e, gm::launch_cand_refine(e->d_lcol, e->d_loff, e->loff_stride, n, cq, bits, flag + r, e->num_cu, s));
+        HIP_TRY(e, hipMemcpyAsync(changed, flag, sizeof(changed), hipMemcpyDeviceToHost, s));
         HIP_TRY(e, hipStreamSynchronize(s));
-        ++ci->rounds;
-        if (!changed) break;
+        for (int r = 0; r < kSweeps && !done; ++r) {
+            ++ci->rounds;
+            done = changed[r] == 0;
+        }
     }
     uint32_t hb[kMaxK + 1] = {};
     HIP_TRY(e, gm::launch_cand_lists(bits, n, k, scratch, tmp, e->d_clist, bounds, e->num_cu, s));
@@ -753,6 +760,7 @@ gm_status build_candidate_graph(gm_engine *e, const Plan &p, CandInfo *ci, uint3
     if (st) return st;
     HIP_TRY(e, gm::launch_cand_fill(e->d_lcol, e->d_loff, e->loff_stride, n, cq, bits, d_edges, m, most, e->d_clist,
                                     scratch, e->d_gcol, reinterpret_cast<uint32_t *>(e->d_gbounds), e->num_cu, s));
+    HIP_TRY(e, hipStreamSynchronize(s));  // the build's time ends with its last kernel
     return GM_OK;
 }
 
@@ -829,7 +837,18 @@ gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, ui
     p.hub_cut = e->opt.pool_hub_cut > 0 ? static_cast<uint32_t>(e->opt.pool_hub_cut) : kHubCut;
     p.vrow0 = 0;
     p.perm_mul = root_order(R);
-    p.item_split = items_of(R);
+    if (e->opt.pool_roots_per_item > 0) {
+        p.rpi = static_cast<uint32_t>(e->opt.pool_roots_per_item);
+    } else {
+        // Fewer roots than resident wavefronts: one root per item, so every root
+        // starts on a wavefront of its own (a candidate graph often leaves that
+        // few).  Otherwise 64: measured on the scale-20 workload, items of R /
+        // wavefronts roots (about 3) ran 3 % slower than 64.
+        const unsigned long long waves = static_cast<unsigned long long>(
+            std::max(1, gm::search_waves(q->k, e->num_cu, e->opt.waves_per_cu, cg || use_slim(e, q->k))));
+        p.rpi = R < waves ? 1u : static_cast<uint32_t>(gm::kWave);
+    }
+    p.item_split = (R + p.rpi - 1) / p.rpi;
     e->lc.h_plans.assign(1, p);
     e->lc.h_streams.assign(1, gm::StreamCtl{});
     e->lc.h_streams[0].plan0 = 0;
@@ -1654,7 +1673,8 @@ gm_status gm_create(int32_t device, const gm_options *opt, gm_engine **out) {
     if (opt) o = *opt;
     if (o.stack_layout < 0 || o.stack_layout > 2 || o.steal_threshold < 0 || o.waves_per_cu < 0 ||
         o.pool_row_limit < 0 || o.batch_single_launch < 0 || o.batch_single_launch > 1 || o.batch_streams < 0 ||
-        o.pool_hub_cut < 0 || o.hub_bitmap_mib < 0 || o.candidate_graph < 0 || o.candidate_graph > 1) {
+        o.pool_hub_cut < 0 || o.hub_bitmap_mib < 0 || o.candidate_graph < 0 || o.candidate_graph > 1 ||
+        o.pool_roots_per_item < 0 || o.pool_roots_per_item > 64) {
         g_create_error = "option out of range";
         return GM_ERR_ARG;
     }

@@ -56,6 +56,10 @@ struct Plan {
     // bit j of sb_gt[i] requires M(phi[i]) < M(phi[j]), for j < i
     uint32_t sb_lt[kMaxK];
     uint32_t sb_gt[kMaxK];
+    // rows per work item of the pool's first part (0 = 64, one per lane): fewer
+    // when a query has few roots, so that more wavefronts start at once
+    uint32_t rpi;
+    uint32_t pad_rpi;
     // candidate graph (opt-in): the query edge from position i to position l
     // (i a backward neighbour) is list gslot[l] + (backward neighbours of l
     // before i) of SearchArgs::gbounds

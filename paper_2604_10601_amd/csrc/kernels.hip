@@ -920,9 +920,10 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                 break;
             }
             const int d = P->depth;
-            const unsigned long long r0 = (it - P->item0) * kWave;
+            const uint32_t rpi = P->rpi ? P->rpi : static_cast<uint32_t>(kWave);
+            const unsigned long long r0 = (it - P->item0) * rpi;
             const unsigned long long left = P->rows - r0;
-            const uint32_t nrows = left < kWave ? static_cast<uint32_t>(left) : kWave;
+            const uint32_t nrows = left < rpi ? static_cast<uint32_t>(left) : rpi;
             const bool mine = lane < nrows;
             const int32_t *src = a.pool + P->row0 + permuted(r0 + lane, P->perm_mul, P->rows) *
                                                         static_cast<unsigned long long>(d);

@@ -345,6 +345,16 @@ def batch_rmat20(num_queries: int = 10_000, seed: int = 40, g: Optional[Graph] =
     return Workload("rmat20_ef16_zipf16_q4-32_mixed", g, qs, cap=1_000_000, time_limit_s=1.0)
 
 
+def cg_er20(per_size: int = 20, sizes: Sequence[int] = (16, 24, 32)) -> Workload:
+    """Large queries over a labelled graph without hubs: G(n, M) with n = 2^20
+    and M = 2^23 (average degree 16), 16 labels drawn uniformly, random-walk
+    queries of each size.  Cap 1e9 per query, 5 s limit."""
+    row_ptr, col = erdos_renyi(1 << 20, 1 << 23, seed=72)
+    g = Graph(row_ptr, col, uniform_labels(1 << 20, 16, seed=73))
+    qs = walk_queries(g, np.repeat(np.asarray(sizes), per_size), seed=74)
+    return Workload("er20_d16_uniform16_q16-32", g, qs, cap=1_000_000_000, time_limit_s=5.0)
+
+
 def cg_rmat20(per_size: int = 20, sizes: Sequence[int] = (16, 24, 32), g: Optional[Graph] = None) -> Workload:
     """Large queries over a labelled graph, the workload class the paper searches
     on a candidate graph: the scale-20 R-MAT edges with 16 labels drawn uniformly

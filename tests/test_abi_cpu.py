@@ -155,9 +155,10 @@ def test_bad_options():
         with pytest.raises(gm.GmError) as ei:
             gm.Engine(device=-1, candidate_graph=True, **bad)
         assert ei.value.status == gm.GM_ERR_ARG, bad
-    with pytest.raises(gm.GmError) as ei:
-        gm.Engine(device=-1, hub_bitmap_mib=-1)
-    assert ei.value.status == gm.GM_ERR_ARG
+    for bad in (dict(hub_bitmap_mib=-1), dict(pool_roots_per_item=-1), dict(pool_roots_per_item=65)):
+        with pytest.raises(gm.GmError) as ei:
+            gm.Engine(device=-1, **bad)
+        assert ei.value.status == gm.GM_ERR_ARG, bad
     opt = gm.Options()
     opt.candidate_graph = 2
     assert gm.load_library().gm_create(-1, ctypes.byref(opt), ctypes.byref(h)) == gm.GM_ERR_ARG

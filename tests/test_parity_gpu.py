@@ -117,7 +117,8 @@ def test_cliques_closed_form(engine, n, k):
 
 
 @pytest.mark.parametrize("opts", [dict(), dict(steal_threshold=2), dict(disable_stealing=True),
-                                  dict(stack_layout=1, steal_threshold=2)])
+                                  dict(stack_layout=1, steal_threshold=2), dict(pool_roots_per_item=1),
+                                  dict(pool_roots_per_item=7, steal_threshold=2)])
 def test_first_vertex_lists_around_the_two_phase_cut(opts):
     """Roots with 63..130 candidates at position 1: the first phase keeps 64
     tasks per root and the second phase the rest, also when position 1 is
@@ -135,6 +136,20 @@ def test_first_vertex_lists_around_the_two_phase_cut(opts):
                     groups = sum(math.perm(n, i) for i in range(1, k))
                     assert (r.groups, r.tasks) == (groups, (n - 1) * groups), (n, k)
                     e.free_query(qid)
+
+
+@pytest.mark.parametrize("rpi", [1, 5, 64])
+def test_roots_per_item_against_oracle(rpi):
+    """First-phase items of 1, 5 and 64 roots (ragged last items): counts and counters."""
+    rng = np.random.default_rng(77 + rpi)
+    with gm.Engine(device=0, pool_roots_per_item=rpi) as e:
+        for trial in range(25):
+            g = S.gnp(int(rng.integers(20, 140)), float(rng.uniform(0.05, 0.3)), rng, 2)
+            q = S.random_connected_query(int(rng.integers(2, 6)), rng, extra_p=0.4, num_labels=2)
+            e.load(g)
+            _say(f"roots per item {rpi} trial {trial}")
+            r, o, _ = run_pair(e, g, q)
+            assert_same(r, o, f"rpi {rpi} trial {trial}")
 
 
 @pytest.mark.parametrize("disable", [False, True])
