@@ -1,0 +1,84 @@
+"""Host logic of bench.py (CPU only): kernel names, the algorithmic-byte count, the
+rocprofv3 summaries behind the roofline object, and the one-GPU contract."""
+import csv
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+SEARCH = "void gm::(anonymous namespace)::search_kernel<{}, {}, {}, {}, {}>(gm::SearchArgs)"
+
+
+def test_kernel_keys():
+    assert bench.kernel_key(SEARCH.format(0, "true", "false", "false", 4)) == "search<slim>"
+    assert bench.kernel_key(SEARCH.format(0, "true", "false", "false", 5)) == "search<slim,5w>"
+    assert bench.kernel_key(SEARCH.format(1, "true", "true", "true", 4)) == "enumerate<slim,sb,cg>"
+    assert bench.kernel_key(SEARCH.format(2, "false", "true", "false", 4)) == "expand<full,sb>"
+    assert bench.kernel_key("__amd_rocclr_copyBuffer") == "copy"
+    assert bench.kernel_key("gm::(anonymous namespace)::cand_fill_kernel(int const*)") == "cand_fill_kernel"
+
+
+def test_algorithmic_bytes():
+    # 12 B per scanned candidate, 8 B per slice lookup, 4 B per probe, 12 B per matched position of a pool row
+    assert bench.algorithmic_bytes(pool_rows=0, depth=1, scanned=1, lookups=0, probes=0) == 12
+    assert bench.algorithmic_bytes(pool_rows=10, depth=3, scanned=100, lookups=7, probes=5) == 1200 + 56 + 20 + 360
+
+
+def test_traffic_summary_is_used_only_for_the_same_sources(tmp_path, monkeypatch):
+    f = tmp_path / "traffic.txt"
+    f.write_text(f"# header\n\nkernel_sha: {bench.kernel_sha()}\ntraffic_bytes_per_launch: 12345\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.read_traffic() == {"bytes_per_launch": 12345.0}
+    f.write_text("kernel_sha: 0000000000000000\ntraffic_bytes_per_launch: 12345\n")
+    assert bench.read_traffic() is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
+    assert bench.read_traffic() is None
+
+
+def _write_csv(path, header, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_stats_and_counter_summaries(tmp_path):
+    stats = tmp_path / "stats" / "run_kernel_stats.csv"
+    _write_csv(str(stats), ["Name", "Calls", "TotalDurationNs", "AverageNs", "MinNs", "MaxNs", "Percentage"],
+               [[SEARCH.format(0, "true", "false", "false", 5), 2, 6e6, 3e6, 2e6, 4e6, 99.0],
+                ["__amd_rocclr_copyBuffer", 4, 4e3, 1e3, 1e3, 1e3, 1.0]])
+    out = bench.summarize_stats(str(tmp_path / "stats"))
+    assert out.splitlines()[0].startswith("search<slim,5w>")
+    assert "avg_ms=   3.0000" in out.splitlines()[0] and "calls=    2" in out.splitlines()[0]
+
+    def pmc(d, counter, search_vals, copy_vals):
+        rows = [[SEARCH.format(0, "true", "false", "false", 5), counter, v] for v in search_vals]
+        rows += [["__amd_rocclr_copyBuffer", counter, v] for v in copy_vals]
+        _write_csv(str(tmp_path / d / "run_counter_collection.csv"), ["Kernel_Name", "Counter_Name", "Counter_Value"],
+                   rows)
+
+    # the calibration copy moves 256 MiB: FETCH_SIZE reads half of it, WRITE_SIZE all of it
+    pmc("fetch", "FETCH_SIZE", [900.0, 1100.0], [131072.0, 4.0])
+    pmc("write", "WRITE_SIZE", [10.0, 30.0], [262144.0])
+    got = bench.pmc_per_kernel(str(tmp_path / "fetch"), "FETCH_SIZE")
+    assert got["search<slim,5w>"] == (1000.0, 2) and got["copy"] == (131072.0, 1)
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--summarize-traffic",
+                          str(tmp_path / "fetch"), str(tmp_path / "write"), "--copy-bytes", str(256 << 20)],
+                         capture_output=True, text=True, check=True)
+    kv = dict(line.split(": ", 1) for line in res.stdout.splitlines())
+    assert kv["kernel"] == "search<slim,5w>"
+    assert float(kv["fetch_scale"]) == pytest.approx(2.0) and float(kv["write_scale"]) == pytest.approx(1.0)
+    assert int(kv["traffic_bytes_per_launch"]) == 1000 * 1024 * 2 + 20 * 1024
+
+
+def test_more_than_one_gpu_is_refused():
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True)
+    assert res.returncode == 2
+    assert "exactly one GPU" in res.stderr
