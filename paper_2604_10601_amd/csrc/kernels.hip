@@ -100,8 +100,12 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
 // neighbours waits for the longest search, not for the sum of them.  Each
 // range is narrowed until at most kTail entries remain, and those tails are
 // read with independent loads (indices clamped into the list).  Returns true
-// iff v is in every used list; adds the 4-byte reads made to probes.
-constexpr int kLists = 4;
+// iff v is in every used list; adds the 4-byte reads made to probes.  One list
+// at a time: testing several in lockstep saves round trips on dense queries
+// but costs more instructions per candidate than those trips (same box, the
+// 8-vertex workload: 34.7, 37.1 and 38.5 G embeddings/s with four, two and
+// one; the 12-32-vertex sample: 14.6, 15.4 and 15.7).
+constexpr int kLists = 1;
 constexpr uint32_t kTail = 4;
 
 __device__ __forceinline__ bool in_all_lists(const int32_t *__restrict__ col, uint32_t (&lo)[kLists],
@@ -476,8 +480,8 @@ __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanP
         const uint32_t sblt = SB ? P->sb_lt[l] : 0u, sbgt = SB ? P->sb_gt[l] : 0u;
         const uint32_t js = S.cl[l * kWave + r.owner] & 0xffu;
         const uint32_t lab = a.loff_stride > 1 ? static_cast<uint32_t>(P->lab[l]) : 0u;
-        uint32_t lo[kLists] = {0u, 0u, 0u, 0u};
-        uint32_t n[kLists] = {0u, 0u, 0u, 0u};
+        uint32_t lo[kLists] = {};
+        uint32_t n[kLists] = {};
         int used = 0;
         uint32_t q = r.owner;
         for (int i = l - 1; i >= 0; --i) {
@@ -494,17 +498,17 @@ __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanP
                 const bool skip = static_cast<uint32_t>(i) == js;
                 const uint32_t st = SLIM ? static_cast<uint32_t>(w) : S.st[i * kWave + q];
                 const uint32_t len = skip ? 0u : (CG ? cg_slot(P, l, bw, i) + 1u : (SLIM ? 1u : ent_deg(S, i, q)));
-                if (used == 0) { lo[0] = st; n[0] = len; }
-                else if (used == 1) { lo[1] = st; n[1] = len; }
-                else if (used == 2) { lo[2] = st; n[2] = len; }
-                else { lo[3] = st; n[3] = len; }
+#pragma unroll
+                for (int t = 0; t < kLists; ++t)
+                    if (used == t) { lo[t] = st; n[t] = len; }
                 if (++used == kLists) {
                     if (!test_lists<SLIM, CG>(a, lab, lo, n, r.v, probes, lookups)) {
                         ok = false;
                         break;
                     }
                     used = 0;
-                    n[0] = n[1] = n[2] = n[3] = 0u;
+#pragma unroll
+                    for (int t = 0; t < kLists; ++t) n[t] = 0u;
                 }
             }
             q = ent_pid<SLIM>(S, i, q);
