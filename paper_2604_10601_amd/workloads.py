@@ -2,8 +2,9 @@
 
 This module only builds inputs.  It holds none of the matching arithmetic, so
 both the GPU path and the CPU oracle can be fed from it.  Every generator takes
-an explicit integer seed and draws from numpy's PCG64, so a (recipe, seed) pair
-names one input exactly.
+an explicit integer seed and draws from numpy's PCG64 or from the counter-based
+SplitMix64 streams of workloads_gen.c, so a (recipe, seed) pair names one input
+exactly.
 
 Recipes (the paper's own datasets are not available; these stand in for them):
 
@@ -14,20 +15,70 @@ Recipes (the paper's own datasets are not available; these stand in for them):
   Table 3): ``edge_factor * 2**scale`` draws; each of the ``scale`` bits of a
   draw picks one quadrant (a, b, c, d) with one uniform number; the result is
   symmetrised, self-loops and duplicates are dropped and vertex ids are
-  permuted at random.
+  permuted at random.  Built natively (workloads_gen.c).
 * Zipf labels (App. A, "label distribution skewness"): P(l) proportional to
   (l+1)**-s for l in [0, |Sigma|-1].
 * Queries (Sec. 6.1, "Query Sets"): a random walk from a random seed vertex
-  adds unseen neighbours until k vertices are collected; the query is the
-  induced subgraph on them with labels copied, ids in discovery order.  Dense
+  adds unseen neighbours until k vertices are collected (restarting after
+  100 * k steps without a new one); the query is the induced subgraph on them
+  with labels copied, ids in discovery order.  Walks are native
+  (workloads_gen.c), walk t of a set drawing from stream t of its seed.  Dense
   means average query degree >= 3 (App. A, "query graph density").
 """
 from __future__ import annotations
 
+import ctypes
 import dataclasses
+import os
+import subprocess
+import threading
 from typing import List, Optional, Sequence
 
 import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_GEN_SRC = os.path.join(_HERE, "workloads_gen.c")
+_GEN_LIB = os.path.join(_HERE, "libworkloads.so")
+_gen = None
+_gen_lock = threading.Lock()
+
+
+def build_native(force: bool = False) -> str:
+    """Compile workloads_gen.c into libworkloads.so next to it (gcc, pthreads)."""
+    if force or not os.path.exists(_GEN_LIB) or os.path.getmtime(_GEN_LIB) < os.path.getmtime(_GEN_SRC):
+        tmp = _GEN_LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O3", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-pthread",
+                               "-o", tmp, _GEN_SRC])
+        os.replace(tmp, _GEN_LIB)
+    return _GEN_LIB
+
+
+def _native():
+    global _gen
+    with _gen_lock:
+        if _gen is None:
+            if not os.path.exists(_GEN_LIB) or os.path.getmtime(_GEN_LIB) < os.path.getmtime(_GEN_SRC):
+                build_native()
+            lib = ctypes.CDLL(_GEN_LIB)
+            vp, i32, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+            lib.wg_rmat.argtypes = [ctypes.c_int, ctypes.c_int, dbl, dbl, dbl, u64, vp, ctypes.c_int,
+                                    ctypes.POINTER(vp)]
+            lib.wg_rmat.restype = ctypes.c_int
+            lib.wg_graph_nnz.argtypes = [vp]
+            lib.wg_graph_nnz.restype = i64
+            lib.wg_graph_fetch.argtypes = [vp, vp, vp]
+            lib.wg_graph_fetch.restype = ctypes.c_int
+            lib.wg_graph_free.argtypes = [vp]
+            lib.wg_graph_free.restype = None
+            lib.wg_walk.argtypes = [vp, vp, vp, i64, ctypes.c_int, u64, u64, i64, vp, vp, ctypes.POINTER(i32)]
+            lib.wg_walk.restype = i64
+            _gen = lib
+        return _gen
+
+
+def _ptr(a: np.ndarray) -> ctypes.c_void_p:
+    assert a.flags["C_CONTIGUOUS"]
+    return ctypes.c_void_p(a.ctypes.data)
 
 
 @dataclasses.dataclass
@@ -101,18 +152,6 @@ def csr_from_pairs(n: int, lo: np.ndarray, hi: np.ndarray) -> tuple:
     return row_ptr, dst
 
 
-def dedup_undirected(n: int, u: np.ndarray, v: np.ndarray) -> tuple:
-    """Canonical distinct undirected pairs (lo < hi) from arbitrary endpoint arrays."""
-    u = np.asarray(u, dtype=np.int64)
-    v = np.asarray(v, dtype=np.int64)
-    lo = np.minimum(u, v)
-    hi = np.maximum(u, v)
-    keep = lo != hi
-    key = np.unique(lo[keep] * n + hi[keep])
-    lo = key // n
-    return lo, key - lo * n
-
-
 def erdos_renyi(n: int, m: int, seed: int) -> tuple:
     """G(n, M): m distinct non-loop pairs drawn uniformly without replacement."""
     total = n * (n - 1) // 2
@@ -127,38 +166,35 @@ def erdos_renyi(n: int, m: int, seed: int) -> tuple:
     return csr_from_pairs(n, lo, hi)
 
 
-def rmat_pairs(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int,
-               chunk: int = 1 << 23) -> tuple:
-    """Raw R-MAT endpoint draws (before symmetrisation and dedup)."""
-    rng = _rng(seed)
-    draws = edge_factor << scale
-    src = np.empty(draws, dtype=np.int64)
-    dst = np.empty(draws, dtype=np.int64)
-    ab, abc = a + b, a + b + c
-    for s0 in range(0, draws, chunk):
-        cnt = min(chunk, draws - s0)
-        s = np.zeros(cnt, dtype=np.int64)
-        d = np.zeros(cnt, dtype=np.int64)
-        for _ in range(scale):
-            u = rng.random(cnt)
-            down = u >= ab
-            right = ((u >= a) & (u < ab)) | (u >= abc)
-            s = (s << 1) | down
-            d = (d << 1) | right
-        src[s0:s0 + cnt] = s
-        dst[s0:s0 + cnt] = d
-    return src, dst
+def _native_threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
 
 
 def rmat(scale: int, edge_factor: int, seed: int, a: float = 0.57, b: float = 0.19,
-         c: float = 0.19) -> tuple:
-    """Symmetrised, deduplicated, loop-free R-MAT graph with randomly permuted ids."""
+         c: float = 0.19, threads: int = 0) -> tuple:
+    """Symmetrised, deduplicated, loop-free R-MAT graph with randomly permuted ids.
+
+    The draws and the CSR build are native (workloads_gen.c: counter-based
+    SplitMix64, so the graph does not depend on the thread count); the id
+    permutation is numpy's PCG64 with seed + 1_000_003.
+    """
     n = 1 << scale
-    src, dst = rmat_pairs(scale, edge_factor, a, b, c, seed)
-    lo, hi = dedup_undirected(n, src, dst)
-    del src, dst
-    perm = _rng(seed + 1_000_003).permutation(n).astype(np.int64)
-    return csr_from_pairs(n, perm[lo], perm[hi])
+    perm = np.ascontiguousarray(_rng(seed + 1_000_003).permutation(n).astype(np.int64))
+    lib = _native()
+    h = ctypes.c_void_p()
+    rc = lib.wg_rmat(scale, edge_factor, a, b, c, ctypes.c_uint64(seed), _ptr(perm), threads or _native_threads(),
+                     ctypes.byref(h))
+    if rc != 0:
+        raise RuntimeError(f"R-MAT generator failed with code {rc}")
+    try:
+        nnz = int(lib.wg_graph_nnz(h))
+        row_ptr = np.empty(n + 1, dtype=np.int64)
+        col = np.empty(max(nnz, 1), dtype=np.int32)
+        if lib.wg_graph_fetch(h, _ptr(row_ptr), _ptr(col)) != 0:
+            raise RuntimeError("R-MAT generator: fetch failed")
+    finally:
+        lib.wg_graph_free(h)
+    return row_ptr, col[:nnz]
 
 
 def uniform_labels(n: int, num_labels: int, seed: int) -> np.ndarray:
@@ -189,39 +225,42 @@ def induced_query(g: Graph, verts: Sequence[int]) -> Query:
                  witness=verts.astype(np.int32))
 
 
-def random_walk_vertices(g: Graph, k: int, rng: np.random.Generator) -> np.ndarray:
-    """k distinct vertices visited by a random walk; restarts after 100*k idle steps."""
-    deg = g.degrees()
-    live = np.flatnonzero(deg > 0)
+def _live(g: Graph) -> np.ndarray:
+    live = np.flatnonzero(np.diff(g.row_ptr) > 0).astype(np.int32)
     if live.shape[0] == 0:
         raise ValueError("graph has no edges")
-    while True:
-        cur = int(live[rng.integers(live.shape[0])])
-        seen = {cur: 0}
-        order = [cur]
-        idle = 0
-        while len(order) < k and idle < 100 * k:
-            nxt = int(g.col[g.row_ptr[cur] + rng.integers(deg[cur])])
-            if nxt in seen:
-                idle += 1
-            else:
-                seen[nxt] = len(order)
-                order.append(nxt)
-                idle = 0
-            cur = nxt
-        if len(order) == k:
-            return np.asarray(order, dtype=np.int64)
+    return live
+
+
+def walk_query(g: Graph, k: int, seed: int, stream: int, live: Optional[np.ndarray] = None) -> Query:
+    """The query cut out by random walk `stream` under `seed` (workloads_gen.c): k
+    distinct vertices in discovery order, the induced edges among them, labels copied."""
+    live = _live(g) if live is None else live
+    row_ptr = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(g.col, dtype=np.int32)
+    verts = np.empty(k, dtype=np.int32)
+    edges = np.empty(max(1, k * (k - 1)), dtype=np.int32)
+    m = ctypes.c_int32(0)
+    rc = _native().wg_walk(_ptr(row_ptr), _ptr(col), _ptr(live), live.shape[0], k, ctypes.c_uint64(seed),
+                           ctypes.c_uint64(stream), ctypes.c_int64(1_000_000), _ptr(verts), _ptr(edges),
+                           ctypes.byref(m))
+    if rc < 0:
+        raise RuntimeError(f"random walk failed with code {rc} (k={k}: no component that large?)")
+    e = edges[:2 * m.value].reshape(-1, 2).copy()
+    return Query(k=k, edges=e, labels=g.labels[verts].astype(np.int32), witness=verts.copy())
 
 
 def extract_queries(g: Graph, k_list: Sequence[int], n_dense: int, n_sparse: int, seed: int,
-                    max_attempts: int = 200000) -> List[Query]:
+                    max_attempts: int = 1_000_000) -> List[Query]:
     """For every k in k_list: n_dense dense and n_sparse sparse random-walk queries.
 
-    Queries whose density class is already full are rejected and redrawn.
+    Attempt t (counted across all of k_list) is walk stream t under `seed`;
+    queries whose density class is already full are rejected.
     Order of the result: grouped by k, dense first, then sparse.
     """
-    rng = _rng(seed)
+    live = _live(g)
     out: List[Query] = []
+    t = 0
     for k in k_list:
         dense: List[Query] = []
         sparse: List[Query] = []
@@ -230,7 +269,8 @@ def extract_queries(g: Graph, k_list: Sequence[int], n_dense: int, n_sparse: int
             attempts += 1
             if attempts > max_attempts:
                 raise RuntimeError(f"could not fill dense/sparse quotas for k={k}")
-            q = induced_query(g, random_walk_vertices(g, k, rng))
+            q = walk_query(g, k, seed, t, live)
+            t += 1
             if q.dense and len(dense) < n_dense:
                 dense.append(q)
             elif (not q.dense) and len(sparse) < n_sparse:
@@ -241,9 +281,15 @@ def extract_queries(g: Graph, k_list: Sequence[int], n_dense: int, n_sparse: int
 
 
 def extract_queries_any(g: Graph, k: int, count: int, seed: int) -> List[Query]:
-    """count random-walk queries of size k with no density quota."""
-    rng = _rng(seed)
-    return [induced_query(g, random_walk_vertices(g, k, rng)) for _ in range(count)]
+    """count random-walk queries of size k (streams 0 .. count-1) with no density quota."""
+    live = _live(g)
+    return [walk_query(g, k, seed, i, live) for i in range(count)]
+
+
+def walk_queries(g: Graph, sizes: Sequence[int], seed: int) -> List[Query]:
+    """Random-walk queries of the given sizes, query i from walk stream i under `seed`."""
+    live = _live(g)
+    return [walk_query(g, int(k), seed, i, live) for i, k in enumerate(sizes)]
 
 
 # ---------------------------------------------------------------------------
@@ -293,35 +339,6 @@ def large_rmat24(per_class: int = 25, g: Optional[Graph] = None) -> Workload:
     return Workload("rmat24_ef16_zipf8_q12-32", g, qs, cap=1_000_000_000, time_limit_s=60.0)
 
 
-_WALK_GRAPH: Optional[Graph] = None  # graph shared with forked query-drawing workers
-
-
-def _walk_queries(args) -> List[Query]:
-    sizes, seed = args
-    g = _WALK_GRAPH
-    rng = _rng(seed)
-    return [induced_query(g, random_walk_vertices(g, int(k), rng)) for k in sizes]
-
-
-def walk_queries(g: Graph, sizes: Sequence[int], seed: int, workers: int = 8) -> List[Query]:
-    """Random-walk queries of the given sizes, drawn in chunks of 500 with seeds
-    1000 * seed + chunk (the set does not depend on `workers`)."""
-    global _WALK_GRAPH
-    sizes = np.asarray(sizes)
-    chunks = [(sizes[c:c + 500], 1000 * seed + c // 500) for c in range(0, sizes.shape[0], 500)]
-    _WALK_GRAPH = g
-    try:
-        if workers > 1 and len(chunks) > 1:
-            import multiprocessing as mp
-            with mp.get_context("fork").Pool(min(workers, len(chunks))) as pool:
-                parts = pool.map(_walk_queries, chunks)
-        else:
-            parts = [_walk_queries(c) for c in chunks]
-    finally:
-        _WALK_GRAPH = None
-    return [q for part in parts for q in part]
-
-
 def rmat22_graph() -> Graph:
     """R-MAT scale 22, edge factor 16, 16 Zipf(1.0) labels (the scale-20 recipe, larger)."""
     row_ptr, col = rmat(22, 16, seed=52)
@@ -333,15 +350,13 @@ def order_sizes(n: int, seed: int) -> np.ndarray:
     return _rng(seed).integers(8, 33, size=n)
 
 
-def batch_rmat20(num_queries: int = 10_000, seed: int = 40, g: Optional[Graph] = None,
-                 workers: int = 8) -> Workload:
+def batch_rmat20(num_queries: int = 10_000, seed: int = 40, g: Optional[Graph] = None) -> Workload:
     """The R-MAT scale-20 graph with num_queries random-walk queries whose sizes are
     uniform in 4..32 (labels copied from G, so they follow G's label frequencies).
-    Per query: cap 1e6 embeddings, 1 s time limit.  Queries are drawn in chunks of
-    500, chunk c with seed 1000 * seed + c, so the set does not depend on `workers`."""
+    Per query: cap 1e6 embeddings, 1 s time limit."""
     g = rmat20_graph() if g is None else g
     sizes = _rng(seed).integers(4, 33, size=num_queries)
-    qs = walk_queries(g, sizes, seed, workers)
+    qs = walk_queries(g, sizes, seed)
     return Workload("rmat20_ef16_zipf16_q4-32_mixed", g, qs, cap=1_000_000, time_limit_s=1.0)
 
 
