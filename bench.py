@@ -26,8 +26,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2604_10601_amd", "csrc", f)
-               for f in ("kernels.hip", "gm_internal.h", "engine.cpp")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_kernel_rmat20_q8_traffic.txt")
+               for f in ("kernels.hip", "gm_internal.h", "engine.cpp", "graph_build.hip")]
 
 
 def log(msg: str) -> None:
@@ -42,22 +41,18 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(pool_rows: int, depth: int, scanned: int, lookups: int, probes: int) -> int:
-    """Bytes the search kernel must read by the method's own accounting.
-
-    per scanned candidate: 4 B id from the neighbour list + 8 B vertex record
-    (label, degree, list start); per label-slice lookup: 8 B (two bounds); per
-    membership probe: 4 B list entry; per pool row: depth x (4 B id + 8 B record).
-    """
-    return 12 * scanned + 8 * lookups + 4 * probes + 12 * depth * pool_rows
+def traffic_file_for(workload: str) -> str:
+    """Committed counter summary of the search kernel on a workload."""
+    short = {"rmat24_ef16_zipf8_q12-32": "rmat24_q12-32", "rmat20_ef16_zipf16_q8": "rmat20_q8"}.get(workload, workload)
+    return os.path.join(ROOT, "profiles", f"search_kernel_{short}_traffic.txt")
 
 
-def read_traffic() -> dict | None:
-    """HBM traffic per launch from the committed counter summary, if it matches this kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(path: str) -> dict | None:
+    """HBM traffic per launch from a committed counter summary, if it matches this kernel source."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
@@ -90,15 +85,18 @@ def make_workload(name: str, num_queries: int, stride: int = 1):
     return w
 
 
-def cpu_baseline(w, phis, budget_s: float, cap: int, per_query_s: float) -> dict:
-    """The oracle, as it is, on the host cores, over a bounded sample of the same queries."""
+def cpu_baseline(w, phis, budget_s: float, cap: int, per_query_s: float, gpu_results) -> dict:
+    """The oracle, as it is, on the host cores, over a bounded sample of the same
+    queries; its counts are compared with the GPU's for every query both decided."""
     import oracle
     total = 0
     secs = 0.0
     used = 0
     threads = 0
     capped = 0
-    for q, phi in zip(w.queries, phis):
+    compared = 0
+    mismatched = []
+    for i, (q, phi) in enumerate(zip(w.queries, phis)):
         if secs >= budget_s:
             break
         r = oracle.count(w.graph, q, order=phi, cap=cap, time_limit_s=per_query_s)
@@ -107,11 +105,17 @@ def cpu_baseline(w, phis, budget_s: float, cap: int, per_query_s: float) -> dict
         used += 1
         threads = r.threads
         capped += r.outcome == oracle.CAPPED
+        g = gpu_results[i]
+        if r.outcome != oracle.TIMEOUT and g.outcome != 2:
+            compared += 1
+            if (r.count, r.outcome) != (g.count, g.outcome):
+                mismatched.append(i)
     rate = total / secs if secs > 0 else 0.0
     return {"value": rate, "unit": "embeddings/s", "cores": threads, "kind": "oracle",
             "sample": (f"first {used} of the {len(w.queries)} queries in workload order, each with the "
                        f"workload's cap ({cap}) and at most {per_query_s} s ({capped} reached the cap); "
-                       f"stopped after {secs:.1f} s of oracle time")}
+                       f"stopped after {secs:.1f} s of oracle time"),
+            "counts_compared": compared, "same_counts": not mismatched, "mismatched_queries": mismatched}
 
 
 def copy_probe(nbytes: int) -> None:
@@ -190,7 +194,7 @@ def main() -> int:
     ap.add_argument("--train-limit", type=float, default=0.05, help="learned: time limit of the training runs (s)")
     ap.add_argument("--eval-cap", type=int, default=1_000_000, help="learned: cap of the evaluation runs")
     ap.add_argument("--eval-limit", type=float, default=1.0, help="learned: time limit of the evaluation runs (s)")
-    ap.add_argument("--workload", default="medium",
+    ap.add_argument("--workload", default="large",
                     choices=["medium", "small", "large", "batch", "serve", "learned", "cg"],
                     help="batch = 10,000 mixed-size queries in shared launches (autotuned); "
                          "serve = the same queries as a Poisson request stream through the server; "
@@ -210,6 +214,11 @@ def main() -> int:
     ap.add_argument("--time-limit", type=float, default=-1.0, help="override the workload's per-query limit")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle time budget for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-side-medium", action="store_true",
+                    help="large workload: skip the side measurement of the 8-vertex scale-20 workload")
+    ap.add_argument("--merge-ratio", type=int, default=0,
+                    help="LDS-staged intersection: stage a list when its length <= ratio x the candidates "
+                         "testing it (0 = default, -1 = never)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the extra gm_count_batch pass over the same queries (profiling runs)")
     ap.add_argument("--tau", type=int, default=0)
@@ -276,48 +285,36 @@ def main() -> int:
         w.time_limit_s = args.time_limit
     log(f"workload {w.name}: n={w.graph.n} |E|={w.graph.num_edges} queries={len(w.queries)} "
         f"({time.time() - t:.1f} s to generate)")
-    e = gm.Engine(device=0, tau=args.tau, waves_per_cu=args.waves_per_cu,
-                  disable_stealing=args.disable_stealing, steal_threshold=args.steal_threshold,
-                  stack_layout=args.stack_layout, pool_hub_cut=args.hub_cut,
-                  disable_hub_bitmaps=args.no_hub_bitmaps, hub_bitmap_mib=args.hub_mib,
-                  pool_roots_per_item=args.roots_per_item)
+    opts = dict(tau=args.tau, waves_per_cu=args.waves_per_cu, disable_stealing=args.disable_stealing,
+                steal_threshold=args.steal_threshold, stack_layout=args.stack_layout, pool_hub_cut=args.hub_cut,
+                disable_hub_bitmaps=args.no_hub_bitmaps, hub_bitmap_mib=args.hub_mib,
+                pool_roots_per_item=args.roots_per_item, merge_ratio=args.merge_ratio)
+    e = gm.Engine(device=0, **opts)
+    t = time.time()
     e.load(w.graph)
     qids = [e.add(q) for q in w.queries]
     phis = [e.get_order(qid) for qid in qids]
     cap = w.cap
     limit = w.time_limit_s
-
-    def step(tag: str):
-        res = []
-        for i, qid in enumerate(qids):
-            res.append(e.count(qid, cap=cap, time_limit_s=limit))
-            r = res[-1]
-            log(f"  {tag} query {i}: count={r.count} outcome={r.outcome} {r.search_ms:.2f} ms "
-                f"(kernel {r.kernel_ms:.2f} ms, pool {r.pool_rows} rows at depth {r.pool_depth})")
-        log(f"{tag}: {sum(r.count for r in res)} embeddings, "
-            f"{sum(r.search_ms for r in res):.1f} ms search time")
-        return res
+    log(f"graph and queries loaded in {time.time() - t:.1f} s")
 
     for i in range(args.warmup):
-        step(f"warmup {i}")
+        res = plain_pass(e, qids, cap, limit)
+        log(f"warmup {i}: {pass_line(res)}")
     t0 = time.perf_counter()
     steps = []
     for i in range(args.steps):
-        steps.append(step(f"step {i}"))
+        steps.append(plain_pass(e, qids, cap, limit))
     t1 = time.perf_counter()
     wall = t1 - t0
+    for i, res in enumerate(steps):  # progress is written after the timed region
+        log(f"step {i}: {pass_line(res)}")
 
-    flat = [r for s in steps for r in s]
+    flat = [r for s_ in steps for r in s_]
     solved = [r for r in flat if r.outcome != gm.GM_TIMEOUT]
     embeddings = sum(r.count for r in flat)
     tasks = sum(r.tasks for r in flat)
     lat = np.array([r.search_ms for r in flat])
-    kernel_s = sum(r.kernel_ms for r in flat) / 1000.0
-    launches = sum(1 for r in flat if r.kernel_ms > 0)
-    b_alg = sum(algorithmic_bytes(r.pool_rows, r.pool_depth, r.kernel_scanned, r.kernel_lookups, r.kernel_probes)
-                for r in flat)
-    achieved = b_alg / kernel_s / 1e9 if kernel_s > 0 else 0.0
-    traffic = read_traffic()
     outcomes = {"done": sum(r.outcome == gm.GM_DONE for r in steps[-1]),
                 "capped": sum(r.outcome == gm.GM_CAPPED for r in steps[-1]),
                 "timeout": sum(r.outcome == gm.GM_TIMEOUT for r in steps[-1])}
@@ -341,7 +338,9 @@ def main() -> int:
                    "initial_pool": (f"breadth-first to tau={args.tau}" if args.tau > 0 else
                                     "first-vertex candidates" if args.tau < 0 else "two-phase pool"),
                    "work_stealing": not args.disable_stealing},
+        # the paper's task count: sum of |C^L| over task groups (Sec. 4.1)
         "intersected_edges_per_s": tasks / wall,
+        # candidates actually read (label slices of C^L)
         "scanned_candidates_per_s": sum(r.scanned for r in flat) / wall,
         "query_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                              "mean": float(lat.mean())},
@@ -349,18 +348,7 @@ def main() -> int:
         "solved_queries": len(solved) // max(1, args.steps),
         "idle_rate": 1.0 - sum(r.lanes_active for r in flat) / max(1, sum(r.lanes_issued for r in flat)),
         "steals_per_step": sum(r.steals for r in flat) // max(1, args.steps),
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic["bytes_per_launch"] if traffic else None,
-            "kernel": "search_kernel (persistent depth-first search)",
-            "launches": launches,
-            "avg_launch_ms": kernel_s * 1000.0 / max(1, launches),
-            "algorithmic_bytes_per_launch": b_alg / max(1, launches),
-        },
+        "roofline": roofline(flat, traffic_file_for(w.name)),
     }
     if not args.no_batched:
         # the same queries in shared persistent launches (gm_count_batch), one call
@@ -371,15 +359,84 @@ def main() -> int:
         out["batched"] = {"value": binfo.count / bwall, "unit": "embeddings/s", "ms": bwall * 1000.0,
                           "kernel_ms": binfo.kernel_ms, "launches": binfo.launches,
                           "same_counts": all((a.count, a.outcome) == (b.count, b.outcome)
-                                             for a, b in zip(steps[-1], bres))}
+                                             for a, b in zip(steps[-1], bres)
+                                             if a.outcome != gm.GM_TIMEOUT and b.outcome != gm.GM_TIMEOUT)}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(w, phis, args.cpu_seconds, cap, per_query_s=10.0)
+        out["cpu_baseline"] = cpu_baseline(w, phis, args.cpu_seconds, cap, 10.0, steps[-1])
     e.close()
+    if args.workload == "large" and not args.no_side_medium:
+        out["medium"] = side_medium(gm, opts)
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib << 20)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def plain_pass(e, qids, cap, limit):
+    """One step of the plain method: every query counted alone (gm_count), in order."""
+    return [e.count(qid, cap=cap, time_limit_s=limit) for qid in qids]
+
+
+def pass_line(res) -> str:
+    import paper_2604_10601_amd as gm
+    return (f"{sum(r.count for r in res)} embeddings, {sum(r.search_ms for r in res):.1f} ms search time, "
+            f"outcomes done/capped/timeout = {sum(r.outcome == gm.GM_DONE for r in res)}/"
+            f"{sum(r.outcome == gm.GM_CAPPED for r in res)}/{sum(r.outcome == gm.GM_TIMEOUT for r in res)}, "
+            f"slowest query {max(r.search_ms for r in res):.1f} ms")
+
+
+def roofline(flat, traffic_file: str) -> dict:
+    """HBM roofline of the search kernel over the timed launches: bytes it
+    requested (counted by the kernel where each load or store is issued) over its
+    device time (HIP events on the engine's stream)."""
+    kernel_s = sum(r.kernel_ms for r in flat) / 1000.0
+    launches = sum(1 for r in flat if r.kernel_ms > 0)
+    issued = sum(r.kernel_bytes for r in flat)
+    late = sum(r.kernel_bytes_late for r in flat)
+    achieved = issued / kernel_s / 1e9 if kernel_s > 0 else 0.0
+    traffic = read_traffic(traffic_file)
+    return {
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic["bytes_per_launch"] if traffic else None,
+        "kernel": "search_kernel (persistent depth-first search)",
+        "launches": launches,
+        "avg_launch_ms": kernel_s * 1000.0 / max(1, launches),
+        "issued_bytes_per_launch": issued / max(1, launches),
+        # upper bound on the bytes spent after a query reached its cap (or time limit)
+        "late_bytes_per_launch_max": late / max(1, launches),
+        "frac_excluding_late": (issued - late) / kernel_s / 1e9 / HBM_PEAK_GBS if kernel_s > 0 else 0.0,
+        "traffic_fraction_of_peak": (traffic["bytes_per_launch"] * launches / kernel_s / 1e9 / HBM_PEAK_GBS
+                                     if traffic and kernel_s > 0 else None),
+    }
+
+
+def side_medium(gm, opts) -> dict:
+    """The 8-vertex workload on the scale-20 graph (100 queries, cap 1e8), three
+    passes after one warm-up: a side figure next to the headline."""
+    w = make_workload("medium", 0)
+    e = gm.Engine(device=0, **opts)
+    e.load(w.graph)
+    qids = [e.add(q) for q in w.queries]
+    plain_pass(e, qids, w.cap, w.time_limit_s)
+    t0 = time.perf_counter()
+    passes = [plain_pass(e, qids, w.cap, w.time_limit_s) for _ in range(3)]
+    wall = time.perf_counter() - t0
+    e.close()
+    flat = [r for p_ in passes for r in p_]
+    lat = np.array([r.search_ms for r in flat])
+    rf = roofline(flat, traffic_file_for(w.name))
+    return {"workload": w.name, "value": sum(r.count for r in flat) / wall, "unit": "embeddings/s",
+            "ms_per_pass": wall * 1000.0 / 3, "query_latency_ms": {"p50": float(np.percentile(lat, 50)),
+                                                                   "p99": float(np.percentile(lat, 99))},
+            "outcomes_per_pass": {"done": sum(r.outcome == gm.GM_DONE for r in passes[-1]),
+                                  "capped": sum(r.outcome == gm.GM_CAPPED for r in passes[-1])},
+            "roofline_frac": rf["frac"], "avg_launch_ms": rf["avg_launch_ms"],
+            "issued_bytes_per_launch": rf["issued_bytes_per_launch"]}
 
 
 def bench_batch(args, gm) -> int:
@@ -424,9 +481,8 @@ def bench_batch(args, gm) -> int:
     embeddings = sum(i.count for i in infos)
     kernel_s = sum(i.kernel_ms for i in infos) / 1000.0
     launches = sum(i.launches for i in infos)
-    b_alg = sum(algorithmic_bytes(r.pool_rows, 1, r.kernel_scanned, r.kernel_lookups, r.kernel_probes)
-                for res in results for r in res)
-    achieved = b_alg / kernel_s / 1e9 if kernel_s > 0 else 0.0
+    issued = sum(i.bytes for i in infos)
+    achieved = issued / kernel_s / 1e9 if kernel_s > 0 else 0.0
     alone_lat = np.array([a.search_ms for a in alone])
     out = {
         "metric": "embeddings/s",
@@ -460,7 +516,8 @@ def bench_batch(args, gm) -> int:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "search_kernel (persistent depth-first search, shared by the batch)",
                      "launches": launches, "avg_launch_ms": kernel_s * 1000.0 / max(1, launches),
-                     "algorithmic_bytes_per_launch": b_alg / max(1, launches)},
+                     "issued_bytes_per_launch": issued / max(1, launches),
+                     "late_bytes_per_launch_max": sum(i.bytes_late for i in infos) / max(1, launches)},
     }
     e.close()
     print(json.dumps(out), flush=True)

@@ -124,7 +124,16 @@ typedef struct {
      * the launch has resident wavefronts (each starts on a root of its own),
      * else 64. */
     int32_t pool_roots_per_item;
-    int32_t reserved[3];
+    /* Membership tests (Sec. 5.2, "Time Cost"; Alg. 2 Process): the candidates
+     * a parent hands out in one scatter round form an ascending run, and each of
+     * them is tested against the same backward neighbour lists.  A list of
+     * length n tested by a run of r candidates is staged into LDS by the run's
+     * lanes and intersected there by merge path when n <= merge_ratio * r (it
+     * must also fit the run's share of the staging buffer, 8 entries per lane);
+     * longer lists are bisected in device memory by each lane (or answered by a
+     * hub bitmap).  0 = default 4, -1 = never stage. */
+    int32_t merge_ratio;
+    int32_t reserved[2];
 } gm_options;
 
 /* Result of one count or enumerate call. */
@@ -157,6 +166,13 @@ typedef struct {
     uint64_t kernel_lookups; /* label-slice bound lookups (8 B each) of that launch */
     double candidate_ms;     /* candidate graph: host wall time of its build (inside search_ms) */
     uint64_t candidate_edges; /* candidate graph: list entries, summed over query edges */
+    uint64_t kernel_bytes;   /* device-memory bytes the depth-first search launch requested for
+                                this query: every load it issued (list entries, vertex records,
+                                slice bounds, bisection and tail probes, bitmap words, pool rows)
+                                and every row it wrote, counted where issued */
+    uint64_t kernel_bytes_late; /* part of kernel_bytes from the last 32-round window of each
+                                wavefront that saw the cap or time limit: an upper bound on the
+                                bytes spent after the query was decided */
 } gm_result;
 
 /* Create an engine on HIP device `device` (>= 0).  device = -1 creates a
@@ -175,6 +191,27 @@ void gm_destroy(gm_engine *engine);
  * row_ptr[n] < 2^32 and every degree < 2^24.  Violations: GM_ERR_GRAPH. */
 gm_status gm_load_graph(gm_engine *engine, int32_t n, const int64_t *row_ptr, const int32_t *col,
                         const int32_t *labels);
+
+/* Load G from CSR arrays that already live in device memory of the engine's
+ * device (for example tensors of a framework that owns the GPU's memory and
+ * streams), replacing any previous graph.  Same graph as gm_load_graph (Def. 1,
+ * Sec. 2.1), same checks and GM_ERR_GRAPH cases, with these layouts:
+ *   row_ptr: n + 1 offsets of row_ptr_bytes bytes each (4: int32, 8: int64);
+ *   col:     row_ptr[n] int32 neighbour ids, every row strictly ascending;
+ *   labels:  n uint8 label values (at most 255 distinct).
+ * Ownership: col is NOT copied.  The engine searches the caller's col in place
+ * until the graph is replaced or the engine destroyed; the caller must keep it
+ * alive and unchanged until then.  row_ptr and labels are read during the call
+ * only.  The engine allocates and owns the structures it derives (vertex
+ * records, label-sorted lists, hub bitmaps).
+ * hip_stream: the HIP stream (hipStream_t; NULL = the null stream) on which the
+ * caller produced the arrays; the load's copies and kernels run on it after the
+ * caller's queued work, and the call returns once they are done.
+ * Errors: GM_ERR_ARG for a pointer that is not device memory of this engine's
+ * device or a row_ptr_bytes other than 4 or 8, GM_ERR_DEVICE on a host-only
+ * engine, GM_ERR_STATE while a server is open. */
+gm_status gm_load_graph_device(gm_engine *engine, int32_t n, const void *row_ptr, int32_t row_ptr_bytes,
+                               const int32_t *col, const uint8_t *labels, void *hip_stream);
 
 /* Load Q: k vertices (1..32), m undirected edges given as pairs
  * edges[2e], edges[2e+1], labels[k].  Q must be simple and connected.  On
@@ -231,7 +268,9 @@ typedef struct {
     uint64_t probes;
     uint64_t groups;
     uint64_t steals;
-    uint64_t reserved[4];
+    uint64_t bytes;      /* kernel_bytes and kernel_bytes_late of gm_result, summed */
+    uint64_t bytes_late;
+    uint64_t reserved[2];
 } gm_batch_info;
 
 /* Count several queries in shared persistent launches (Alg. 2 for many

@@ -21,7 +21,7 @@ GM_OK, GM_ERR_ARG, GM_ERR_GRAPH, GM_ERR_QUERY, GM_ERR_ORDER = 0, -1, -2, -3, -4
 GM_ERR_NOMEM, GM_ERR_DEVICE, GM_ERR_BUFFER, GM_ERR_STATE = -5, -6, -7, -8
 GM_DONE, GM_CAPPED, GM_TIMEOUT = 0, 1, 2
 
-ABI_FUNCTIONS = ("gm_create", "gm_destroy", "gm_load_graph", "gm_load_query", "gm_set_order",
+ABI_FUNCTIONS = ("gm_create", "gm_destroy", "gm_load_graph", "gm_load_graph_device", "gm_load_query", "gm_set_order",
                  "gm_get_order", "gm_count", "gm_enumerate", "gm_count_batch", "gm_tune_batch",
                  "gm_get_options", "gm_serve_open", "gm_serve_submit", "gm_serve_poll", "gm_serve_stats",
                  "gm_serve_close", "gm_order_features", "gm_candidate_orders", "gm_model_create",
@@ -55,7 +55,8 @@ class Options(ctypes.Structure):
         ("hub_bitmap_mib", ctypes.c_int32),
         ("candidate_graph", ctypes.c_int32),
         ("pool_roots_per_item", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("merge_ratio", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -72,7 +73,9 @@ class BatchInfo(ctypes.Structure):
         ("probes", ctypes.c_uint64),
         ("groups", ctypes.c_uint64),
         ("steals", ctypes.c_uint64),
-        ("reserved", ctypes.c_uint64 * 4),
+        ("bytes", ctypes.c_uint64),
+        ("bytes_late", ctypes.c_uint64),
+        ("reserved", ctypes.c_uint64 * 2),
     ]
 
     def as_dict(self) -> dict:
@@ -120,6 +123,8 @@ class _CResult(ctypes.Structure):
         ("kernel_lookups", ctypes.c_uint64),
         ("candidate_ms", ctypes.c_double),
         ("candidate_edges", ctypes.c_uint64),
+        ("kernel_bytes", ctypes.c_uint64),
+        ("kernel_bytes_late", ctypes.c_uint64),
     ]
 
 
@@ -160,6 +165,8 @@ class Result:
     candidate_rounds: int = 0
     candidate_ms: float = 0.0
     candidate_edges: int = 0
+    kernel_bytes: int = 0
+    kernel_bytes_late: int = 0
 
     @property
     def idle_rate(self) -> float:
@@ -209,6 +216,7 @@ def load_library():
     lib.gm_destroy.argtypes = [p]
     lib.gm_destroy.restype = None
     lib.gm_load_graph.argtypes = [p, i32, p, p, p]
+    lib.gm_load_graph_device.argtypes = [p, i32, p, i32, p, p, p]
     lib.gm_load_query.argtypes = [p, i32, i32, p, p, ctypes.POINTER(i32)]
     lib.gm_set_order.argtypes = [p, i32, p]
     lib.gm_get_order.argtypes = [p, i32, p]
@@ -240,7 +248,7 @@ def load_library():
     lib.gm_candidate_sets.argtypes = [p, i32, p, ctypes.POINTER(u64), ctypes.POINTER(i32)]
     lib.gm_last_error.argtypes = [p]
     lib.gm_last_error.restype = ctypes.c_char_p
-    for name in ("gm_create", "gm_load_graph", "gm_load_query", "gm_set_order", "gm_get_order", "gm_count",
+    for name in ("gm_create", "gm_load_graph", "gm_load_graph_device", "gm_load_query", "gm_set_order", "gm_get_order", "gm_count",
                  "gm_enumerate", "gm_count_batch", "gm_tune_batch", "gm_get_options", "gm_serve_open",
                  "gm_serve_submit", "gm_serve_poll", "gm_serve_stats", "gm_serve_close", "gm_order_features",
                  "gm_candidate_orders", "gm_model_create", "gm_model_predict", "gm_model_train",
@@ -262,7 +270,8 @@ class Engine:
                  steal_threshold: int = 0, waves_per_cu: int = 0, skip_symmetry_check: bool = False,
                  stack_layout: int = 0, disable_label_index: bool = False, batch_single_launch: bool = False,
                  batch_streams: int = 0, pool_hub_cut: int = 0, disable_hub_bitmaps: bool = False,
-                 hub_bitmap_mib: int = 0, candidate_graph: bool = False, pool_roots_per_item: int = 0):
+                 hub_bitmap_mib: int = 0, candidate_graph: bool = False, pool_roots_per_item: int = 0,
+                 merge_ratio: int = 0):
         self._lib = load_library()
         opt = Options()
         opt.tau = tau
@@ -280,6 +289,7 @@ class Engine:
         opt.hub_bitmap_mib = hub_bitmap_mib
         opt.candidate_graph = int(candidate_graph)
         opt.pool_roots_per_item = pool_roots_per_item
+        opt.merge_ratio = merge_ratio
         h = ctypes.c_void_p()
         st = self._lib.gm_create(device, ctypes.byref(opt), ctypes.byref(h))
         if st != GM_OK:
@@ -316,6 +326,15 @@ class Engine:
         self._check(self._lib.gm_load_graph(self._h, rp.shape[0] - 1, _ptr(rp), _ptr(cl), _ptr(lb)))
         self._n = rp.shape[0] - 1
 
+    def load_graph_device(self, n: int, row_ptr_ptr: int, row_ptr_bytes: int, col_ptr: int, labels_ptr: int,
+                          stream: int = 0) -> None:
+        """Load G from device buffers given by address (e.g. tensor.data_ptr()); the
+        engine keeps using col in place, so the caller keeps it alive (gm_load_graph_device)."""
+        self._check(self._lib.gm_load_graph_device(self._h, int(n), ctypes.c_void_p(row_ptr_ptr), int(row_ptr_bytes),
+                                                   ctypes.c_void_p(col_ptr), ctypes.c_void_p(labels_ptr),
+                                                   ctypes.c_void_p(stream)))
+        self._n = int(n)
+
     def load_query(self, k: int, edges, labels) -> int:
         e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
         lb = np.ascontiguousarray(labels, dtype=np.int32)
@@ -340,7 +359,7 @@ class Engine:
                       int(r.steals), int(r.rows), float(r.kernel_ms), int(r.grid_waves), int(r.kernel_tasks),
                       int(r.kernel_probes), int(r.kernel_groups), int(r.scanned), int(r.kernel_scanned),
                       int(r.kernel_lookups), matches, int(r.candidate_rounds), float(r.candidate_ms),
-                      int(r.candidate_edges))
+                      int(r.candidate_edges), int(r.kernel_bytes), int(r.kernel_bytes_late))
 
     def count(self, qid: int, cap: int = 0, time_limit_s: float = 0.0) -> Result:
         r = _CResult()

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgmatch.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "candidate.hip", "order_model.hip", "engine.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "graph_build.hip", "candidate.hip", "order_model.hip",
+                                                     "engine.cpp")]
 
 # Packed fp32 ops are switched off: some of their forms have misbehaved on this
 # hardware class, and nothing here needs them.

@@ -233,6 +233,7 @@ struct gm_engine {
     uint64_t nnz = 0;
     VInfo *d_vinfo = nullptr;
     int32_t *d_col = nullptr;
+    bool col_owned = true;         // false: the caller's device buffer (gm_load_graph_device)
     int32_t *d_lcol = nullptr;     // lists ordered by (label, id); aliases d_col when not partitioned
     uint32_t *d_loff = nullptr;    // label slice bounds
     int32_t loff_stride = 1;
@@ -408,7 +409,8 @@ gm_status ensure_query_slots(gm_engine *e, LaunchCtx &c, size_t nq) {
 void free_graph(gm_engine *e) {
     if (e->d_vinfo) (void)hipFree(e->d_vinfo);
     if (e->d_lcol && e->d_lcol != e->d_col) (void)hipFree(e->d_lcol);
-    if (e->d_col) (void)hipFree(e->d_col);
+    if (e->d_col && e->col_owned) (void)hipFree(e->d_col);
+    e->col_owned = true;
     if (e->d_loff) (void)hipFree(e->d_loff);
     if (e->d_bylabel) (void)hipFree(e->d_bylabel);
     if (e->d_hub_id) (void)hipFree(e->d_hub_id);
@@ -479,6 +481,231 @@ gm_status check_graph(gm_engine *e, int32_t n, const int64_t *row_ptr, const int
         });
         if (bad == 3) return e->fail(GM_ERR_GRAPH, "graph is not symmetric (an edge is stored in one direction only)");
     }
+    return GM_OK;
+}
+
+// Host-side description of a graph being loaded: sizes, degrees, compact label
+// ids and the map from G's label values to them.
+struct HostGraph {
+    int32_t n = 0;
+    uint64_t nnz = 0;
+    std::vector<uint32_t> deg;   // [n]
+    std::vector<uint8_t> clab;   // [n]
+    int32_t labels_used = 0;
+    std::unordered_map<int32_t, int32_t> ids;
+};
+
+// G's label values -> compact ids 0 .. labels_used - 1 in ascending value order.
+gm_status compact_labels(gm_engine *e, const int32_t *labels, int32_t n, HostGraph &hg) {
+    hg.clab.resize(static_cast<size_t>(n));
+    if (n == 0) return GM_OK;
+    int32_t lo = labels[0], hi = labels[0];
+    for (int32_t v = 1; v < n; ++v) {
+        lo = std::min(lo, labels[v]);
+        hi = std::max(hi, labels[v]);
+    }
+    std::vector<int32_t> values;
+    if (static_cast<int64_t>(hi) - lo < (int64_t(1) << 20)) {
+        std::vector<int32_t> id(static_cast<size_t>(static_cast<int64_t>(hi) - lo + 1), -1);
+        for (int32_t v = 0; v < n; ++v) id[labels[v] - lo] = 0;
+        int32_t used = 0;
+        for (size_t i = 0; i < id.size(); ++i)
+            if (id[i] == 0) {
+                if (used >= 255) return e->fail(GM_ERR_GRAPH, "more than 255 distinct vertex labels");
+                id[i] = used++;
+                hg.ids.emplace(static_cast<int32_t>(lo + static_cast<int64_t>(i)), id[i]);
+            }
+        parallel_ranges(n, [&](int64_t b, int64_t en) {
+            for (int64_t v = b; v < en; ++v) hg.clab[v] = static_cast<uint8_t>(id[labels[v] - lo]);
+        });
+        hg.labels_used = used;
+        return GM_OK;
+    }
+    std::unordered_map<int32_t, int32_t> seen;
+    for (int32_t v = 0; v < n; ++v) {
+        if (seen.emplace(labels[v], 0).second && seen.size() > 255)
+            return e->fail(GM_ERR_GRAPH, "more than 255 distinct vertex labels");
+    }
+    for (auto &kv : seen) values.push_back(kv.first);
+    std::sort(values.begin(), values.end());
+    for (size_t i = 0; i < values.size(); ++i) hg.ids[values[i]] = static_cast<int32_t>(i);
+    for (int32_t v = 0; v < n; ++v) hg.clab[v] = static_cast<uint8_t>(hg.ids[labels[v]]);
+    hg.labels_used = static_cast<int32_t>(values.size());
+    return GM_OK;
+}
+
+// Label-partitioned lists need (labels + 1) bounds per vertex; they are skipped
+// when asked, when there is one label, or when the table would exceed 8 GiB.
+int32_t slice_stride(const gm_engine *e, int32_t n, int32_t labels_used) {
+    const int32_t stride = labels_used + 1;
+    if (e->opt.disable_label_index || labels_used <= 1 ||
+        static_cast<uint64_t>(n) * static_cast<uint64_t>(stride) * 4ull > (8ull << 30))
+        return 1;
+    return stride;
+}
+
+// Vertices grouped by label, highest degree first within a label, ties by id
+// (two stable counting sorts), and all vertices by degree (highest first).
+void order_vertices(const HostGraph &hg, std::vector<int64_t> &lab_start, std::vector<int32_t> &bylabel,
+                    std::vector<uint32_t> &bylabel_deg, std::vector<int32_t> &by_degree) {
+    const int32_t n = hg.n;
+    uint32_t maxd = 0;
+    for (int32_t v = 0; v < n; ++v) maxd = std::max(maxd, hg.deg[v]);
+    std::vector<int64_t> at(static_cast<size_t>(maxd) + 2, 0);
+    for (int32_t v = 0; v < n; ++v) ++at[maxd - hg.deg[v] + 1];  // bucket 0 = the largest degree
+    for (size_t i = 1; i < at.size(); ++i) at[i] += at[i - 1];
+    by_degree.assign(static_cast<size_t>(n), 0);
+    for (int32_t v = 0; v < n; ++v) by_degree[at[maxd - hg.deg[v]]++] = v;
+    lab_start.assign(static_cast<size_t>(hg.labels_used) + 1, 0);
+    for (int32_t v = 0; v < n; ++v) ++lab_start[hg.clab[v] + 1];
+    for (int32_t c = 0; c < hg.labels_used; ++c) lab_start[c + 1] += lab_start[c];
+    std::vector<int64_t> fill(lab_start.begin(), lab_start.end() - 1);
+    bylabel.assign(static_cast<size_t>(n), 0);
+    bylabel_deg.assign(static_cast<size_t>(n), 0);
+    for (int32_t v : by_degree) {
+        const int64_t pos = fill[hg.clab[v]]++;
+        bylabel[pos] = v;
+        bylabel_deg[pos] = hg.deg[v];
+    }
+}
+
+gm_status install_host_only(gm_engine *e, HostGraph &hg) {
+    std::vector<int64_t> lab_start;
+    std::vector<int32_t> bylabel, by_degree;
+    std::vector<uint32_t> bylabel_deg;
+    order_vertices(hg, lab_start, bylabel, bylabel_deg, by_degree);
+    free_graph(e);
+    e->loff_stride = slice_stride(e, hg.n, hg.labels_used);
+    e->label_id = std::move(hg.ids);
+    e->lab_start = std::move(lab_start);
+    e->bylabel_deg = std::move(bylabel_deg);
+    e->n = hg.n;
+    e->nnz = hg.nnz;
+    e->has_graph = true;
+    return GM_OK;
+}
+
+// Is p device memory of the engine's device?
+bool device_buffer(const gm_engine *e, const void *p) {
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice && at.device == e->device;
+}
+
+// Checks the graph on the device and builds every derived structure there:
+// vertex records, label slices, the vertex order by label and degree, hub
+// bitmaps.  d_row_ptr, d_col and d_clab are device arrays; d_col becomes the
+// engine's adjacency array (freed with the graph when col_owned, and freed here
+// on failure).  On success the previous graph is released and replaced.
+gm_status install_device(gm_engine *e, HostGraph &hg, const void *d_row_ptr, int rp_bytes, int32_t *d_col,
+                         bool col_owned, const uint8_t *d_clab, hipStream_t s) {
+    const int32_t n = hg.n;
+    VInfo *vinfo = nullptr;
+    uint32_t *loff = nullptr;
+    int32_t *lcol = nullptr, *bylabel_d = nullptr, *hub_id = nullptr, *hub_list = nullptr;
+    uint32_t *hub_bits = nullptr;
+    unsigned int *d_err = nullptr;
+    auto release = [&](bool all) {
+        if (d_err) (void)hipFree(d_err);
+        if (hub_list) (void)hipFree(hub_list);
+        d_err = nullptr;
+        hub_list = nullptr;
+        if (!all) return;
+        for (void *p : {static_cast<void *>(vinfo), static_cast<void *>(loff), static_cast<void *>(lcol),
+                        static_cast<void *>(bylabel_d), static_cast<void *>(hub_id), static_cast<void *>(hub_bits)})
+            if (p) (void)hipFree(p);
+        if (col_owned && d_col) (void)hipFree(d_col);
+    };
+    auto device_error = [&](hipError_t h, const char *what) {
+        (void)hipStreamSynchronize(s);
+        release(true);
+        return e->fail(h == hipErrorOutOfMemory ? GM_ERR_NOMEM : GM_ERR_DEVICE,
+                       std::string("graph load, ") + what + ": " + hipGetErrorString(h));
+    };
+    // 1. checks: offsets first (they bound every row the second pass reads)
+    hipError_t h = hipMalloc(reinterpret_cast<void **>(&d_err), sizeof(unsigned int));
+    unsigned int err = 0;
+    for (int pass = 0; pass < 2 && h == hipSuccess && err == 0; ++pass) {
+        h = hipMemsetAsync(d_err, 0, sizeof(unsigned int), s);
+        if (h == hipSuccess)
+            h = gm::launch_graph_check(d_row_ptr, rp_bytes, d_col, n, e->opt.skip_symmetry_check == 0, d_err, pass == 1,
+                                       e->num_cu, s);
+        if (h == hipSuccess) h = hipMemcpyAsync(&err, d_err, sizeof(err), hipMemcpyDeviceToHost, s);
+        if (h == hipSuccess) h = hipStreamSynchronize(s);
+    }
+    if (h != hipSuccess) return device_error(h, "check");
+    if (err) {
+        release(true);
+        if (err & gm::kGraphBadRowPtr) return e->fail(GM_ERR_GRAPH, "row_ptr must start at 0 and be non-decreasing");
+        if (err & gm::kGraphBadDegree) return e->fail(GM_ERR_GRAPH, "a vertex degree exceeds 2^24 - 1");
+        if (err & gm::kGraphBadEntry)
+            return e->fail(GM_ERR_GRAPH, "adjacency rows must be strictly ascending ids in [0, n) without self-loops");
+        return e->fail(GM_ERR_GRAPH, "graph is not symmetric (an edge is stored in one direction only)");
+    }
+    // 2. vertex records and label slices
+    const int32_t stride = slice_stride(e, n, hg.labels_used);
+    const size_t loff_len = stride > 1 ? static_cast<size_t>(n) * stride : static_cast<size_t>(n) + 1;
+    h = hipMalloc(reinterpret_cast<void **>(&vinfo), std::max<size_t>(n, 1) * sizeof(VInfo));
+    if (h == hipSuccess) h = hipMalloc(reinterpret_cast<void **>(&loff), std::max<size_t>(loff_len, 1) * sizeof(uint32_t));
+    if (h == hipSuccess && stride > 1)
+        h = hipMalloc(reinterpret_cast<void **>(&lcol), std::max<uint64_t>(hg.nnz, 1) * sizeof(int32_t));
+    if (h == hipSuccess) h = hipMalloc(reinterpret_cast<void **>(&bylabel_d), std::max<size_t>(n, 1) * sizeof(int32_t));
+    if (h == hipSuccess)
+        h = gm::launch_graph_build(d_row_ptr, rp_bytes, d_col, d_clab, n, stride, vinfo, loff, stride > 1 ? lcol : nullptr,
+                                   e->num_cu, s);
+    if (h != hipSuccess) return device_error(h, "vertex records and label slices");
+    // 3. vertices by label and degree (host), hubs: the highest degrees
+    std::vector<int64_t> lab_start;
+    std::vector<int32_t> bylabel, by_degree;
+    std::vector<uint32_t> bylabel_deg;
+    order_vertices(hg, lab_start, bylabel, bylabel_deg, by_degree);
+    if (n) h = hipMemcpyAsync(bylabel_d, bylabel.data(), static_cast<size_t>(n) * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (h != hipSuccess) return device_error(h, "vertex order");
+    const uint64_t words = (static_cast<uint64_t>(n) + 31) / 32;
+    int32_t hubs = 0;
+    if (!e->opt.disable_hub_bitmaps && n > 0) {
+        int64_t big = 0;
+        while (big < n && hg.deg[by_degree[big]] >= kHubMinDegree) ++big;
+        const uint64_t mib = e->opt.hub_bitmap_mib > 0 ? e->opt.hub_bitmap_mib : kHubDefaultMiB;
+        const uint64_t fit = (mib << 20) / (words * 4);
+        hubs = static_cast<int32_t>(std::min<uint64_t>({static_cast<uint64_t>(big), static_cast<uint64_t>(kMaxHubs), fit}));
+    }
+    if (hubs > 0) {
+        h = hipMalloc(reinterpret_cast<void **>(&hub_id), static_cast<size_t>(n) * sizeof(int32_t));
+        if (h == hipSuccess) h = hipMalloc(reinterpret_cast<void **>(&hub_bits), static_cast<size_t>(hubs) * words * sizeof(uint32_t));
+        if (h == hipSuccess) h = hipMalloc(reinterpret_cast<void **>(&hub_list), static_cast<size_t>(hubs) * sizeof(int32_t));
+        if (h == hipSuccess) h = hipMemsetAsync(hub_id, 0xff, static_cast<size_t>(n) * sizeof(int32_t), s);
+        if (h == hipSuccess) h = hipMemsetAsync(hub_bits, 0, static_cast<size_t>(hubs) * words * sizeof(uint32_t), s);
+        if (h == hipSuccess)
+            h = hipMemcpyAsync(hub_list, by_degree.data(), static_cast<size_t>(hubs) * sizeof(int32_t), hipMemcpyHostToDevice, s);
+        if (h == hipSuccess) h = gm::launch_hub_bitmaps(vinfo, d_col, hub_list, hubs, hub_bits, words, hub_id, e->num_cu, s);
+        if (h != hipSuccess) return device_error(h, "hub bitmaps");
+    }
+    h = hipStreamSynchronize(s);
+    if (h == hipSuccess) h = hipGetLastError();
+    if (h != hipSuccess) return device_error(h, "build");
+    release(false);
+    free_graph(e);
+    e->d_vinfo = vinfo;
+    e->d_col = d_col;
+    e->col_owned = col_owned;
+    e->d_loff = loff;
+    e->d_lcol = stride > 1 ? lcol : d_col;
+    e->loff_stride = stride;
+    e->d_bylabel = bylabel_d;
+    e->d_hub_id = hub_id;
+    e->d_hub_bits = hub_bits;
+    e->hub_words = hubs > 0 ? words : 0;
+    e->hubs = hubs;
+    e->label_id = std::move(hg.ids);
+    e->lab_start = std::move(lab_start);
+    e->bylabel_deg = std::move(bylabel_deg);
+    e->n = n;
+    e->nnz = hg.nnz;
+    e->has_graph = true;
     return GM_OK;
 }
 
@@ -930,6 +1157,8 @@ gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, ui
     out->scanned = k0.scanned + l1.scanned;
     out->kernel_scanned = k0.scanned + l1.scanned;  // the search launch reads the level-1 candidates itself
     out->kernel_lookups = k0.lookups;
+    out->kernel_bytes = k0.bytes;
+    out->kernel_bytes_late = k0.bytes_late;
     if (enumerate) {
         const uint64_t nrows = std::min<uint64_t>(out->count, std::min<uint64_t>(c.out_rows, cap));
         if (nrows) {
@@ -1130,6 +1359,8 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
     out->scanned = qc.scanned;
     out->kernel_scanned = qc.scanned - before.scanned;
     out->kernel_lookups = qc.lookups - before.lookups;
+    out->kernel_bytes = qc.bytes - before.bytes;
+    out->kernel_bytes_late = qc.bytes_late - before.bytes_late;
     if (enumerate) {
         const uint64_t nrows = std::min<uint64_t>(out->count, std::min<uint64_t>(c.out_rows, cap));
         if (nrows) {
@@ -1262,9 +1493,15 @@ gm_status harvest_group(gm_engine *e, LaunchCtx &c, const GroupLaunch &gl, gm_re
             r.steals = qc.steals;
             r.scanned = r.kernel_scanned = qc.scanned;
             r.kernel_lookups = qc.lookups;
+            r.kernel_bytes = qc.bytes;
+            r.kernel_bytes_late = qc.bytes_late;
             r.kernel_ms = kernel_ms;
             r.grid_waves = gl.grid_waves;
-            if (sum) sum->lookups += qc.lookups;
+            if (sum) {
+                sum->lookups += qc.lookups;
+                sum->bytes += qc.bytes;
+                sum->bytes_late += qc.bytes_late;
+            }
         }
     }
     return GM_OK;
@@ -1674,7 +1911,7 @@ gm_status gm_create(int32_t device, const gm_options *opt, gm_engine **out) {
     if (o.stack_layout < 0 || o.stack_layout > 2 || o.steal_threshold < 0 || o.waves_per_cu < 0 ||
         o.pool_row_limit < 0 || o.batch_single_launch < 0 || o.batch_single_launch > 1 || o.batch_streams < 0 ||
         o.pool_hub_cut < 0 || o.hub_bitmap_mib < 0 || o.candidate_graph < 0 || o.candidate_graph > 1 ||
-        o.pool_roots_per_item < 0 || o.pool_roots_per_item > 64) {
+        o.pool_roots_per_item < 0 || o.pool_roots_per_item > 64 || o.merge_ratio < -1 || o.merge_ratio > 8) {
         g_create_error = "option out of range";
         return GM_ERR_ARG;
     }
@@ -1739,148 +1976,135 @@ gm_status gm_load_graph(gm_engine *e, int32_t n, const int64_t *row_ptr, const i
     if (n < 0) return e->fail(GM_ERR_ARG, "n must be >= 0");
     if (!row_ptr || (n > 0 && !labels)) return e->fail(GM_ERR_ARG, "row_ptr and labels must not be null");
     if (e->servers.load() > 0) return e->fail(GM_ERR_STATE, "a server is open on this engine");
-    gm_status st = check_graph(e, n, row_ptr, col, e->opt.skip_symmetry_check == 0);
+    if (row_ptr[0] != 0) return e->fail(GM_ERR_GRAPH, "row_ptr[0] must be 0");
+    const int64_t nnz64 = row_ptr[n];
+    if (nnz64 < 0 || nnz64 >= (int64_t(1) << 32))
+        return e->fail(GM_ERR_GRAPH, "row_ptr[n] must lie in [0, 2^32): at most 2^32 - 1 adjacency entries");
+    if (nnz64 > 0 && !col) return e->fail(GM_ERR_ARG, "col is null");
+    if (e->device < 0) {
+        // host-only engine: the whole check on the host, then the planning tables
+        gm_status st = check_graph(e, n, row_ptr, col, e->opt.skip_symmetry_check == 0);
+        if (st) return st;
+    } else {
+        // the offsets must be sane before they size anything; the rows are checked on the device
+        std::atomic<int> bad{0};
+        parallel_ranges(n, [&](int64_t b, int64_t en) {
+            for (int64_t v = b; v < en; ++v)
+                if (row_ptr[v + 1] < row_ptr[v] || row_ptr[v + 1] - row_ptr[v] >= (int64_t(1) << 24)) bad = 1;
+        });
+        if (bad) return e->fail(GM_ERR_GRAPH, "row_ptr must be non-decreasing with every degree below 2^24");
+    }
+    HostGraph hg;
+    hg.n = n;
+    hg.nnz = static_cast<uint64_t>(nnz64);
+    gm_status st = compact_labels(e, labels, n, hg);
     if (st) return st;
-    std::unordered_map<int32_t, int32_t> ids;
-    std::vector<VInfo> vinfo(static_cast<size_t>(n));
-    for (int32_t v = 0; v < n; ++v) {
-        auto it = ids.find(labels[v]);
-        int32_t id;
-        if (it == ids.end()) {
-            id = static_cast<int32_t>(ids.size());
-            if (id >= 255) return e->fail(GM_ERR_GRAPH, "more than 255 distinct vertex labels");
-            ids.emplace(labels[v], id);
-        } else {
-            id = it->second;
-        }
-        const uint64_t deg = static_cast<uint64_t>(row_ptr[v + 1] - row_ptr[v]);
-        vinfo[v].x = static_cast<uint32_t>(row_ptr[v]);
-        vinfo[v].y = static_cast<uint32_t>(deg << 8) | static_cast<uint32_t>(id);
+    hg.deg.resize(static_cast<size_t>(n));
+    parallel_ranges(n, [&](int64_t b, int64_t en) {
+        for (int64_t v = b; v < en; ++v) hg.deg[v] = static_cast<uint32_t>(row_ptr[v + 1] - row_ptr[v]);
+    });
+    if (e->device < 0) return install_host_only(e, hg);
+    HIP_TRY(e, hipSetDevice(e->device));
+    hipStream_t s = e->lc.stream;
+    int64_t *d_rp = nullptr;
+    int32_t *d_col = nullptr;
+    uint8_t *d_clab = nullptr;
+    auto release = [&]() {
+        if (d_rp) (void)hipFree(d_rp);
+        if (d_clab) (void)hipFree(d_clab);
+    };
+    hipError_t h = hipMalloc(reinterpret_cast<void **>(&d_rp), (static_cast<size_t>(n) + 1) * sizeof(int64_t));
+    if (h == hipSuccess) h = hipMalloc(reinterpret_cast<void **>(&d_col), std::max<uint64_t>(hg.nnz, 1) * sizeof(int32_t));
+    if (h == hipSuccess) h = hipMalloc(reinterpret_cast<void **>(&d_clab), std::max<size_t>(n, 1));
+    if (h == hipSuccess) h = hipMemcpyAsync(d_rp, row_ptr, (static_cast<size_t>(n) + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    if (h == hipSuccess && hg.nnz) h = hipMemcpyAsync(d_col, col, hg.nnz * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (h == hipSuccess && n) h = hipMemcpyAsync(d_clab, hg.clab.data(), static_cast<size_t>(n), hipMemcpyHostToDevice, s);
+    if (h != hipSuccess) {
+        release();
+        if (d_col) (void)hipFree(d_col);
+        return e->fail(h == hipErrorOutOfMemory ? GM_ERR_NOMEM : GM_ERR_DEVICE,
+                       std::string("graph upload: ") + hipGetErrorString(h));
     }
-    const uint64_t nnz = static_cast<uint64_t>(row_ptr[n]);
-    // Label-partitioned copy of the lists: N(v) ordered by (label, id), with the
-    // bounds of every label slice, so a task group scans only candidates that
-    // carry its query vertex's label.  Skipped when asked, when there is one
-    // label, or when the bounds table would exceed 8 GiB.
-    const int32_t labels_used = static_cast<int32_t>(ids.size());
-    int32_t stride = labels_used + 1;
-    if (e->opt.disable_label_index || labels_used <= 1 ||
-        static_cast<uint64_t>(n) * static_cast<uint64_t>(stride) * 4ull > (8ull << 30))
-        stride = 1;
-    std::vector<uint32_t> loff;
-    std::vector<int32_t> lcol;
-    if (stride == 1) {
-        loff.resize(static_cast<size_t>(n) + 1);
-        for (int32_t v = 0; v <= n; ++v) loff[v] = static_cast<uint32_t>(row_ptr[v]);
+    st = install_device(e, hg, d_rp, 8, d_col, true, d_clab, s);  // takes d_col
+    (void)hipStreamSynchronize(s);
+    release();
+    return st;
+}
+
+gm_status gm_load_graph_device(gm_engine *e, int32_t n, const void *row_ptr, int32_t row_ptr_bytes,
+                               const int32_t *col, const uint8_t *labels, void *hip_stream) {
+    if (!e) return GM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (e->device < 0) return e->fail(GM_ERR_DEVICE, "a host-only engine cannot load device buffers");
+    if (n < 0) return e->fail(GM_ERR_ARG, "n must be >= 0");
+    if (row_ptr_bytes != 4 && row_ptr_bytes != 8) return e->fail(GM_ERR_ARG, "row_ptr_bytes must be 4 or 8");
+    if (!row_ptr || (n > 0 && !labels)) return e->fail(GM_ERR_ARG, "row_ptr and labels must not be null");
+    if (e->servers.load() > 0) return e->fail(GM_ERR_STATE, "a server is open on this engine");
+    HIP_TRY(e, hipSetDevice(e->device));
+    if (!device_buffer(e, row_ptr) || (n > 0 && !device_buffer(e, labels)))
+        return e->fail(GM_ERR_ARG, "row_ptr and labels must be device memory of the engine's device");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    // the offsets come to the host: they give the degrees and the size of col
+    std::vector<int64_t> rp(static_cast<size_t>(n) + 1);
+    if (row_ptr_bytes == 8) {
+        HIP_TRY(e, hipMemcpyAsync(rp.data(), row_ptr, rp.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(e, hipStreamSynchronize(s));
     } else {
-        loff.resize(static_cast<size_t>(n) * stride);
-        lcol.resize(nnz);
-        parallel_ranges(n, [&](int64_t b, int64_t end) {
-            std::vector<uint32_t> cnt(stride);
-            for (int64_t v = b; v < end; ++v) {
-                std::fill(cnt.begin(), cnt.end(), 0u);
-                for (int64_t p = row_ptr[v]; p < row_ptr[v + 1]; ++p) ++cnt[(vinfo[col[p]].y & 0xffu) + 1];
-                uint32_t *o = &loff[static_cast<size_t>(v) * stride];
-                o[0] = static_cast<uint32_t>(row_ptr[v]);
-                for (int32_t c = 1; c < stride; ++c) o[c] = o[c - 1] + cnt[c];
-                for (int32_t c = 0; c + 1 < stride; ++c) cnt[c] = o[c];  // fill cursors
-                for (int64_t p = row_ptr[v]; p < row_ptr[v + 1]; ++p) lcol[cnt[vinfo[col[p]].y & 0xffu]++] = col[p];
-            }
-        });
+        std::vector<int32_t> rp32(rp.size());
+        HIP_TRY(e, hipMemcpyAsync(rp32.data(), row_ptr, rp32.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(e, hipStreamSynchronize(s));
+        for (size_t i = 0; i < rp.size(); ++i) rp[i] = rp32[i];
     }
-    // Vertices by label, highest degree first within a label (ties by id): the
-    // first query vertex's candidates are a prefix of its label's bucket, and
-    // hub roots, the heaviest work, are claimed first.
-    std::vector<int64_t> lab_start(static_cast<size_t>(labels_used) + 1, 0);
-    for (int32_t v = 0; v < n; ++v) ++lab_start[(vinfo[v].y & 0xffu) + 1];
-    for (int32_t c = 0; c < labels_used; ++c) lab_start[c + 1] += lab_start[c];
-    std::vector<int32_t> bylabel(static_cast<size_t>(n));
-    {
-        std::vector<int64_t> fill(lab_start.begin(), lab_start.end() - 1);
-        for (int32_t v = 0; v < n; ++v) bylabel[fill[vinfo[v].y & 0xffu]++] = v;
-    }
-    for (int32_t c = 0; c < labels_used; ++c)
-        std::sort(bylabel.begin() + lab_start[c], bylabel.begin() + lab_start[c + 1], [&](int32_t x, int32_t y) {
-            const uint32_t dx = vinfo[x].y >> 8, dy = vinfo[y].y >> 8;
-            return dx != dy ? dx > dy : x < y;
-        });
-    std::vector<uint32_t> bylabel_deg(static_cast<size_t>(n));
-    for (int32_t i = 0; i < n; ++i) bylabel_deg[i] = vinfo[bylabel[i]].y >> 8;
-    // Adjacency bitmaps of the highest-degree vertices (at least kHubMinDegree
-    // neighbours; at most kMaxHubs, within the option's MiB): a membership test in a hub's
-    // long list becomes one bit read instead of a bisection.
-    std::vector<int32_t> hub_id;
-    std::vector<uint32_t> hub_bits;
-    const uint64_t words = (static_cast<uint64_t>(n) + 31) / 32;
-    int32_t hubs = 0;
-    if (e->device >= 0 && !e->opt.disable_hub_bitmaps && n > 0) {
-        std::vector<int32_t> big;
-        for (int32_t v = 0; v < n; ++v)
-            if (row_ptr[v + 1] - row_ptr[v] >= kHubMinDegree) big.push_back(v);
-        std::sort(big.begin(), big.end(), [&](int32_t x, int32_t y) {
-            const int64_t dx = row_ptr[x + 1] - row_ptr[x], dy = row_ptr[y + 1] - row_ptr[y];
-            return dx != dy ? dx > dy : x < y;
-        });
-        const uint64_t mib = e->opt.hub_bitmap_mib > 0 ? e->opt.hub_bitmap_mib : kHubDefaultMiB;
-        const uint64_t fit = (mib << 20) / (words * 4);
-        hubs = static_cast<int32_t>(std::min<uint64_t>({big.size(), static_cast<uint64_t>(kMaxHubs), fit}));
-        if (hubs > 0) {
-            hub_id.assign(static_cast<size_t>(n), -1);
-            hub_bits.assign(static_cast<size_t>(hubs) * words, 0u);
-            for (int32_t h = 0; h < hubs; ++h) hub_id[big[h]] = h;
-            parallel_ranges(hubs, [&](int64_t b, int64_t en) {
-                for (int64_t h = b; h < en; ++h) {
-                    const int32_t v = big[h];
-                    uint32_t *bits = &hub_bits[static_cast<size_t>(h) * words];
-                    for (int64_t p = row_ptr[v]; p < row_ptr[v + 1]; ++p) bits[col[p] >> 5] |= 1u << (col[p] & 31);
-                }
-            });
+    if (rp[0] != 0) return e->fail(GM_ERR_GRAPH, "row_ptr[0] must be 0");
+    for (int32_t v = 0; v < n; ++v)
+        if (rp[v + 1] < rp[v] || rp[v + 1] - rp[v] >= (int64_t(1) << 24))
+            return e->fail(GM_ERR_GRAPH, "row_ptr must be non-decreasing with every degree below 2^24");
+    if (rp[n] >= (int64_t(1) << 32)) return e->fail(GM_ERR_GRAPH, "at most 2^32 - 1 adjacency entries");
+    HostGraph hg;
+    hg.n = n;
+    hg.nnz = static_cast<uint64_t>(rp[n]);
+    if (hg.nnz > 0 && (!col || !device_buffer(e, col)))
+        return e->fail(GM_ERR_ARG, "col must be device memory of the engine's device");
+    hg.deg.resize(static_cast<size_t>(n));
+    for (int32_t v = 0; v < n; ++v) hg.deg[v] = static_cast<uint32_t>(rp[v + 1] - rp[v]);
+    // labels: a histogram on the device gives the values present; compact ids in value order
+    unsigned int *d_hist = nullptr;
+    uint8_t *d_clab = nullptr;
+    auto release = [&]() {
+        if (d_hist) (void)hipFree(d_hist);
+        if (d_clab) (void)hipFree(d_clab);
+    };
+    hipError_t h = hipMalloc(reinterpret_cast<void **>(&d_hist), 256 * sizeof(unsigned int));
+    if (h == hipSuccess) h = hipMalloc(reinterpret_cast<void **>(&d_clab), std::max<size_t>(n, 1));
+    if (h == hipSuccess) h = hipMemsetAsync(d_hist, 0, 256 * sizeof(unsigned int), s);
+    if (h == hipSuccess) h = gm::launch_label_hist(labels, n, d_hist, e->num_cu, s);
+    unsigned int hist[256] = {};
+    if (h == hipSuccess) h = hipMemcpyAsync(hist, d_hist, sizeof(hist), hipMemcpyDeviceToHost, s);
+    if (h == hipSuccess) h = hipStreamSynchronize(s);
+    uint8_t map[256] = {};
+    int32_t used = 0;
+    for (int32_t c = 0; c < 256 && h == hipSuccess; ++c) {
+        if (!hist[c]) continue;
+        if (used >= 255) {
+            release();
+            return e->fail(GM_ERR_GRAPH, "more than 255 distinct vertex labels");
         }
+        map[c] = static_cast<uint8_t>(used);
+        hg.ids.emplace(c, used++);
     }
-    if (e->device >= 0) {
-        HIP_TRY(e, hipSetDevice(e->device));
-        free_graph(e);
-        hipError_t h = hipMalloc(reinterpret_cast<void **>(&e->d_vinfo), std::max<size_t>(n, 1) * sizeof(VInfo));
-        if (h == hipSuccess)
-            h = hipMalloc(reinterpret_cast<void **>(&e->d_col), std::max<uint64_t>(nnz, 1) * sizeof(int32_t));
-        if (h == hipSuccess)
-            h = hipMalloc(reinterpret_cast<void **>(&e->d_loff), std::max<size_t>(loff.size(), 1) * sizeof(uint32_t));
-        if (h == hipSuccess && stride > 1)
-            h = hipMalloc(reinterpret_cast<void **>(&e->d_lcol), std::max<uint64_t>(nnz, 1) * sizeof(int32_t));
-        if (h == hipSuccess)
-            h = hipMalloc(reinterpret_cast<void **>(&e->d_bylabel), std::max<size_t>(n, 1) * sizeof(int32_t));
-        if (h == hipSuccess && hubs > 0)
-            h = hipMalloc(reinterpret_cast<void **>(&e->d_hub_id), static_cast<size_t>(n) * sizeof(int32_t));
-        if (h == hipSuccess && hubs > 0)
-            h = hipMalloc(reinterpret_cast<void **>(&e->d_hub_bits), hub_bits.size() * sizeof(uint32_t));
-        if (h != hipSuccess) {
-            free_graph(e);
-            return e->fail(GM_ERR_NOMEM, std::string("graph upload: ") + hipGetErrorString(h));
-        }
-        if (stride == 1) e->d_lcol = e->d_col;
-        e->loff_stride = stride;
-        if (n) HIP_TRY(e, hipMemcpy(e->d_vinfo, vinfo.data(), static_cast<size_t>(n) * sizeof(VInfo), hipMemcpyHostToDevice));
-        if (nnz) HIP_TRY(e, hipMemcpy(e->d_col, col, nnz * sizeof(int32_t), hipMemcpyHostToDevice));
-        HIP_TRY(e, hipMemcpy(e->d_loff, loff.data(), loff.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
-        if (stride > 1 && nnz) HIP_TRY(e, hipMemcpy(e->d_lcol, lcol.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
-        if (n) HIP_TRY(e, hipMemcpy(e->d_bylabel, bylabel.data(), static_cast<size_t>(n) * sizeof(int32_t), hipMemcpyHostToDevice));
-        if (hubs > 0) {
-            HIP_TRY(e, hipMemcpy(e->d_hub_id, hub_id.data(), static_cast<size_t>(n) * sizeof(int32_t), hipMemcpyHostToDevice));
-            HIP_TRY(e, hipMemcpy(e->d_hub_bits, hub_bits.data(), hub_bits.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
-            e->hub_words = words;
-            e->hubs = hubs;
-        }
-    } else {
-        free_graph(e);
-        e->loff_stride = stride;
+    hg.labels_used = used;
+    hg.clab.resize(static_cast<size_t>(n));
+    if (h == hipSuccess) h = gm::launch_label_map(labels, n, map, d_clab, e->num_cu, s);
+    if (h == hipSuccess && n) h = hipMemcpyAsync(hg.clab.data(), d_clab, static_cast<size_t>(n), hipMemcpyDeviceToHost, s);
+    if (h == hipSuccess) h = hipStreamSynchronize(s);
+    if (h != hipSuccess) {
+        release();
+        return hip_fail(e, h, "label compaction");
     }
-    e->label_id = std::move(ids);
-    e->lab_start = std::move(lab_start);
-    e->bylabel_deg = std::move(bylabel_deg);
-    e->n = n;
-    e->nnz = nnz;
-    e->has_graph = true;
-    return GM_OK;
+    gm_status st = install_device(e, hg, row_ptr, row_ptr_bytes, const_cast<int32_t *>(col), false, d_clab, s);
+    (void)hipStreamSynchronize(s);
+    release();
+    return st;
 }
 
 gm_status gm_load_query(gm_engine *e, int32_t k, int32_t m, const int32_t *edges, const int32_t *labels,

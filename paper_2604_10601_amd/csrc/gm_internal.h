@@ -85,8 +85,14 @@ struct alignas(128) QCtl {
     unsigned long long lanes_active;
     unsigned long long lanes_issued;
     unsigned long long steals;
+    // bytes the search kernel requested from device memory (reads and writes)
+    // for this query; bytes_late: those of the last 32-round window of each
+    // wavefront in which it saw the query's (or the launch's) abort word, an
+    // upper bound on the work done after the cap or time limit was reached
+    unsigned long long bytes;
+    unsigned long long bytes_late;
     int live;                        // work units (items, donations) taken and not finished
-    int pad3[15];
+    int pad3[11];
 };
 
 static_assert(sizeof(QCtl) == 384 && offsetof(QCtl, abort) == 128 && offsetof(QCtl, groups) == 256,
@@ -257,5 +263,27 @@ hipError_t launch_level1(const int32_t *roots, int32_t R, unsigned long long per
 // Wavefronts a depth-first search launch for a query of `levels` positions keeps resident.
 int search_waves(int levels, int num_cu, int waves_per_cu, bool slim);
 hipError_t launch_steal_init(Mailbox *mail, unsigned long long *idle_bits, int32_t n, hipStream_t s);
+
+// Graph load (graph_build.hip).  Error bits of the checks:
+enum : unsigned int { kGraphBadRowPtr = 1, kGraphBadEntry = 2, kGraphBadDegree = 4, kGraphAsymmetric = 8 };
+// entries = false: row offsets (start at 0, non-decreasing, degrees < 2^24);
+// entries = true (only after the offsets passed): ids in [0, n), rows strictly
+// ascending, no self-loops, and symmetry if asked.  ORs error bits into *err.
+hipError_t launch_graph_check(const void *row_ptr, int row_ptr_bytes, const int32_t *col, int32_t n, bool symmetric,
+                              unsigned int *err, bool entries, int num_cu, hipStream_t s);
+// hist256[c] += number of vertices with label value c.
+hipError_t launch_label_hist(const uint8_t *labels, int32_t n, unsigned int *hist256, int num_cu, hipStream_t s);
+// clab[v] = map256[labels[v]] (compact label ids).
+hipError_t launch_label_map(const uint8_t *labels, int32_t n, const uint8_t *map256, uint8_t *clab, int num_cu,
+                            hipStream_t s);
+// Vertex records; with stride > 1 the label slices (loff [n * stride], lcol [nnz]),
+// else loff [n + 1] = the row offsets as 32-bit values (lcol unused).
+hipError_t launch_graph_build(const void *row_ptr, int row_ptr_bytes, const int32_t *col, const uint8_t *clab,
+                              int32_t n, int32_t stride, VInfo *vinfo, uint32_t *loff, int32_t *lcol, int num_cu,
+                              hipStream_t s);
+// Adjacency bitmaps of the hubs hubs[0 .. nh) (bits cleared beforehand) and
+// hub_id[hubs[h]] = h (hub_id set to -1 beforehand).
+hipError_t launch_hub_bitmaps(const VInfo *vinfo, const int32_t *col, const int32_t *hubs, int32_t nh, uint32_t *bits,
+                              unsigned long long words, int32_t *hub_id, int num_cu, hipStream_t s);
 
 }  // namespace gm

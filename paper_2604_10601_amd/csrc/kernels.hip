@@ -10,9 +10,13 @@
 //     task groups of all of them form one virtual task pool that two cursors
 //     (parent lane, offset in its list) walk 64 tasks at a time.  Partial
 //     matches are rebuilt by following parent pointers down the stack.
-//   * Initial pool (Sec. 4.3): partial matches are first expanded breadth-first
-//     until a level holds at least tau of them; wavefronts then claim pool rows
-//     with an atomic counter.
+//   * Initial pool (Sec. 4.3): wavefronts claim work items with an atomic
+//     counter.  By default the pool is two-phase: first-phase items hold 64
+//     candidates of the first query vertex, each with at most its first
+//     hub_cut tasks at position 1; second-phase items are 64 consecutive tasks
+//     of the rest of those position-1 lists, laid out by a prefix sum.  With
+//     tau > 0 the paper's own scheme runs instead: breadth-first expansion
+//     until a level holds at least tau partial matches, then rows of it.
 //
 // gfx950 design, which differs from the paper's 32-lane CUDA design:
 //   * 64-lane wavefronts: the stack is K x 64, ballots are 64-bit.
@@ -23,8 +27,10 @@
 //     its parent and offset.
 //   * A wavefront claims 64 pool rows at a time, one per lane, so the first
 //     level is already a full batch.
-//   * Each stack entry caches the start and length of its vertex's neighbour
-//     list, so GenerateTask and the membership tests read no vertex records.
+//   * Two stack layouts: the slim default keeps only each entry's vertex and
+//     parent lane, and membership tests bisect label slices of N(w) whose
+//     bounds cost one lookup; the full layout also caches each entry's list
+//     start and degree, so tests bisect the id-sorted lists with no lookup.
 //   * Per-vertex data is one packed 8-byte record (list start, degree, label):
 //     a single load decides the label and degree filters.
 //   * Membership is bisection while the remaining range is longer than a few
@@ -94,24 +100,24 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
     return x;
 }
 
-// Membership of v in up to kLists ascending lists col[lo[s], lo[s] + n[s]) at
-// once (n[s] == 0 marks an unused slot).  The lists are bisected in lockstep,
-// so one round trip serves every list: a candidate with several backward
-// neighbours waits for the longest search, not for the sum of them.  Each
-// range is narrowed until at most kTail entries remain, and those tails are
-// read with independent loads (indices clamped into the list).  Returns true
-// iff v is in every used list; adds the 4-byte reads made to probes.  One list
-// at a time: testing several in lockstep saves round trips on dense queries
-// but costs more instructions per candidate than those trips (same box, the
-// 8-vertex workload: 34.7, 37.1 and 38.5 G embeddings/s with four, two and
-// one; the 12-32-vertex sample: 14.6, 15.4 and 15.7).
+// Membership of v in the ascending lists col[lo[s], lo[s] + n[s]), s < kLists
+// (n[s] == 0 marks an unused slot).  kLists is 1: the caller tests one list
+// at a time.  (The code can bisect several lists in lockstep, one round trip
+// for all of them, but on this hardware that cost more instructions per
+// candidate than the round trips it saved: same box, the 8-vertex workload ran
+// at 34.7, 37.1 and 38.5 G embeddings/s with four, two and one lists, the
+// 12-32-vertex sample at 14.6, 15.4 and 15.7.)  A range is bisected until at
+// most kTail entries remain, and the tail is read with kTail independent loads
+// (indices clamped into the list).  Returns true iff v is in every used list;
+// adds the list entries examined to probes and the bytes of the loads issued
+// to bytes.
 constexpr int kLists = 1;
 // Tail of 8 entries (one or two 64-byte sectors): against 4, +1 % on the
 // 8-vertex workload and +3 % on the 12-32-vertex sample.
 constexpr uint32_t kTail = 8;
 
 __device__ __forceinline__ bool in_all_lists(const int32_t *__restrict__ col, uint32_t (&lo)[kLists],
-                                             uint32_t (&n)[kLists], int32_t v, uint32_t &probes) {
+                                             uint32_t (&n)[kLists], int32_t v, uint32_t &probes, uint32_t &bytes) {
     bool found[kLists];
 #pragma unroll
     for (int s = 0; s < kLists; ++s) found[s] = n[s] == 0u;
@@ -128,6 +134,7 @@ __device__ __forceinline__ bool in_all_lists(const int32_t *__restrict__ col, ui
             const bool act = !found[s] && n[s] > kTail;
             x[s] = act ? col[lo[s] + h[s]] : 0;
             probes += act;
+            bytes += act ? 4u : 0u;
         }
 #pragma unroll
         for (int s = 0; s < kLists; ++s) {
@@ -151,6 +158,7 @@ __device__ __forceinline__ bool in_all_lists(const int32_t *__restrict__ col, ui
 #pragma unroll
             for (uint32_t i = 0; i < kTail; ++i) f |= col[lo[s] + (i < n[s] ? i : n[s] - 1u)] == v;
             probes += n[s];
+            bytes += 4u * kTail;  // every tail load is issued, clamped ones included
         }
         all &= f;
     }
@@ -243,6 +251,7 @@ struct Gen {
     uint32_t tasks;    // |C^L| by the paper's rule: the smallest backward list
     uint32_t scanned;  // length of the label slice that is actually scanned
     uint32_t lookups;  // slice bounds read
+    uint32_t bytes;    // device-memory bytes those reads requested
 };
 
 // GenerateTask (Alg. 2): for every parent lane in F at level l-1, walk its chain
@@ -255,7 +264,7 @@ struct Gen {
 template <bool SLIM, bool CG = false>
 __device__ __forceinline__ Gen generate_tasks(WaveStack &S, const SearchArgs &a, PlanPtr P, int l, uint64_t F,
                                               uint32_t lane) {
-    Gen g{0u, 0u, 0u};
+    Gen g{0u, 0u, 0u, 0u};
     uint32_t cs = 0, cl = 0xffu;
     if ((F >> lane) & 1ull) {
         const uint32_t bw = P->bwd[l];
@@ -277,6 +286,7 @@ __device__ __forceinline__ Gen generate_tasks(WaveStack &S, const SearchArgs &a,
                     sn = o[1] - sa;
                     d = sn;
                     ++g.lookups;
+                    g.bytes += 8u;
                 } else if (SLIM) {
                     const uint32_t *o = a.loff + static_cast<unsigned long long>(S.v[i * kWave + q]) * stride;
                     const uint32_t row0 = o[0];
@@ -284,6 +294,7 @@ __device__ __forceinline__ Gen generate_tasks(WaveStack &S, const SearchArgs &a,
                     sa = o[lab];
                     sn = o[lab + 1] - sa;
                     ++g.lookups;
+                    g.bytes += 16u;  // list bounds and slice bounds
                 } else {
                     d = ent_deg(S, i, q);
                     if (sliced) {
@@ -291,6 +302,7 @@ __device__ __forceinline__ Gen generate_tasks(WaveStack &S, const SearchArgs &a,
                         sa = o[0];
                         sn = o[1] - sa;
                         ++g.lookups;
+                        g.bytes += 8u;
                     } else {
                         sa = S.st[i * kWave + q];
                         sn = d;
@@ -413,7 +425,8 @@ __device__ __forceinline__ Round scatter(WaveStack &S, const int32_t *__restrict
 // carries the list's query edge + 1 and the bounds come from G' instead.
 template <bool SLIM, bool CG = false>
 __device__ __forceinline__ bool test_lists(const SearchArgs &a, uint32_t lab, uint32_t (&lo)[kLists],
-                                           uint32_t (&n)[kLists], int32_t v, uint32_t &probes, uint32_t &lookups) {
+                                           uint32_t (&n)[kLists], int32_t v, uint32_t &probes, uint32_t &lookups,
+                                           uint32_t &bytes) {
     if (SLIM) {
         uint32_t b0[kLists], b1[kLists];
         int32_t hub[kLists];
@@ -429,6 +442,7 @@ __device__ __forceinline__ bool test_lists(const SearchArgs &a, uint32_t lab, ui
             b1[t] = use ? o[1] : 0u;
             hub[t] = use && a.hub_id ? a.hub_id[w] : -1;  // read in the same round as the bounds
             lookups += use ? 1u : 0u;
+            bytes += use ? (a.hub_id ? 12u : 8u) : 0u;
         }
         bool empty = false;
 #pragma unroll
@@ -449,13 +463,14 @@ __device__ __forceinline__ bool test_lists(const SearchArgs &a, uint32_t lab, ui
                     a.hub_bits[static_cast<unsigned long long>(hub[t]) * a.hub_words + (static_cast<uint32_t>(v) >> 5)];
                 miss |= ((word >> (static_cast<uint32_t>(v) & 31u)) & 1u) == 0u;
                 ++probes;
+                bytes += 4u;
                 n[t] = 0u;
             }
         }
         if (miss) return false;
-        return in_all_lists(a.lcol, lo, n, v, probes);
+        return in_all_lists(a.lcol, lo, n, v, probes, bytes);
     }
-    return in_all_lists(a.col, lo, n, v, probes);
+    return in_all_lists(a.col, lo, n, v, probes, bytes);
 }
 
 // Process (Alg. 2): label and degree filters, then one walk down the parent
@@ -465,7 +480,8 @@ __device__ __forceinline__ bool test_lists(const SearchArgs &a, uint32_t lab, ui
 // tested together.
 template <bool SLIM, bool SB, bool CG = false>
 __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanPtr P, int l, const Round &r,
-                                        uint32_t lane, VInfo &vi, uint32_t &probes, uint32_t &lookups) {
+                                        uint32_t lane, VInfo &vi, uint32_t &probes, uint32_t &lookups,
+                                        uint32_t &bytes) {
     bool ok = lane < r.ntask;
     // The vertex record serves the filters only (the slim stack keeps no copy of
     // it), and often they hold already: a label slice holds that label alone,
@@ -473,7 +489,10 @@ __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanP
     // candidate-graph list holds only vertices that passed both filters.
     const bool need = !SLIM || (!CG && (a.loff_stride <= 1 || P->qdeg[l] > 1));
     vi = make_uint2(0u, 0u);
-    if (ok && need) vi = a.vinfo[r.v];
+    if (ok && need) {
+        vi = a.vinfo[r.v];
+        bytes += 8u;
+    }
     if (need)
         ok = ok && vi_lab(vi) == static_cast<uint32_t>(P->lab[l]) && vi_deg(vi) >= static_cast<uint32_t>(P->qdeg[l]);
     if (ok) {
@@ -504,7 +523,7 @@ __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanP
                 for (int t = 0; t < kLists; ++t)
                     if (used == t) { lo[t] = st; n[t] = len; }
                 if (++used == kLists) {
-                    if (!test_lists<SLIM, CG>(a, lab, lo, n, r.v, probes, lookups)) {
+                    if (!test_lists<SLIM, CG>(a, lab, lo, n, r.v, probes, lookups, bytes)) {
                         ok = false;
                         break;
                     }
@@ -515,7 +534,7 @@ __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanP
             }
             q = ent_pid<SLIM>(S, i, q);
         }
-        if (ok && used > 0) ok = test_lists<SLIM, CG>(a, lab, lo, n, r.v, probes, lookups);
+        if (ok && used > 0) ok = test_lists<SLIM, CG>(a, lab, lo, n, r.v, probes, lookups, bytes);
     }
     return ok;
 }
@@ -614,10 +633,10 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 // them the upper half of the unscattered tasks of this wavefront's
 // shallowest non-leaf level holding at least `threshold` of them ("split the
 // stack in half").  The donor keeps the lower half by moving that level's end.
-// The thief takes over one work unit of query cq.  Returns true if work was
-// handed over.
+// The thief takes over one work unit of query cq.  Returns the bytes this lane
+// wrote into the thief's mailbox (0 everywhere when nothing was handed over).
 template <bool SLIM>
-__device__ bool donate(WaveStack &S, const SearchArgs &a, PlanPtr P, int32_t cq, int base, int l, uint32_t lane) {
+__device__ uint32_t donate(WaveStack &S, const SearchArgs &a, PlanPtr P, int32_t cq, int base, int l, uint32_t lane) {
     const int k = P->k;
     const int top = l < k - 2 ? l : k - 2;
     for (int L = base; L <= top; ++L) {
@@ -633,7 +652,7 @@ __device__ bool donate(WaveStack &S, const SearchArgs &a, PlanPtr P, int32_t cq,
         if (total < static_cast<uint32_t>(a.steal_threshold)) continue;
         Control *ctl = a.ctl;
         const int32_t thief = claim_idle(a, (blockIdx.x * 37u) & 0xffffu);
-        if (thief < 0) return false;
+        if (thief < 0) return 0u;
         if (lane == 0) atomicAdd(&ctl->idle_count, -1);
         // split at h: the donor keeps tasks [0, h), the thief takes [h, total)
         const uint32_t h = total / 2;
@@ -667,9 +686,9 @@ __device__ bool donate(WaveStack &S, const SearchArgs &a, PlanPtr P, int32_t cq,
         }
         wait_memory();
         if (lane == 0) store_agent(&mb.status, static_cast<unsigned int>(kMailFull));
-        return true;
+        return mine ? 4u * static_cast<uint32_t>(L) : 0u;  // this lane's rows written to the mailbox
     }
-    return false;
+    return 0u;
 }
 
 enum Mode { kCount = 0, kEnumerate = 1, kExpand = 2 };
@@ -747,14 +766,26 @@ __device__ __forceinline__ int32_t find_query(const SearchArgs &a, PlanPtr P, in
 struct Tally {
     uint64_t tasks, scanned, lookups, probes;  // per lane
     uint32_t probes_run, lookups_run;          // per lane, folded into the above every 32 rounds
+    uint32_t bytes_run;                        // per lane: device-memory bytes requested since the last fold
     uint64_t groups, active, issued, count, steals;  // wave-uniform
+    uint64_t bytes, bytes_late;                // wave-uniform: folded bytes; those of windows that saw an abort
 };
 
-__device__ __forceinline__ void fold_run(Tally &t) {
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t x) {
+    for (int off = 32; off >= 1; off >>= 1) x += shfl(x, lane_id() ^ static_cast<uint32_t>(off));
+    return __builtin_amdgcn_readfirstlane(x);
+}
+
+// Folds the per-lane run counters; late: this window saw the abort word set.
+__device__ __forceinline__ void fold_run(Tally &t, bool late = false) {
     t.probes += t.probes_run;
     t.lookups += t.lookups_run;
     t.probes_run = 0;
     t.lookups_run = 0;
+    const uint64_t b = wave_sum32(t.bytes_run);
+    if (late) t.bytes_late += b;
+    else t.bytes += b;
+    t.bytes_run = 0;
 }
 
 // Adds the wavefront's matches to query q's count; returns true once the count
@@ -772,10 +803,14 @@ __device__ __forceinline__ bool count_flush(const SearchArgs &a, PlanPtr P, int3
     return capped;
 }
 
-// Adds the wavefront's counters to query q's slots and zeroes them.
+__device__ __forceinline__ unsigned int load_word(unsigned int *p);
+
+// Adds the wavefront's counters to query q's slots and zeroes them.  Bytes
+// since the last poll count as late if the query or the launch has been
+// aborted by now.
 __device__ void tally_flush(const SearchArgs &a, PlanPtr P, int32_t q, Tally &t) {
     (void)count_flush(a, P, q, t);
-    fold_run(t);
+    fold_run(t, load_word(&a.qctl[q].abort) != kAbortNone || load_word(&a.ctl->abort) != kAbortNone);
     const uint64_t tasks = wave_sum64(t.tasks);
     const uint64_t scanned = wave_sum64(t.scanned);
     const uint64_t lookups = wave_sum64(t.lookups);
@@ -790,6 +825,8 @@ __device__ void tally_flush(const SearchArgs &a, PlanPtr P, int32_t q, Tally &t)
         if (t.active) atomicAdd(&c.lanes_active, t.active);
         if (t.issued) atomicAdd(&c.lanes_issued, t.issued);
         if (t.steals) atomicAdd(&c.steals, t.steals);
+        if (t.bytes) atomicAdd(&c.bytes, static_cast<unsigned long long>(t.bytes));
+        if (t.bytes_late) atomicAdd(&c.bytes_late, static_cast<unsigned long long>(t.bytes_late));
     }
     t = Tally{};
 }
@@ -882,10 +919,12 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                         const uint32_t mid = (lo + hi + 1u) >> 1;
                         if (off[mid] <= task) lo = mid;
                         else hi = mid - 1u;
+                        t.bytes_run += 4u;
                     }
                     root = roots[permuted(lo, P->perm_mul, P->rows)];
                     if (!SLIM) rvi = a.vinfo[root];
                     v = a.lcol[a.vstart[P->vrow0 + lo] + (task - off[lo])];
+                    t.bytes_run += SLIM ? 16u : 24u;  // root, its first task, slice start, candidate (+ record)
                 }
                 push_entry<SLIM>(S, 0, lane, root, rvi, lane);
                 S.cl[kWave + lane] = 0u;  // the candidate came from position 0's list
@@ -894,7 +933,8 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                 r1.owner = lane;
                 r1.v = v;
                 VInfo vi;
-                const bool ok = process<SLIM, SB, CG>(S, a, P, 1, r1, lane, vi, t.probes_run, t.lookups_run);
+                const bool ok = process<SLIM, SB, CG>(S, a, P, 1, r1, lane, vi, t.probes_run, t.lookups_run,
+                                                      t.bytes_run);
                 const uint64_t m = ballot(ok);
                 t.active += ntask;
                 t.issued += kWave;
@@ -906,6 +946,7 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                             int32_t *row = a.out + slot * 2ull;
                             row[P->phi[0]] = root;
                             row[P->phi[1]] = v;
+                            t.bytes_run += 8u;
                         }
                     }
                     t.count += __popcll(m);
@@ -919,6 +960,7 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                 t.tasks += g.tasks;
                 t.scanned += g.scanned;
                 t.lookups += g.lookups;
+                t.bytes_run += g.bytes;
                 t.groups += __popcll(m);
                 open_level(S, 2, lane);
                 base = 2;
@@ -942,6 +984,7 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                 }
                 push_entry<SLIM>(S, i, lane, v, vi, lane);
             }
+            t.bytes_run += mine ? 12u * static_cast<uint32_t>(d) : 0u;  // id and record per position
             const uint64_t F0 = ballot(mine);
             if (d >= P->k) {  // the rows are whole matches (a one-vertex query)
                 t.count += __popcll(F0);
@@ -950,6 +993,7 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
             }
             lane0_add(&a.qctl[cq].live, 1);
             Gen g = generate_tasks<SLIM, CG>(S, a, P, d, F0, lane);
+            t.bytes_run += g.bytes;
             if (P->vmode) {  // first phase: each root's first hub_cut tasks only
                 first_phase_cut(S, P, lane);
                 g.scanned = g.scanned < P->hub_cut ? g.scanned : P->hub_cut;
@@ -1023,7 +1067,9 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                 }
                 push_entry<SLIM>(S, i, lane, v, vi, lane);
             }
-            generate_tasks<SLIM, CG>(S, a, P, L, lanes, lane);  // already counted by the donor
+            t.bytes_run += mine ? 12u * static_cast<uint32_t>(L) : 0u;
+            // the tasks and groups were counted by the donor; the reads are this wavefront's
+            t.bytes_run += generate_tasks<SLIM, CG>(S, a, P, L, lanes, lane).bytes;
             // position 1 is donated only by first-phase items of a two-phase pool: keep their cut
             if (P->vmode && L == 1) first_phase_cut(S, P, lane);
             if (lane == 0) {
@@ -1053,8 +1099,9 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
             }
             t.active += r.ntask;
             t.issued += kWave;
+            t.bytes_run += lane < r.ntask ? 4u : 0u;  // the candidate's id
             VInfo vi;
-            const bool ok = process<SLIM, SB, CG>(S, a, P, l, r, lane, vi, t.probes_run, t.lookups_run);
+            const bool ok = process<SLIM, SB, CG>(S, a, P, l, r, lane, vi, t.probes_run, t.lookups_run, t.bytes_run);
             const uint64_t m = ballot(ok);
             if (MODE == kExpand) {
                 if (m) {
@@ -1066,6 +1113,7 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                             for (int i = 0; i < d; ++i) row[i] = S.v[(i) * kWave + (r.owner)];
                             row[d] = r.v;
                             if (a.measure_next) my_bound += next_level_bound(S, a, P, d, r);
+                            t.bytes_run += 4u * static_cast<uint32_t>(d + 1);  // the row, written at the flush
                         }
                         staged += nv;
                     } else {
@@ -1075,6 +1123,7 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                             int32_t *row = a.out + slot * static_cast<unsigned long long>(d + 1);
                             for (int i = 0; i < d; ++i) row[i] = S.v[(i) * kWave + (r.owner)];
                             row[d] = r.v;
+                            t.bytes_run += 4u * static_cast<uint32_t>(d + 1);
                         }
                         if (ok && a.measure_next) my_bound += next_level_bound(S, a, P, d, r);
                     }
@@ -1091,6 +1140,7 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                             row[P->phi[i]] = S.v[(i) * kWave + (q)];
                             q = ent_pid<SLIM>(S, i, q);
                         }
+                        t.bytes_run += 4u * static_cast<uint32_t>(k);
                     }
                 }
                 t.count += __popcll(m);
@@ -1100,6 +1150,7 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                 t.tasks += g.tasks;
                 t.scanned += g.scanned;
                 t.lookups += g.lookups;
+                t.bytes_run += g.bytes;
                 t.groups += __popcll(m);
                 open_level(S, l + 1, lane);
                 ++l;
@@ -1122,9 +1173,9 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                         int waiting = 0;
                         if (lane == 0) waiting = load_agent(&ctl->idle_count);
                         if (static_cast<int>(read_lane(static_cast<uint32_t>(waiting), 0)) > 0)
-                            donate<SLIM>(S, a, P, cq, base, l, lane);
+                            t.bytes_run += donate<SLIM>(S, a, P, cq, base, l, lane);
                     }
-                    fold_run(t);
+                    fold_run(t, stop || dropped);
                 }
                 if (stop || dropped) break;
             }

@@ -225,6 +225,29 @@ def induced_query(g: Graph, verts: Sequence[int]) -> Query:
                  witness=verts.astype(np.int32))
 
 
+def restricted(g: Graph, keep: np.ndarray) -> Graph:
+    """The same vertex set with only the edges whose two ends have keep[v] set
+    (vertices without keep become isolated); labels unchanged.  Random walks on
+    it stay inside the kept vertices, and the induced edges among kept vertices
+    are those of g."""
+    keep = np.asarray(keep, dtype=bool)
+    src = np.repeat(np.arange(g.n, dtype=np.int32), np.diff(g.row_ptr))
+    m = keep[src] & keep[g.col]
+    deg = np.bincount(src[m], minlength=g.n)
+    row_ptr = np.zeros(g.n + 1, dtype=np.int64)
+    np.cumsum(deg, out=row_ptr[1:])
+    return Graph(row_ptr, np.ascontiguousarray(g.col[m]), g.labels)
+
+
+def hub_split_labels(g: Graph, max_degree: int, num_labels: int, seed: int) -> np.ndarray:
+    """A test labelling of g's vertices: vertices of degree above max_degree get
+    label num_labels (one label for all of them), every other vertex a uniform
+    label in [0, num_labels)."""
+    labels = uniform_labels(g.n, num_labels, seed)
+    labels[np.diff(g.row_ptr) > max_degree] = num_labels
+    return labels
+
+
 def _live(g: Graph) -> np.ndarray:
     live = np.flatnonzero(np.diff(g.row_ptr) > 0).astype(np.int32)
     if live.shape[0] == 0:

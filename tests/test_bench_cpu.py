@@ -23,21 +23,26 @@ def test_kernel_keys():
     assert bench.kernel_key("gm::(anonymous namespace)::cand_fill_kernel(int const*)") == "cand_fill_kernel"
 
 
-def test_algorithmic_bytes():
-    # 12 B per scanned candidate, 8 B per slice lookup, 4 B per probe, 12 B per matched position of a pool row
-    assert bench.algorithmic_bytes(pool_rows=0, depth=1, scanned=1, lookups=0, probes=0) == 12
-    assert bench.algorithmic_bytes(pool_rows=10, depth=3, scanned=100, lookups=7, probes=5) == 1200 + 56 + 20 + 360
-
-
-def test_traffic_summary_is_used_only_for_the_same_sources(tmp_path, monkeypatch):
+def test_traffic_summary_is_used_only_for_the_same_sources(tmp_path):
     f = tmp_path / "traffic.txt"
     f.write_text(f"# header\n\nkernel_sha: {bench.kernel_sha()}\ntraffic_bytes_per_launch: 12345\n")
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
-    assert bench.read_traffic() == {"bytes_per_launch": 12345.0}
+    assert bench.read_traffic(str(f)) == {"bytes_per_launch": 12345.0}
     f.write_text("kernel_sha: 0000000000000000\ntraffic_bytes_per_launch: 12345\n")
-    assert bench.read_traffic() is None
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
-    assert bench.read_traffic() is None
+    assert bench.read_traffic(str(f)) is None
+    assert bench.read_traffic(str(tmp_path / "missing.txt")) is None
+    assert bench.traffic_file_for("rmat24_ef16_zipf8_q12-32").endswith("profiles/search_kernel_rmat24_q12-32_traffic.txt")
+
+
+def test_roofline_uses_the_issued_bytes():
+    class R:
+        def __init__(self, ms, b, late):
+            self.kernel_ms, self.kernel_bytes, self.kernel_bytes_late = ms, b, late
+    rf = bench.roofline([R(2.0, 8e9, 1e9), R(2.0, 8e9, 0.0)], "/nonexistent")
+    assert rf["launches"] == 2 and rf["avg_launch_ms"] == 2.0
+    assert rf["achieved"] == 4000.0 and rf["frac"] == 0.5
+    assert rf["issued_bytes_per_launch"] == 8e9 and rf["late_bytes_per_launch_max"] == 0.5e9
+    assert abs(rf["frac_excluding_late"] - 0.46875) < 1e-12
+    assert rf["traffic"] is None
 
 
 def _write_csv(path, header, rows):
