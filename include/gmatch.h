@@ -301,13 +301,17 @@ typedef struct {
     int32_t trials;              /* settings measured */
     double best_ms;              /* device time of the chosen setting on the sample */
     double default_ms;           /* device time of the engine's settings before tuning */
+    int32_t merge_ratio;         /* as in gm_options: LDS staging of short lists (-1 = never) */
+    int32_t reserved;
 } gm_tuning;
 
 /* Autotuner of the batched launch: runs gm_count_batch on the sample qids[nq]
  * and tunes one setting at a time, each over a fixed list, keeping the best
  * value before moving on: streams (queries in flight) over 1, 16, 64, 256;
  * wavefronts per CU over as-many-as-fit, 12, 8; stack layout (LDS bytes per
- * wavefront) slim, full; steal threshold 32, 128, 512; launch grouping.  The
+ * wavefront) slim, full; steal threshold 32, 128, 512; LDS staging of short
+ * lists (merge_ratio: the staging buffer, 2, 4 or 8 entries per lane, or
+ * none); launch grouping.  The
  * measure is the device time of the batch's launches.  The result stays in
  * the engine's options and is reported in *out.  Every setting must give the
  * same count for each query that finishes under both; a difference returns

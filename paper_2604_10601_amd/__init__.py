@@ -82,7 +82,7 @@ class BatchInfo(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
-class Tuning(ctypes.Structure):
+class Tuning(ctypes.Structure):  # gm_tuning
     _fields_ = [
         ("waves_per_cu", ctypes.c_int32),
         ("steal_threshold", ctypes.c_int32),
@@ -92,6 +92,8 @@ class Tuning(ctypes.Structure):
         ("trials", ctypes.c_int32),
         ("best_ms", ctypes.c_double),
         ("default_ms", ctypes.c_double),
+        ("merge_ratio", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -204,12 +206,23 @@ _lib = None
 
 
 def load_library():
-    """Load libgmatch.so (raises if it has not been built)."""
+    """Load libgmatch.so (raises if it has not been built).
+
+    PyTorch for ROCm ships its own HIP and HSA runtimes, and two runtimes in one
+    process cannot both own the GPU: whichever initialises second finds no
+    device.  When torch is installed it is therefore imported first, so that
+    libgmatch binds to the runtime torch has loaded and device buffers and
+    streams can pass between the two.  Without torch the system runtime is used.
+    """
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2604_10601_amd/build.py")
+    try:
+        import torch  # noqa: F401  (loads torch's HIP runtime before libgmatch resolves its own)
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     p, i32, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
     lib.gm_create.argtypes = [i32, ctypes.POINTER(Options), ctypes.POINTER(p)]

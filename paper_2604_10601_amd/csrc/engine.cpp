@@ -796,6 +796,11 @@ gm_status attach_stealing(gm_engine *e, LaunchCtx &c, SearchArgs &a) {
     return GM_OK;
 }
 
+// Staging entries per lane of the LDS-staged intersection (0 = never stage).
+int32_t merge_slots(const gm_engine *e) {
+    return e->opt.merge_ratio < 0 ? 0 : (e->opt.merge_ratio == 0 ? gm::kDefaultMergeSlots : e->opt.merge_ratio);
+}
+
 SearchArgs graph_args(const gm_engine *e, const LaunchCtx &c) {
     SearchArgs a{};
     a.vinfo = e->d_vinfo;
@@ -810,6 +815,7 @@ SearchArgs graph_args(const gm_engine *e, const LaunchCtx &c) {
     a.plans = c.d_plans;
     a.qctl = c.d_qctl;
     a.streams = c.d_streams;
+    a.merge_slots = merge_slots(e);
     return a;
 }
 
@@ -1072,7 +1078,7 @@ gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, ui
         // few).  Otherwise 64: measured on the scale-20 workload, items of R /
         // wavefronts roots (about 3) ran 3 % slower than 64.
         const unsigned long long waves = static_cast<unsigned long long>(
-            std::max(1, gm::search_waves(q->k, e->num_cu, e->opt.waves_per_cu, cg || use_slim(e, q->k))));
+            std::max(1, gm::search_waves(q->k, e->num_cu, e->opt.waves_per_cu, cg || use_slim(e, q->k), merge_slots(e))));
         p.rpi = R < waves ? 1u : static_cast<uint32_t>(gm::kWave);
     }
     p.item_split = (R + p.rpi - 1) / p.rpi;
@@ -1377,7 +1383,7 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
 
 // Wavefronts per CU a search launch for a query of k vertices keeps resident.
 int residency(const gm_engine *e, int32_t k) {
-    return gm::search_waves(k, e->num_cu, e->opt.waves_per_cu, use_slim(e, k));
+    return gm::search_waves(k, e->num_cu, e->opt.waves_per_cu, use_slim(e, k), merge_slots(e));
 }
 
 // Work-item streams of a batched launch: the option, else 64 (queries in flight).
@@ -1605,6 +1611,7 @@ gm_status run_tune(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t cap, 
     best.steal_threshold = saved.steal_threshold > 0 ? saved.steal_threshold : 128;
     best.stack_layout = saved.stack_layout == 1 ? 1 : 2;
     best.batch_streams = batch_streams(e);
+    best.merge_ratio = saved.merge_ratio != 0 ? saved.merge_ratio : gm::kDefaultMergeSlots;
     double best_ms = info.kernel_ms;
     const double default_ms = info.kernel_ms;
     int32_t trials = 1;
@@ -1617,6 +1624,7 @@ gm_status run_tune(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t cap, 
         {&gm_options::waves_per_cu, {0, 12, 8}},
         {&gm_options::stack_layout, {2, 1}},
         {&gm_options::steal_threshold, {32, 128, 512}},
+        {&gm_options::merge_ratio, {-1, 2, 4, 8}},
         {&gm_options::batch_single_launch, {0, 1}},
     };
     for (const Knob &kb : knobs) {
@@ -1652,6 +1660,7 @@ gm_status run_tune(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t cap, 
     t.stack_layout = best.stack_layout;
     t.batch_single_launch = best.batch_single_launch;
     t.batch_streams = best.batch_streams;
+    t.merge_ratio = best.merge_ratio;
     t.trials = trials;
     t.best_ms = best_ms;
     t.default_ms = default_ms;

@@ -9,6 +9,8 @@
 namespace gm {
 
 constexpr int kMaxK = 32;  // largest query supported
+constexpr int kMaxMergeSlots = 8;      // LDS-staged intersection: largest staging entries per lane
+constexpr int kDefaultMergeSlots = 4;  // ... and the default (lists up to 4 x the run's candidates)
 constexpr int kWave = 64;  // CDNA wavefront width
 
 // Packed per-vertex record, one 8-byte load per candidate:
@@ -184,6 +186,8 @@ struct SearchArgs {
     const uint32_t *gbounds;
     unsigned long long gn;     // |V(G)|
     int32_t measure_next;      // expansion: add the next level's size bound to ctl->measure
+    int32_t merge_slots;       // LDS-staged intersection: staging entries per lane, 0 = off (slim
+                               // layout only); a run of r candidates stages a list of n <= slots * r
 };
 
 // Candidate graph of one query (candidate.hip).  Positions follow the
@@ -261,7 +265,7 @@ hipError_t launch_level1(const int32_t *roots, int32_t R, unsigned long long per
                          uint32_t *voff, uint32_t *tmp, QCtl *qc, Plan *plan, StreamCtl *sc, int num_cu,
                          hipStream_t s);
 // Wavefronts a depth-first search launch for a query of `levels` positions keeps resident.
-int search_waves(int levels, int num_cu, int waves_per_cu, bool slim);
+int search_waves(int levels, int num_cu, int waves_per_cu, bool slim, int merge_slots);
 hipError_t launch_steal_init(Mailbox *mail, unsigned long long *idle_bits, int32_t n, hipStream_t s);
 
 // Graph load (graph_build.hip).  Error bits of the checks:

@@ -353,6 +353,7 @@ struct Round {
     uint32_t ntask;  // tasks this round (0: level exhausted)
     uint32_t owner;  // parent lane of this lane's task
     int32_t v;       // candidate of this lane's task (valid if lane < ntask)
+    uint32_t run;    // lanes [run & 0xff, run >> 8) hold this parent's tasks of the round (ascending ids)
 };
 
 // ScatterTask (Alg. 2) for the whole wavefront: hand the next <= 64 tasks of
@@ -378,6 +379,7 @@ __device__ __forceinline__ Round scatter(WaveStack &S, const int32_t *__restrict
         r.ntask = 0;
         r.owner = 0;
         r.v = -1;
+        r.run = 0;
         return r;
     }
     r.ntask = tot < 64u ? tot : 64u;
@@ -390,6 +392,9 @@ __device__ __forceinline__ Round scatter(WaveStack &S, const int32_t *__restrict
     const uint64_t starts = ballot(o != 0xffu);
     const uint64_t upto = lane == 63u ? ~0ull : ((2ull << lane) - 1ull);
     const uint32_t s = 63u - static_cast<uint32_t>(__clzll(starts & upto));
+    const uint64_t later = starts & ~upto;  // runs starting after this lane
+    const uint32_t e = later ? static_cast<uint32_t>(__builtin_ctzll(later)) : 64u;
+    r.run = s | ((e < r.ntask ? e : r.ntask) << 8);
     const uint32_t owner = shfl(o, s);
     const uint32_t ocst = shfl(cst, owner);
     const uint32_t j = lane - s + (owner == ci ? cjo : 0u);
@@ -418,70 +423,110 @@ __device__ __forceinline__ Round scatter(WaveStack &S, const int32_t *__restrict
     return r;
 }
 
-// Test the collected lists (lo[t], n[t]); n[t] == 0 marks an unused slot.  In
-// the slim layout lo[t] holds the list's vertex w and n[t] = 1 until the bounds
-// of w's slice with the candidate's label are read here, for all slots at once;
-// an empty slice means v is not a neighbour of w.  On the candidate graph n[t]
-// carries the list's query edge + 1 and the bounds come from G' instead.
-template <bool SLIM, bool CG = false>
-__device__ __forceinline__ bool test_lists(const SearchArgs &a, uint32_t lab, uint32_t (&lo)[kLists],
-                                           uint32_t (&n)[kLists], int32_t v, uint32_t &probes, uint32_t &lookups,
-                                           uint32_t &bytes) {
-    if (SLIM) {
-        uint32_t b0[kLists], b1[kLists];
-        int32_t hub[kLists];
-#pragma unroll
-        for (int t = 0; t < kLists; ++t) {
-            const bool use = n[t] != 0u;
-            const uint32_t w = use ? lo[t] : 0u;
-            // candidate graph: n[t] - 1 is the list's query edge, and the
-            // candidate is in C(phi[l]), so N(w) restricted to C(phi[l]) answers
-            const uint32_t *o = CG ? a.gbounds + 2ull * (static_cast<unsigned long long>(use ? n[t] - 1u : 0u) * a.gn + w)
-                                   : a.loff + static_cast<unsigned long long>(w) * a.loff_stride + lab;
-            b0[t] = use ? o[0] : 0u;
-            b1[t] = use ? o[1] : 0u;
-            hub[t] = use && a.hub_id ? a.hub_id[w] : -1;  // read in the same round as the bounds
-            lookups += use ? 1u : 0u;
-            bytes += use ? (a.hub_id ? 12u : 8u) : 0u;
-        }
-        bool empty = false;
-#pragma unroll
-        for (int t = 0; t < kLists; ++t) {
-            if (n[t] != 0u) {
-                empty |= b1[t] == b0[t];
-                lo[t] = b0[t];
-                n[t] = b1[t] - b0[t];
-            }
-        }
-        if (empty) return false;
-        // a hub's list is answered by one bit of its adjacency bitmap, not by bisection
-        bool miss = false;
-#pragma unroll
-        for (int t = 0; t < kLists; ++t) {
-            if (n[t] != 0u && hub[t] >= 0) {
-                const uint32_t word =
-                    a.hub_bits[static_cast<unsigned long long>(hub[t]) * a.hub_words + (static_cast<uint32_t>(v) >> 5)];
-                miss |= ((word >> (static_cast<uint32_t>(v) & 31u)) & 1u) == 0u;
-                ++probes;
-                bytes += 4u;
-                n[t] = 0u;
-            }
-        }
-        if (miss) return false;
-        return in_all_lists(a.lcol, lo, n, v, probes, bytes);
+// Bits [lo, hi) of a 64-bit lane mask.
+__device__ __forceinline__ uint64_t lane_range(uint32_t lo, uint32_t hi) {
+    const uint64_t below_hi = hi >= 64u ? ~0ull : ((1ull << hi) - 1ull);
+    return below_hi & ~((1ull << lo) - 1ull);
+}
+
+// LDS-staged intersection (Sec. 5.2 costs each membership test as one binary
+// search; here a run of candidates shares one list).  The lanes calling this
+// together belong to one or more runs; within a run every lane tests the same
+// ascending list B = list[0 .. n) and the run's candidates, taken in lane order,
+// form the ascending sequence A (distinct ids).  The run's lanes load B into
+// their share of the staging area (slots entries per lane, so n <= slots * r
+// fits), write A next to it, and intersect the two by merge path (Green,
+// McColl and Bader, 2012): the merge of A and B (A first on ties) is cut into
+// r segments of equal length, lane j finds where segment j starts by bisecting
+// its diagonal, then walks the segment.  When the walk takes A[x] it has just
+// passed every entry of B below A[x], so A[x] is in B iff the next entry of B
+// equals it; lane j writes that into flag x, and each lane reads its own flag.
+// One wavefront's LDS operations complete in issue order, so the writes of one
+// step are seen by the reads of the next.  Adds the entries this lane loaded to
+// probes and their bytes to bytes.
+__device__ __forceinline__ bool merge_member(const int32_t *__restrict__ list, uint32_t n, uint8_t *area,
+                                             uint32_t slots, uint32_t run, int32_t v, uint32_t &probes,
+                                             uint32_t &bytes) {
+    const uint32_t rs = run & 0xffu, re = run >> 8;
+    const uint64_t mine = ballot(true) & lane_range(rs, re);
+    const uint32_t r = static_cast<uint32_t>(__popcll(mine));
+    const uint32_t j = popc_below(mine);
+    int32_t *B = reinterpret_cast<int32_t *>(area) + rs * slots;
+    int32_t *A = reinterpret_cast<int32_t *>(area) + kWave * slots + rs;
+    uint8_t *F = area + (kWave * slots + kWave) * 4u + rs;
+    A[j] = v;
+    for (uint32_t k = j; k < n; k += r) {
+        B[k] = list[k];
+        ++probes;
+        bytes += 4u;
     }
-    return in_all_lists(a.col, lo, n, v, probes, bytes);
+    const uint32_t total = r + n;
+    const uint32_t seg = (total + r - 1u) / r;
+    const uint32_t k0 = j * seg < total ? j * seg : total;
+    const uint32_t k1 = k0 + seg < total ? k0 + seg : total;
+    // split of diagonal k0: the number x of A's entries among the first k0 of the merge
+    uint32_t x = k0 > n ? k0 - n : 0u;
+    uint32_t xh = k0 < r ? k0 : r;
+    while (x < xh) {
+        const uint32_t mid = (x + xh) >> 1;
+        if (B[k0 - mid - 1u] >= A[mid]) x = mid + 1u;
+        else xh = mid;
+    }
+    uint32_t y = k0 - x;
+    for (uint32_t k = k0; k < k1; ++k) {
+        if (x < r && (y >= n || A[x] <= B[y])) {
+            F[x] = static_cast<uint8_t>(y < n && B[y] == A[x]);
+            ++x;
+        } else {
+            ++y;
+        }
+    }
+    return F[j] != 0;
+}
+
+// Membership of v in the list of backward neighbour w at position l (slim
+// layout): w's label slice for l's label, or on the candidate graph the list of
+// query edge `edge` for w.  One round reads the list bounds and w's hub id; an
+// empty list rejects v; a hub's list is answered by one bit of its adjacency
+// bitmap; a list short against its run (n <= slots x the run's lanes still
+// testing) is staged in LDS and intersected by merge path; any other list is
+// bisected in device memory lane by lane (in_all_lists).
+template <bool CG>
+__device__ __forceinline__ bool slim_member(const SearchArgs &a, uint8_t *marea, uint32_t run, uint32_t lab,
+                                            uint32_t w, uint32_t edge, int32_t v, uint32_t &probes,
+                                            uint32_t &lookups, uint32_t &bytes) {
+    const uint32_t *o = CG ? a.gbounds + 2ull * (static_cast<unsigned long long>(edge) * a.gn + w)
+                           : a.loff + static_cast<unsigned long long>(w) * a.loff_stride + lab;
+    const uint32_t b0 = o[0], b1 = o[1];
+    const int32_t hub = a.hub_id ? a.hub_id[w] : -1;  // read in the same round as the bounds
+    ++lookups;
+    bytes += a.hub_id ? 12u : 8u;
+    if (b1 == b0) return false;
+    if (hub >= 0) {
+        const uint32_t word =
+            a.hub_bits[static_cast<unsigned long long>(hub) * a.hub_words + (static_cast<uint32_t>(v) >> 5)];
+        ++probes;
+        bytes += 4u;
+        return ((word >> (static_cast<uint32_t>(v) & 31u)) & 1u) != 0u;
+    }
+    const uint32_t n = b1 - b0;
+    if (a.merge_slots > 0) {
+        // lanes of this run still testing here: all of them reached this point with the same list
+        const uint32_t live = static_cast<uint32_t>(__popcll(ballot(true) & lane_range(run & 0xffu, run >> 8)));
+        if (n <= static_cast<uint32_t>(a.merge_slots) * live)
+            return merge_member(a.lcol + b0, n, marea, static_cast<uint32_t>(a.merge_slots), run, v, probes, bytes);
+    }
+    uint32_t lo1[kLists] = {b0}, n1[kLists] = {n};
+    return in_all_lists(a.lcol, lo1, n1, v, probes, bytes);
 }
 
 // Process (Alg. 2): label and degree filters, then one walk down the parent
 // chain checking injectivity and membership in every backward neighbour's list
-// other than the one the candidate came from.  The lists are collected during
-// the walk (kLists at a time, the slot index being the same in every lane) and
-// tested together.
+// other than the one the candidate came from, one list at a time.
 template <bool SLIM, bool SB, bool CG = false>
 __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanPtr P, int l, const Round &r,
                                         uint32_t lane, VInfo &vi, uint32_t &probes, uint32_t &lookups,
-                                        uint32_t &bytes) {
+                                        uint32_t &bytes, uint8_t *marea) {
     bool ok = lane < r.ntask;
     // The vertex record serves the filters only (the slim stack keeps no copy of
     // it), and often they hold already: a label slice holds that label alone,
@@ -499,11 +544,10 @@ __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanP
         const uint32_t bw = P->bwd[l];
         // symmetry-breaking conditions: only in launches that hold a query with them
         const uint32_t sblt = SB ? P->sb_lt[l] : 0u, sbgt = SB ? P->sb_gt[l] : 0u;
+        // the backward neighbour whose list the candidate came from needs no
+        // test; it is the same for every lane of a run
         const uint32_t js = S.cl[l * kWave + r.owner] & 0xffu;
         const uint32_t lab = a.loff_stride > 1 ? static_cast<uint32_t>(P->lab[l]) : 0u;
-        uint32_t lo[kLists] = {};
-        uint32_t n[kLists] = {};
-        int used = 0;
         uint32_t q = r.owner;
         for (int i = l - 1; i >= 0; --i) {
             const int32_t w = S.v[i * kWave + q];
@@ -515,26 +559,22 @@ __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanP
                 ok = false;
                 break;
             }
-            if ((bw >> i) & 1u) {
-                const bool skip = static_cast<uint32_t>(i) == js;
-                const uint32_t st = SLIM ? static_cast<uint32_t>(w) : S.st[i * kWave + q];
-                const uint32_t len = skip ? 0u : (CG ? cg_slot(P, l, bw, i) + 1u : (SLIM ? 1u : ent_deg(S, i, q)));
-#pragma unroll
-                for (int t = 0; t < kLists; ++t)
-                    if (used == t) { lo[t] = st; n[t] = len; }
-                if (++used == kLists) {
-                    if (!test_lists<SLIM, CG>(a, lab, lo, n, r.v, probes, lookups, bytes)) {
-                        ok = false;
-                        break;
-                    }
-                    used = 0;
-#pragma unroll
-                    for (int t = 0; t < kLists; ++t) n[t] = 0u;
+            if (((bw >> i) & 1u) && static_cast<uint32_t>(i) != js) {
+                bool in;
+                if (SLIM) {
+                    in = slim_member<CG>(a, marea, r.run, lab, static_cast<uint32_t>(w), CG ? cg_slot(P, l, bw, i) : 0u,
+                                         r.v, probes, lookups, bytes);
+                } else {
+                    uint32_t lo1[kLists] = {S.st[i * kWave + q]}, n1[kLists] = {ent_deg(S, i, q)};
+                    in = in_all_lists(a.col, lo1, n1, r.v, probes, bytes);
+                }
+                if (!in) {
+                    ok = false;
+                    break;
                 }
             }
             q = ent_pid<SLIM>(S, i, q);
         }
-        if (ok && used > 0) ok = test_lists<SLIM, CG>(a, lab, lo, n, r.v, probes, lookups, bytes);
     }
     return ok;
 }
@@ -736,8 +776,15 @@ __device__ __forceinline__ void flush_stage(int32_t *stage, uint32_t &staged, in
 
 // LDS of one wavefront for a query of `levels` positions (stack, plus the output
 // staging buffer of an expansion).
-__host__ __device__ constexpr size_t wave_lds_bytes(int levels, bool expand, bool slim) {
-    return stack_bytes(levels, slim) + (expand ? static_cast<size_t>(kStageRows) * kStageWidth * 4u : 0u);
+// Staging area of the LDS-staged intersection: slots list entries per lane, the
+// candidates (one per lane) and their flags.
+__host__ __device__ constexpr size_t merge_area_bytes(int slots) {
+    return slots > 0 ? static_cast<size_t>(slots) * kWave * 4u + kWave * 4u + kWave : 0u;
+}
+
+__host__ __device__ constexpr size_t wave_lds_bytes(int levels, bool expand, bool slim, int slots) {
+    return stack_bytes(levels, slim) + (expand ? static_cast<size_t>(kStageRows) * kStageWidth * 4u : 0u) +
+           (slim ? (merge_area_bytes(slots) + 15u) / 16u * 16u : 0u);
 }
 
 // First phase of a two-phase pool: a root's position-1 task group keeps only
@@ -803,14 +850,16 @@ __device__ __forceinline__ bool count_flush(const SearchArgs &a, PlanPtr P, int3
     return capped;
 }
 
-__device__ __forceinline__ unsigned int load_word(unsigned int *p);
-
 // Adds the wavefront's counters to query q's slots and zeroes them.  Bytes
 // since the last poll count as late if the query or the launch has been
 // aborted by now.
-__device__ void tally_flush(const SearchArgs &a, PlanPtr P, int32_t q, Tally &t) {
+__device__ __forceinline__ void tally_flush(const SearchArgs &a, PlanPtr P, int32_t q, Tally &t) {
     (void)count_flush(a, P, q, t);
-    fold_run(t, load_word(&a.qctl[q].abort) != kAbortNone || load_word(&a.ctl->abort) != kAbortNone);
+    unsigned int ab = 0;
+    if (lane_id() == 0)
+        ab = __hip_atomic_load(&a.qctl[q].abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) |
+             __hip_atomic_load(&a.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    fold_run(t, read_lane(ab, 0) != kAbortNone);
     const uint64_t tasks = wave_sum64(t.tasks);
     const uint64_t scanned = wave_sum64(t.scanned);
     const uint64_t lookups = wave_sum64(t.lookups);
@@ -844,9 +893,11 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
     static_assert(!CG || (SLIM && MODE != kExpand), "the candidate graph runs the slim depth-first search");
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     const int levels = a.levels;
-    uint8_t *mine = lds + (threadIdx.x / kWave) * wave_lds_bytes(levels, MODE == kExpand, SLIM);
+    uint8_t *mine = lds + (threadIdx.x / kWave) * wave_lds_bytes(levels, MODE == kExpand, SLIM, a.merge_slots);
     WaveStack S = carve_stack<SLIM>(mine, levels);
     int32_t *stage = reinterpret_cast<int32_t *>(mine + stack_bytes(levels, SLIM));
+    uint8_t *marea = mine + stack_bytes(levels, SLIM) +
+                     (MODE == kExpand ? static_cast<size_t>(kStageRows) * kStageWidth * 4u : 0u);
     uint32_t staged = 0;
     const uint32_t lane = lane_id();
     Control *ctl = a.ctl;
@@ -932,9 +983,10 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                 r1.ntask = ntask;
                 r1.owner = lane;
                 r1.v = v;
+                r1.run = lane | ((lane + 1u) << 8);  // every lane is its own root
                 VInfo vi;
                 const bool ok = process<SLIM, SB, CG>(S, a, P, 1, r1, lane, vi, t.probes_run, t.lookups_run,
-                                                      t.bytes_run);
+                                                      t.bytes_run, marea);
                 const uint64_t m = ballot(ok);
                 t.active += ntask;
                 t.issued += kWave;
@@ -1101,7 +1153,8 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
             t.issued += kWave;
             t.bytes_run += lane < r.ntask ? 4u : 0u;  // the candidate's id
             VInfo vi;
-            const bool ok = process<SLIM, SB, CG>(S, a, P, l, r, lane, vi, t.probes_run, t.lookups_run, t.bytes_run);
+            const bool ok = process<SLIM, SB, CG>(S, a, P, l, r, lane, vi, t.probes_run, t.lookups_run, t.bytes_run,
+                                                  marea);
             const uint64_t m = ballot(ok);
             if (MODE == kExpand) {
                 if (m) {
@@ -1343,8 +1396,8 @@ __global__ __launch_bounds__(256) void root_scan_kernel(const VInfo *__restrict_
 }
 
 template <int MODE, bool SLIM, bool SB, bool CG, int OCC>
-int blocks_per_cu(int levels, int waves_per_cu) {
-    const size_t lds_bytes = wave_lds_bytes(levels, MODE == kExpand, SLIM) * kWavesPerBlock;
+int blocks_per_cu(int levels, int waves_per_cu, int slots) {
+    const size_t lds_bytes = wave_lds_bytes(levels, MODE == kExpand, SLIM, slots) * kWavesPerBlock;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel<MODE, SLIM, SB, CG, OCC>, kBlock,
                                                      lds_bytes) != hipSuccess ||
@@ -1362,12 +1415,15 @@ hipError_t launch_persistent(const SearchArgs &a, int num_cu, int waves_per_cu, 
     if (a.levels < 1 || a.levels > kMaxK || a.nq < 1 || !a.plans || !a.qctl || a.nstreams < 1 || !a.streams)
         return hipErrorInvalidValue;
     if (CG && (!a.gbounds || a.gn < 1)) return hipErrorInvalidValue;
-    const size_t lds_bytes = wave_lds_bytes(a.levels, MODE == kExpand, SLIM) * kWavesPerBlock;
-    int blocks = num_cu * blocks_per_cu<MODE, SLIM, SB, CG, OCC>(a.levels, waves_per_cu);
+    if (a.merge_slots < 0 || a.merge_slots > kMaxMergeSlots) return hipErrorInvalidValue;
+    SearchArgs b = a;
+    if (!SLIM) b.merge_slots = 0;  // the full layout bisects whole lists
+    const size_t lds_bytes = wave_lds_bytes(b.levels, MODE == kExpand, SLIM, b.merge_slots) * kWavesPerBlock;
+    int blocks = num_cu * blocks_per_cu<MODE, SLIM, SB, CG, OCC>(b.levels, waves_per_cu, b.merge_slots);
     if (a.mail && blocks * kWavesPerBlock > a.steal_slots) blocks = a.steal_slots / kWavesPerBlock;  // one mailbox each
     if (blocks < 1) blocks = 1;
     if (grid_waves) *grid_waves = blocks * kWavesPerBlock;
-    hipLaunchKernelGGL((search_kernel<MODE, SLIM, SB, CG, OCC>), dim3(blocks), dim3(kBlock), lds_bytes, s, a);
+    hipLaunchKernelGGL((search_kernel<MODE, SLIM, SB, CG, OCC>), dim3(blocks), dim3(kBlock), lds_bytes, s, b);
     return hipGetLastError();
 }
 
@@ -1376,9 +1432,9 @@ hipError_t launch_persistent(const SearchArgs &a, int num_cu, int waves_per_cu, 
 // where LDS cannot hold five stacks per SIMD anyway (queries of 10+ vertices),
 // so they run only where the occupancy calculator says they fit more.
 template <int MODE, bool SB>
-bool five_waves_fit(int levels, int waves_per_cu) {
-    return blocks_per_cu<MODE, true, SB, false, 5>(levels, waves_per_cu) >
-           blocks_per_cu<MODE, true, SB, false, 4>(levels, waves_per_cu);
+bool five_waves_fit(int levels, int waves_per_cu, int slots) {
+    return blocks_per_cu<MODE, true, SB, false, 5>(levels, waves_per_cu, slots) >
+           blocks_per_cu<MODE, true, SB, false, 4>(levels, waves_per_cu, slots);
 }
 
 // One of the instantiations: mode x stack layout x symmetry conditions x
@@ -1392,11 +1448,11 @@ hipError_t launch_mode(const SearchArgs &a, int num_cu, int waves_per_cu, hipStr
         }
         if (a.slim) {
             if (a.sb) {
-                if (five_waves_fit<MODE, true>(a.levels, waves_per_cu))
+                if (five_waves_fit<MODE, true>(a.levels, waves_per_cu, a.merge_slots))
                     return launch_persistent<MODE, true, true, false, 5>(a, num_cu, waves_per_cu, s, grid_waves);
                 return launch_persistent<MODE, true, true, false, 4>(a, num_cu, waves_per_cu, s, grid_waves);
             }
-            if (five_waves_fit<MODE, false>(a.levels, waves_per_cu))
+            if (five_waves_fit<MODE, false>(a.levels, waves_per_cu, a.merge_slots))
                 return launch_persistent<MODE, true, false, false, 5>(a, num_cu, waves_per_cu, s, grid_waves);
             return launch_persistent<MODE, true, false, false, 4>(a, num_cu, waves_per_cu, s, grid_waves);
         }
@@ -1428,11 +1484,11 @@ hipError_t launch_expand(const SearchArgs &a, int num_cu, hipStream_t s) {
     return launch_mode<kExpand>(a, num_cu, 0, s, nullptr);
 }
 
-int search_waves(int levels, int num_cu, int waves_per_cu, bool slim) {
-    int per_cu = slim ? blocks_per_cu<kCount, true, false, false, 4>(levels, waves_per_cu)
-                      : blocks_per_cu<kCount, false, false, false, 4>(levels, waves_per_cu);
-    if (slim && five_waves_fit<kCount, false>(levels, waves_per_cu))
-        per_cu = blocks_per_cu<kCount, true, false, false, 5>(levels, waves_per_cu);
+int search_waves(int levels, int num_cu, int waves_per_cu, bool slim, int merge_slots) {
+    int per_cu = slim ? blocks_per_cu<kCount, true, false, false, 4>(levels, waves_per_cu, merge_slots)
+                      : blocks_per_cu<kCount, false, false, false, 4>(levels, waves_per_cu, 0);
+    if (slim && five_waves_fit<kCount, false>(levels, waves_per_cu, merge_slots))
+        per_cu = blocks_per_cu<kCount, true, false, false, 5>(levels, waves_per_cu, merge_slots);
     return num_cu * per_cu * kWavesPerBlock;
 }
 
