@@ -217,6 +217,8 @@ struct LaunchCtx {
     gm::Mailbox *d_mail = nullptr;
     unsigned long long *d_idle_bits = nullptr;
     int32_t steal_slots = 0;
+    uint2 *d_parked = nullptr;     // parked task groups of the wavefronts (levels x 64 per wavefront)
+    size_t parked_cap = 0;         // in entries
     std::vector<Plan> h_plans;     // host copies (kept until the uploads complete)
     std::vector<gm::QCtl> h_qctl;
     std::vector<gm::StreamCtl> h_streams;
@@ -304,7 +306,8 @@ hipError_t ctx_create(LaunchCtx &c) {
 void ctx_destroy(LaunchCtx &c) {
     if (c.stream) (void)hipStreamSynchronize(c.stream);
     for (void *b : {static_cast<void *>(c.d_ctl), static_cast<void *>(c.d_plans), static_cast<void *>(c.d_qctl),
-                    static_cast<void *>(c.d_streams), static_cast<void *>(c.d_mail), static_cast<void *>(c.d_idle_bits)})
+                    static_cast<void *>(c.d_streams), static_cast<void *>(c.d_mail), static_cast<void *>(c.d_idle_bits),
+                    static_cast<void *>(c.d_parked)})
         if (b) (void)hipFree(b);
     if (c.ev0) (void)hipEventDestroy(c.ev0);
     if (c.ev1) (void)hipEventDestroy(c.ev1);
@@ -770,7 +773,28 @@ unsigned long long flush_for_cap(const gm_engine *e, uint64_t cap) {
 }
 
 // Mailboxes and idle bitmap for work stealing (allocated on first use).
+// Device memory where each wavefront parks the task groups of the levels below
+// the one it scatters: a.levels x 64 entries per wavefront that can be resident
+// (at most 32 per CU).  Grows with the deepest launch; kept in the context.
+gm_status attach_parked(gm_engine *e, LaunchCtx &c, SearchArgs &a) {
+    const int32_t waves = e->num_cu * 32;
+    const size_t need = static_cast<size_t>(waves) * static_cast<size_t>(std::max(a.levels, 1)) * gm::kWave;
+    if (need > c.parked_cap) {
+        if (c.d_parked) (void)hipFree(c.d_parked);
+        c.d_parked = nullptr;
+        c.parked_cap = 0;
+        if (hipMalloc(reinterpret_cast<void **>(&c.d_parked), need * sizeof(uint2)) != hipSuccess)
+            return e->fail(GM_ERR_NOMEM, "allocation of the parked task groups failed");
+        c.parked_cap = need;
+    }
+    a.parked = c.d_parked;
+    a.park_waves = waves;
+    return GM_OK;
+}
+
 gm_status attach_stealing(gm_engine *e, LaunchCtx &c, SearchArgs &a) {
+    gm_status st = attach_parked(e, c, a);
+    if (st) return st;
     a.mail = nullptr;
     a.idle_bits = nullptr;
     a.steal_slots = 0;

@@ -188,6 +188,10 @@ struct SearchArgs {
     int32_t measure_next;      // expansion: add the next level's size bound to ctl->measure
     int32_t merge_slots;       // LDS-staged intersection: staging entries per lane, 0 = off (slim
                                // layout only); a run of r candidates stages a list of n <= slots * r
+    // parked task groups: levels x 64 entries of 8 bytes per wavefront, for up to
+    // park_waves wavefronts (a launch never has more)
+    uint2 *parked;
+    int32_t park_waves;
 };
 
 // Candidate graph of one query (candidate.hip).  Positions follow the

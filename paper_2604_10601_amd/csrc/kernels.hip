@@ -168,19 +168,24 @@ __device__ __forceinline__ bool in_all_lists(const int32_t *__restrict__ col, ui
 // Per-wavefront stack in LDS (Sec. 5.1: S is |V(Q)| x warp width) for exactly k
 // levels (the launch sizes the dynamic LDS from the query).  Element (level i,
 // lane q) of a plane is at [i * 64 + q].  Two layouts:
-//   full (20 B per (level, lane)): the entry caches its vertex's id-sorted list
+//   full (12 B per (level, lane)): the entry caches its vertex's id-sorted list
 //     start and degree, so membership tests bisect N(w) with no extra load;
-//   slim (13 B): the entry keeps only its vertex and parent lane; membership
+//   slim (5 B): the entry keeps only its vertex and parent lane; membership
 //     tests bisect the label slice of N(w) in lcol (ids ascending within a
 //     label), whose bounds cost one 8-byte load per list but which is shorter
-//     than N(w).  Deep queries fit about twice as many wavefronts per CU.
+//     than N(w).
+// The task group of each parent lane (its candidate slice: start in lcol and
+// length << 8 | source level) is needed only while its level is the one being
+// scattered, so the current level's sits in two registers per lane, and a
+// descent parks it in the wavefront's area of device memory (Slice, 8 B per
+// (level, lane), one coalesced 512-byte store) until the backtrack that loads
+// it again.  That keeps 512 B per level out of LDS: a 32-vertex query's stack
+// takes 10.8 KB instead of 27 KB, so 14 wavefronts fit per CU instead of 5.
 struct WaveStack {
     int32_t *v;       // data vertex of the task at (level, lane)
     uint32_t *st;     // full: start of N(v) in col[] (ids ascending)
     uint32_t *dp;     // full: |N(v)| << 8 | lane of the parent entry at level - 1
     uint8_t *pid;     // slim: lane of the parent entry at level - 1
-    uint32_t *cs;     // parent lane's local candidate slice: start in lcol[]
-    uint32_t *cl;     //   ... length << 8 | level of its source list (0xff = no list)
     uint32_t *cur_j;  // per level: scatter cursor, offset in the current parent's slice
     uint32_t *cur_i;  //   ... current parent lane (64 = level exhausted)
     uint32_t *end_j;  // per level: end of the task range, offset in parent end_i's slice
@@ -189,8 +194,14 @@ struct WaveStack {
 };
 
 __host__ __device__ constexpr size_t stack_bytes(int levels, bool slim) {
-    return static_cast<size_t>(levels) * (kWave * (slim ? 13u : 20u) + 16u) + kWave;
+    return static_cast<size_t>(levels) * (kWave * (slim ? 5u : 12u) + 16u) + kWave;
 }
+
+// Task group of one parent lane at one level: cs = start of its candidate slice
+// in lcol, cl = slice length << 8 | the level of its source list (0xff: none).
+struct Slice {
+    uint32_t cs, cl;
+};
 
 template <bool SLIM>
 __device__ __forceinline__ WaveStack carve_stack(uint8_t *base, int levels) {
@@ -210,9 +221,8 @@ __device__ __forceinline__ WaveStack carve_stack(uint8_t *base, int levels) {
         S.pid = nullptr;
         p += 2 * plane;
     }
-    S.cs = reinterpret_cast<uint32_t *>(p);
-    S.cl = reinterpret_cast<uint32_t *>(p + plane);
-    uint32_t *lv = reinterpret_cast<uint32_t *>(p + 2 * plane);
+    p = base + (static_cast<size_t>(p - base) + 3u) / 4u * 4u;
+    uint32_t *lv = reinterpret_cast<uint32_t *>(p);
     S.cur_j = lv;
     S.cur_i = lv + levels;
     S.end_j = lv + 2 * levels;
@@ -252,6 +262,7 @@ struct Gen {
     uint32_t scanned;  // length of the label slice that is actually scanned
     uint32_t lookups;  // slice bounds read
     uint32_t bytes;    // device-memory bytes those reads requested
+    Slice sl;          // this lane's task group at the new level
 };
 
 // GenerateTask (Alg. 2): for every parent lane in F at level l-1, walk its chain
@@ -264,7 +275,7 @@ struct Gen {
 template <bool SLIM, bool CG = false>
 __device__ __forceinline__ Gen generate_tasks(WaveStack &S, const SearchArgs &a, PlanPtr P, int l, uint64_t F,
                                               uint32_t lane) {
-    Gen g{0u, 0u, 0u, 0u};
+    Gen g{0u, 0u, 0u, 0u, {0u, 0xffu}};
     uint32_t cs = 0, cl = 0xffu;
     if ((F >> lane) & 1ull) {
         const uint32_t bw = P->bwd[l];
@@ -322,8 +333,8 @@ __device__ __forceinline__ Gen generate_tasks(WaveStack &S, const SearchArgs &a,
         cs = best_a;
         cl = (best_n << 8) | best_j;
     }
-    S.cs[l * kWave + lane] = cs;
-    S.cl[l * kWave + lane] = cl;
+    g.sl.cs = cs;
+    g.sl.cl = cl;
     return g;
 }
 
@@ -336,13 +347,12 @@ __device__ __forceinline__ void open_level(WaveStack &S, int l, uint32_t lane) {
     }
 }
 
-// Unscattered tasks of this lane's task group at level l, given the level's
+// Unscattered tasks of this lane's task group (slice sl), given its level's
 // cursor (ci, cjo) and end (ei, ej).  Also returns the group's slice.
-__device__ __forceinline__ uint32_t remaining(const WaveStack &S, int l, uint32_t lane, uint32_t ci, uint32_t cjo,
-                                              uint32_t ei, uint32_t ej, uint32_t &cst, uint32_t &cln) {
-    const uint32_t cl = S.cl[(l) * kWave + (lane)];
-    cst = S.cs[(l) * kWave + (lane)];
-    cln = cl >> 8;
+__device__ __forceinline__ uint32_t remaining(Slice sl, uint32_t lane, uint32_t ci, uint32_t cjo, uint32_t ei,
+                                              uint32_t ej, uint32_t &cst, uint32_t &cln) {
+    cst = sl.cs;
+    cln = sl.cl >> 8;
     if (lane < ci || lane > ei) return 0u;
     const uint32_t lo = lane == ci ? cjo : 0u;
     const uint32_t hi = lane == ei ? (ej < cln ? ej : cln) : cln;
@@ -354,18 +364,20 @@ struct Round {
     uint32_t owner;  // parent lane of this lane's task
     int32_t v;       // candidate of this lane's task (valid if lane < ntask)
     uint32_t run;    // lanes [run & 0xff, run >> 8) hold this parent's tasks of the round (ascending ids)
+    uint32_t js;     // level of the backward neighbour whose list the candidate came from
 };
 
 // ScatterTask (Alg. 2) for the whole wavefront: hand the next <= 64 tasks of
 // level l to lanes 0..ntask-1 and advance the level's cursor.
-__device__ __forceinline__ Round scatter(WaveStack &S, const int32_t *__restrict__ lcol, int l, uint32_t lane) {
+__device__ __forceinline__ Round scatter(WaveStack &S, const int32_t *__restrict__ lcol, int l, uint32_t lane,
+                                        Slice sl) {
     Round r;
     const uint32_t ci = __builtin_amdgcn_readfirstlane(S.cur_i[l]);
     const uint32_t cjo = __builtin_amdgcn_readfirstlane(S.cur_j[l]);
     const uint32_t ei = __builtin_amdgcn_readfirstlane(S.end_i[l]);
     const uint32_t ej = __builtin_amdgcn_readfirstlane(S.end_j[l]);
     uint32_t cst, cln;
-    const uint32_t rem = remaining(S, l, lane, ci, cjo, ei, ej, cst, cln);
+    const uint32_t rem = remaining(sl, lane, ci, cjo, ei, ej, cst, cln);
     const uint32_t rc = rem < 64u ? rem : 64u;
     // exclusive scan of rc (values <= 64: seven bit planes)
     uint32_t ex = 0, tot = 0;
@@ -380,6 +392,7 @@ __device__ __forceinline__ Round scatter(WaveStack &S, const int32_t *__restrict
         r.owner = 0;
         r.v = -1;
         r.run = 0;
+        r.js = 0xffu;
         return r;
     }
     r.ntask = tot < 64u ? tot : 64u;
@@ -397,6 +410,7 @@ __device__ __forceinline__ Round scatter(WaveStack &S, const int32_t *__restrict
     r.run = s | ((e < r.ntask ? e : r.ntask) << 8);
     const uint32_t owner = shfl(o, s);
     const uint32_t ocst = shfl(cst, owner);
+    r.js = shfl(sl.cl, owner) & 0xffu;
     const uint32_t j = lane - s + (owner == ci ? cjo : 0u);
     r.owner = owner;
     r.v = lane < r.ntask ? lcol[ocst + j] : -1;
@@ -546,7 +560,7 @@ __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanP
         const uint32_t sblt = SB ? P->sb_lt[l] : 0u, sbgt = SB ? P->sb_gt[l] : 0u;
         // the backward neighbour whose list the candidate came from needs no
         // test; it is the same for every lane of a run
-        const uint32_t js = S.cl[l * kWave + r.owner] & 0xffu;
+        const uint32_t js = r.js;
         const uint32_t lab = a.loff_stride > 1 ? static_cast<uint32_t>(P->lab[l]) : 0u;
         uint32_t q = r.owner;
         for (int i = l - 1; i >= 0; --i) {
@@ -676,7 +690,8 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 // The thief takes over one work unit of query cq.  Returns the bytes this lane
 // wrote into the thief's mailbox (0 everywhere when nothing was handed over).
 template <bool SLIM>
-__device__ uint32_t donate(WaveStack &S, const SearchArgs &a, PlanPtr P, int32_t cq, int base, int l, uint32_t lane) {
+__device__ uint32_t donate(WaveStack &S, const SearchArgs &a, PlanPtr P, int32_t cq, int base, int l, uint32_t lane,
+                           Slice cur, const Slice *parked) {
     const int k = P->k;
     const int top = l < k - 2 ? l : k - 2;
     for (int L = base; L <= top; ++L) {
@@ -685,8 +700,10 @@ __device__ uint32_t donate(WaveStack &S, const SearchArgs &a, PlanPtr P, int32_t
         const uint32_t cjo = __builtin_amdgcn_readfirstlane(S.cur_j[L]);
         const uint32_t ei = __builtin_amdgcn_readfirstlane(S.end_i[L]);
         const uint32_t ej = __builtin_amdgcn_readfirstlane(S.end_j[L]);
+        // the level being scattered holds its task groups in registers; the others are parked
+        const Slice sl = L == l ? cur : parked[L * kWave + lane];
         uint32_t cst, cln;
-        const uint32_t rem = remaining(S, L, lane, ci, cjo, ei, ej, cst, cln);
+        const uint32_t rem = remaining(sl, lane, ci, cjo, ei, ej, cst, cln);
         const uint32_t incl = wave_incl_scan(rem);
         const uint32_t total = read_lane(incl, 63);
         if (total < static_cast<uint32_t>(a.steal_threshold)) continue;
@@ -702,7 +719,7 @@ __device__ uint32_t donate(WaveStack &S, const SearchArgs &a, PlanPtr P, int32_t
         const uint32_t excl_p = read_lane(excl, p);
         const uint32_t pj = (p == ci ? cjo : 0u) + (h - excl_p);
         Mailbox &mb = a.mail[thief];
-        const bool mine = lane >= p && lane <= ei && (S.cl[(L) * kWave + (lane)] & 0xffu) != 0xffu;
+        const bool mine = lane >= p && lane <= ei && (sl.cl & 0xffu) != 0xffu;
         const uint64_t lanes = ballot(mine);
         if (mine) {
             uint32_t q = lane;
@@ -789,9 +806,8 @@ __host__ __device__ constexpr size_t wave_lds_bytes(int levels, bool expand, boo
 
 // First phase of a two-phase pool: a root's position-1 task group keeps only
 // its first hub_cut tasks (the second phase holds the rest).
-__device__ __forceinline__ void first_phase_cut(WaveStack &S, PlanPtr P, uint32_t lane) {
-    const uint32_t cl = S.cl[kWave + lane];
-    if ((cl >> 8) > P->hub_cut) S.cl[kWave + lane] = (P->hub_cut << 8) | (cl & 0xffu);
+__device__ __forceinline__ void first_phase_cut(Slice &sl, PlanPtr P) {
+    if ((sl.cl >> 8) > P->hub_cut) sl.cl = (P->hub_cut << 8) | (sl.cl & 0xffu);
 }
 
 // Query that item t of a stream (queries p0 .. p1 - 1) belongs to: the current
@@ -903,6 +919,9 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
     Control *ctl = a.ctl;
     const bool stealing = a.mail != nullptr;
     const uint32_t wave_id = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    // this wavefront's parked task groups, one level per 64 entries
+    Slice *parked = reinterpret_cast<Slice *>(a.parked) + static_cast<size_t>(wave_id) * levels * kWave;
+    Slice cur{0u, 0xffu};  // task group of this lane at the level being scattered
 
     int32_t cq = 0;  // query of the wavefront's current work (wave-uniform)
     PlanPtr P = plan_at(a, 0);
@@ -978,12 +997,12 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                     t.bytes_run += SLIM ? 16u : 24u;  // root, its first task, slice start, candidate (+ record)
                 }
                 push_entry<SLIM>(S, 0, lane, root, rvi, lane);
-                S.cl[kWave + lane] = 0u;  // the candidate came from position 0's list
                 Round r1;
                 r1.ntask = ntask;
                 r1.owner = lane;
                 r1.v = v;
                 r1.run = lane | ((lane + 1u) << 8);  // every lane is its own root
+                r1.js = 0u;                          // the candidate came from position 0's list
                 VInfo vi;
                 const bool ok = process<SLIM, SB, CG>(S, a, P, 1, r1, lane, vi, t.probes_run, t.lookups_run,
                                                       t.bytes_run, marea);
@@ -1009,6 +1028,7 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                 lane0_add(&a.qctl[cq].live, 1);
                 push_entry<SLIM>(S, 1, lane, v, vi, lane);
                 const Gen g = generate_tasks<SLIM, CG>(S, a, P, 2, m, lane);
+                cur = g.sl;
                 t.tasks += g.tasks;
                 t.scanned += g.scanned;
                 t.lookups += g.lookups;
@@ -1045,9 +1065,10 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
             }
             lane0_add(&a.qctl[cq].live, 1);
             Gen g = generate_tasks<SLIM, CG>(S, a, P, d, F0, lane);
+            cur = g.sl;
             t.bytes_run += g.bytes;
             if (P->vmode) {  // first phase: each root's first hub_cut tasks only
-                first_phase_cut(S, P, lane);
+                first_phase_cut(cur, P);
                 g.scanned = g.scanned < P->hub_cut ? g.scanned : P->hub_cut;
             }
             t.tasks += g.tasks;
@@ -1121,9 +1142,11 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
             }
             t.bytes_run += mine ? 12u * static_cast<uint32_t>(L) : 0u;
             // the tasks and groups were counted by the donor; the reads are this wavefront's
-            t.bytes_run += generate_tasks<SLIM, CG>(S, a, P, L, lanes, lane).bytes;
+            const Gen gd = generate_tasks<SLIM, CG>(S, a, P, L, lanes, lane);
+            cur = gd.sl;
+            t.bytes_run += gd.bytes;
             // position 1 is donated only by first-phase items of a two-phase pool: keep their cut
-            if (P->vmode && L == 1) first_phase_cut(S, P, lane);
+            if (P->vmode && L == 1) first_phase_cut(cur, P);
             if (lane == 0) {
                 S.cur_i[L] = static_cast<uint32_t>(load_agent(&mb.pi));
                 S.cur_j[L] = static_cast<uint32_t>(load_agent(&mb.pj));
@@ -1144,9 +1167,12 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
         bool dropped = false;  // the query reached its cap or time limit: drop the rest of this unit
         int l = base;
         while (l >= base) {
-            const Round r = scatter(S, a.lcol, l, lane);
+            const Round r = scatter(S, a.lcol, l, lane, cur);
             if (r.ntask == 0) {
-                --l;
+                if (--l >= base) {  // back to the parked task groups of the level below
+                    cur = parked[l * kWave + lane];
+                    t.bytes_run += 8u;
+                }
                 continue;
             }
             t.active += r.ntask;
@@ -1199,7 +1225,10 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                 t.count += __popcll(m);
             } else if (m) {
                 push_entry<SLIM>(S, l, lane, r.v, vi, r.owner);
+                parked[l * kWave + lane] = cur;  // this level's task groups wait for the backtrack
                 const Gen g = generate_tasks<SLIM, CG>(S, a, P, l + 1, m, lane);
+                cur = g.sl;
+                t.bytes_run += 8u;
                 t.tasks += g.tasks;
                 t.scanned += g.scanned;
                 t.lookups += g.lookups;
@@ -1226,7 +1255,7 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                         int waiting = 0;
                         if (lane == 0) waiting = load_agent(&ctl->idle_count);
                         if (static_cast<int>(read_lane(static_cast<uint32_t>(waiting), 0)) > 0)
-                            t.bytes_run += donate<SLIM>(S, a, P, cq, base, l, lane);
+                            t.bytes_run += donate<SLIM>(S, a, P, cq, base, l, lane, cur, parked);
                     }
                     fold_run(t, stop || dropped);
                 }
@@ -1416,11 +1445,13 @@ hipError_t launch_persistent(const SearchArgs &a, int num_cu, int waves_per_cu, 
         return hipErrorInvalidValue;
     if (CG && (!a.gbounds || a.gn < 1)) return hipErrorInvalidValue;
     if (a.merge_slots < 0 || a.merge_slots > kMaxMergeSlots) return hipErrorInvalidValue;
+    if (!a.parked || a.park_waves < 1) return hipErrorInvalidValue;
     SearchArgs b = a;
     if (!SLIM) b.merge_slots = 0;  // the full layout bisects whole lists
     const size_t lds_bytes = wave_lds_bytes(b.levels, MODE == kExpand, SLIM, b.merge_slots) * kWavesPerBlock;
     int blocks = num_cu * blocks_per_cu<MODE, SLIM, SB, CG, OCC>(b.levels, waves_per_cu, b.merge_slots);
     if (a.mail && blocks * kWavesPerBlock > a.steal_slots) blocks = a.steal_slots / kWavesPerBlock;  // one mailbox each
+    if (blocks * kWavesPerBlock > a.park_waves) blocks = a.park_waves / kWavesPerBlock;  // one parking area each
     if (blocks < 1) blocks = 1;
     if (grid_waves) *grid_waves = blocks * kWavesPerBlock;
     hipLaunchKernelGGL((search_kernel<MODE, SLIM, SB, CG, OCC>), dim3(blocks), dim3(kBlock), lds_bytes, s, b);
@@ -1428,13 +1459,14 @@ hipError_t launch_persistent(const SearchArgs &a, int num_cu, int waves_per_cu, 
 }
 
 // The slim plain-graph kernels also exist with the register budget of five
-// wavefronts per SIMD.  Their spills cost more than the extra wavefront brings
-// where LDS cannot hold five stacks per SIMD anyway (queries of 10+ vertices),
-// so they run only where the occupancy calculator says they fit more.
+// wavefronts per SIMD.  Their spills cost more than one extra wavefront per CU
+// brings, so they run only where the occupancy calculator says they fit at
+// least an eighth more wavefronts than the four-wavefront build (LDS, not
+// registers, bounds residency for the deepest queries).
 template <int MODE, bool SB>
 bool five_waves_fit(int levels, int waves_per_cu, int slots) {
-    return blocks_per_cu<MODE, true, SB, false, 5>(levels, waves_per_cu, slots) >
-           blocks_per_cu<MODE, true, SB, false, 4>(levels, waves_per_cu, slots);
+    return blocks_per_cu<MODE, true, SB, false, 5>(levels, waves_per_cu, slots) * 8 >
+           blocks_per_cu<MODE, true, SB, false, 4>(levels, waves_per_cu, slots) * 9;
 }
 
 // One of the instantiations: mode x stack layout x symmetry conditions x
