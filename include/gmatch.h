@@ -291,6 +291,24 @@ typedef struct {
 gm_status gm_count_batch(gm_engine *engine, int32_t nq, const int32_t *qids, uint64_t cap, double time_limit_s,
                          gm_result *out, gm_batch_info *info);
 
+/* Count one query without allocating: for callers that cannot allocate device
+ * memory while they run (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same result as gm_count_batch on the one
+ * query qid (first-vertex candidates as the pool, cap and time limit as
+ * gm_count), with every device buffer of its launch in a fixed arena that the
+ * library holds on each GPU until the process ends: 64 MiB, a file-scope
+ * device array, looked up once per device when an engine is created on it.
+ * The call makes no hipMalloc, hipFree or other allocating call.  The arena
+ * holds the query's control blocks and, per wavefront, a stealing mailbox and
+ * the parked task groups of its levels; a launch uses at most as many
+ * wavefronts as fit (all resident ones up to 16-vertex queries, about 2,700 at
+ * 32 vertices), and GM_ERR_BUFFER is returned if not even one would fit.
+ * The arena keeps the last call's contents; each call clears what must start
+ * at zero.  Calls on one GPU share its arena, so calls that overlap on one GPU
+ * (two threads, two engines, or two servers) race: serialise them.  Returns
+ * GM_ERR_STATE with the candidate-graph option (its per-call build allocates). */
+gm_status gm_count_noalloc(gm_engine *engine, int32_t qid, uint64_t cap, double time_limit_s, gm_result *out);
+
 /* Settings chosen by gm_tune_batch. */
 typedef struct {
     int32_t waves_per_cu;        /* resident wavefronts per CU (0 = as many as fit) */

@@ -27,7 +27,7 @@ ABI_FUNCTIONS = ("gm_create", "gm_destroy", "gm_load_graph", "gm_load_graph_devi
                  "gm_serve_close", "gm_order_features", "gm_candidate_orders", "gm_model_create",
                  "gm_model_destroy", "gm_model_predict", "gm_model_train", "gm_model_get_params",
                  "gm_model_set_params", "gm_model_last_error", "gm_choose_order", "gm_set_symmetry_breaking", "gm_free_query",
-                 "gm_candidate_sets", "gm_last_error")
+                 "gm_candidate_sets", "gm_count_noalloc", "gm_last_error")
 
 ORDER_FEATURES = 192
 
@@ -236,6 +236,7 @@ def load_library():
     lib.gm_count.argtypes = [p, i32, u64, dbl, ctypes.POINTER(_CResult)]
     lib.gm_enumerate.argtypes = [p, i32, p, u64, dbl, ctypes.POINTER(_CResult)]
     lib.gm_count_batch.argtypes = [p, i32, p, u64, dbl, p, ctypes.POINTER(BatchInfo)]
+    lib.gm_count_noalloc.argtypes = [p, i32, u64, dbl, ctypes.POINTER(_CResult)]
     lib.gm_tune_batch.argtypes = [p, i32, p, u64, dbl, ctypes.POINTER(Tuning)]
     lib.gm_get_options.argtypes = [p, ctypes.POINTER(Options)]
     lib.gm_serve_open.argtypes = [p, ctypes.POINTER(ServeOptions), ctypes.POINTER(p)]
@@ -266,7 +267,7 @@ def load_library():
                  "gm_serve_submit", "gm_serve_poll", "gm_serve_stats", "gm_serve_close", "gm_order_features",
                  "gm_candidate_orders", "gm_model_create", "gm_model_predict", "gm_model_train",
                  "gm_model_get_params", "gm_model_set_params", "gm_choose_order", "gm_set_symmetry_breaking",
-                 "gm_free_query", "gm_candidate_sets"):
+                 "gm_free_query", "gm_candidate_sets", "gm_count_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -386,6 +387,12 @@ class Engine:
         self._check(self._lib.gm_enumerate(self._h, qid, _ptr(rows), int(cap), float(time_limit_s),
                                            ctypes.byref(r)))
         return self._result(r, rows[: int(r.rows)])
+
+    def count_noalloc(self, qid: int, cap: int = 0, time_limit_s: float = 0.0) -> Result:
+        """gm_count_noalloc: one query, no device allocation (the library's fixed arena)."""
+        r = _CResult()
+        self._check(self._lib.gm_count_noalloc(self._h, qid, int(cap), float(time_limit_s), ctypes.byref(r)))
+        return self._result(r)
 
     def count_batch(self, qids: Sequence[int], cap: int = 0, time_limit_s: float = 0.0):
         """Counts of several queries in shared launches: (list of Result, BatchInfo)."""

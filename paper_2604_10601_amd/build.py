@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgmatch.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "graph_build.hip", "candidate.hip", "order_model.hip",
-                                                     "engine.cpp")]
+                                                     "scratch.hip", "engine.cpp")]
 
 # Packed fp32 ops are switched off: some of their forms have misbehaved on this
 # hardware class, and nothing here needs them.

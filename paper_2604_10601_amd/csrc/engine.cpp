@@ -274,6 +274,7 @@ struct gm_engine {
            cmisc_cap = 0;
     std::vector<gm::CandEdge> h_cedges;
     LaunchCtx lc;                  // device state of the engine's own launches
+    void *scratch = nullptr;       // this device's arena for gm_count_noalloc (shared by its engines)
     std::atomic<int> servers{0};   // open servers (the graph must stay as it is)
     int num_cu = 0;
     long long wall_khz = 0;
@@ -1979,6 +1980,11 @@ gm_status gm_create(int32_t device, const gm_options *opt, gm_engine **out) {
         }
         e->num_cu = prop.multiProcessorCount;
         e->wall_khz = khz > 0 ? khz : 100000;
+        if ((h = gm::scratch_area(device, &e->scratch)) != hipSuccess) {
+            g_create_error = std::string("scratch arena lookup failed: ") + hipGetErrorString(h);
+            gm_destroy(e);
+            return GM_ERR_DEVICE;
+        }
     }
     *out = e;
     return GM_OK;
@@ -2226,6 +2232,128 @@ gm_status gm_count_batch(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t
     if (e->opt.candidate_graph)
         return e->fail(GM_ERR_STATE, "the candidate graph is built per query: use gm_count or gm_enumerate");
     return run_batch(e, nq, qids, cap, time_limit_s, out, info);
+}
+
+gm_status gm_count_noalloc(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_s, gm_result *out) {
+    if (!e) return GM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (!out) return e->fail(GM_ERR_ARG, "out is null");
+    const QueryRec *q = nullptr;
+    gm_status st = get_query(e, qid, &q);
+    if (st) return st;
+    if (!e->has_graph) return e->fail(GM_ERR_STATE, "no data graph loaded");
+    if (e->device < 0) return e->fail(GM_ERR_DEVICE, "host-only engine (created with device -1) cannot search");
+    if (e->opt.candidate_graph) return e->fail(GM_ERR_STATE, "the candidate graph is built per call; it allocates");
+    if (!e->scratch) return e->fail(GM_ERR_DEVICE, "no scratch arena on this device");
+    HIP_TRY(e, hipSetDevice(e->device));
+    const auto t_start = std::chrono::steady_clock::now();
+    std::memset(out, 0, sizeof(*out));
+    // the plan of gm_count_batch for one query: first-vertex candidates as the pool
+    bool missing = false;
+    Plan p = make_plan(e, *q, &missing);
+    p.cap = cap;
+    p.flush = flush_for_cap(e, cap);
+    p.depth = 1;
+    p.budget = time_limit_s > 0 ? std::max<unsigned long long>(1, static_cast<unsigned long long>(
+                                                                       time_limit_s * 1000.0 * static_cast<double>(e->wall_khz)))
+                                : 0ull;
+    if (!missing) root_share(e, p, &p.row0, &p.rows);
+    p.perm_mul = root_order(p.rows);
+    p.item0 = 0;
+    p.item_end = items_of(p.rows);
+    out->pool_depth = 1;
+    out->pool_rows = p.rows;
+    out->outcome = GM_DONE;
+    auto elapsed_ms = [&]() {
+        std::chrono::duration<double, std::milli> el = std::chrono::steady_clock::now() - t_start;
+        return el.count();
+    };
+    if (p.item_end == 0) {  // no candidate for the first query vertex: no match, no launch
+        out->search_ms = elapsed_ms();
+        return GM_OK;
+    }
+    // arena layout: control block, plan, result block, work stream, idle bitmap,
+    // then per wavefront a mailbox (with stealing) and its parked task groups
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const bool steal = e->opt.disable_stealing == 0;
+    const size_t off_plan = up(sizeof(Control));
+    const size_t off_qctl = off_plan + up(sizeof(Plan));
+    const size_t off_sc = off_qctl + up(sizeof(gm::QCtl));
+    const size_t off_idle = off_sc + up(sizeof(gm::StreamCtl));
+    const size_t max_waves = static_cast<size_t>(e->num_cu) * 32;
+    const size_t off_mail = off_idle + up((max_waves + 63) / 64 * sizeof(unsigned long long));
+    const size_t per_wave = (steal ? sizeof(gm::Mailbox) : 0) + static_cast<size_t>(p.k) * gm::kWave * sizeof(uint2);
+    if (off_mail + per_wave > gm::kScratchBytes)
+        return e->fail(GM_ERR_BUFFER, "the scratch arena (" + std::to_string(gm::kScratchBytes >> 20) +
+                                          " MiB) cannot hold the state of one wavefront");
+    const size_t fit = (gm::kScratchBytes - off_mail) / per_wave;
+    const int32_t waves = static_cast<int32_t>(std::min<size_t>({fit, max_waves}));
+    const size_t off_parked = up(off_mail + (steal ? static_cast<size_t>(waves) * sizeof(gm::Mailbox) : 0));
+    if (off_parked + static_cast<size_t>(waves) * p.k * gm::kWave * sizeof(uint2) > gm::kScratchBytes)
+        return e->fail(GM_ERR_BUFFER, "scratch arena layout overflow");
+    uint8_t *base = static_cast<uint8_t *>(e->scratch);
+    hipStream_t s = e->lc.stream;
+    gm::StreamCtl sc{};
+    sc.items = p.item_end;
+    sc.plan0 = 0;
+    sc.plan1 = 1;
+    // the previous call's contents stay in the arena: the counters start at zero
+    HIP_TRY(e, gm::launch_zero_words(base, off_idle / 4, s));
+    HIP_TRY(e, hipMemcpyAsync(base + off_plan, &p, sizeof(Plan), hipMemcpyHostToDevice, s));
+    HIP_TRY(e, hipMemcpyAsync(base + off_sc, &sc, sizeof(gm::StreamCtl), hipMemcpyHostToDevice, s));
+    SearchArgs a = graph_args(e, e->lc);
+    a.ctl = reinterpret_cast<Control *>(base);
+    a.plans = reinterpret_cast<Plan *>(base + off_plan);
+    a.qctl = reinterpret_cast<gm::QCtl *>(base + off_qctl);
+    a.streams = reinterpret_cast<gm::StreamCtl *>(base + off_sc);
+    a.nq = 1;
+    a.nstreams = 1;
+    a.levels = p.k;
+    a.pool = e->d_bylabel;
+    a.slim = use_slim(e, p.k) ? 1 : 0;
+    a.sb = has_sb(p) ? 1 : 0;
+    a.budget = 0;  // the limit is the query's own (plan budget)
+    a.steal_threshold = e->opt.steal_threshold > 0 ? e->opt.steal_threshold : 128;
+    a.mail = steal ? reinterpret_cast<gm::Mailbox *>(base + off_mail) : nullptr;
+    a.idle_bits = steal ? reinterpret_cast<unsigned long long *>(base + off_idle) : nullptr;
+    a.steal_slots = steal ? waves : 0;
+    a.parked = reinterpret_cast<uint2 *>(base + off_parked);
+    a.park_waves = waves;
+    if (steal) HIP_TRY(e, gm::launch_steal_init(a.mail, a.idle_bits, waves, s));
+    HIP_TRY(e, gm::launch_start_clock(a.ctl, s));
+    int grid_waves = 0;
+    HIP_TRY(e, hipEventRecord(e->lc.ev0, s));
+    HIP_TRY(e, gm::launch_search(a, false, e->num_cu, e->opt.waves_per_cu, s, &grid_waves));
+    HIP_TRY(e, hipEventRecord(e->lc.ev1, s));
+    gm::QCtl qc{};
+    Control c{};
+    HIP_TRY(e, hipMemcpyAsync(&qc, a.qctl, sizeof(gm::QCtl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(e, hipMemcpyAsync(&sc, a.streams, sizeof(gm::StreamCtl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(e, hipMemcpyAsync(&c, a.ctl, sizeof(Control), hipMemcpyDeviceToHost, s));
+    HIP_TRY(e, hipStreamSynchronize(s));
+    float kernel_ms = 0.f;
+    HIP_TRY(e, hipEventElapsedTime(&kernel_ms, e->lc.ev0, e->lc.ev1));
+    if (p.cap && qc.count >= p.cap) {
+        out->count = p.cap;
+        out->outcome = GM_CAPPED;
+    } else {
+        out->count = qc.count;
+        out->outcome = qc.abort != gm::kAbortTime && query_finished(p, qc, sc) ? GM_DONE : GM_TIMEOUT;
+    }
+    out->groups = out->kernel_groups = qc.groups;
+    out->tasks = out->kernel_tasks = qc.tasks;
+    out->lanes_active = qc.lanes_active;
+    out->lanes_issued = qc.lanes_issued;
+    out->probes = out->kernel_probes = qc.probes;
+    out->steals = qc.steals;
+    out->scanned = out->kernel_scanned = qc.scanned;
+    out->kernel_lookups = qc.lookups;
+    out->kernel_bytes = qc.bytes;
+    out->kernel_bytes_late = qc.bytes_late;
+    out->kernel_ms = kernel_ms;
+    out->grid_waves = grid_waves;
+    out->search_ms = elapsed_ms();
+    return GM_OK;
 }
 
 gm_status gm_tune_batch(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t cap, double time_limit_s,

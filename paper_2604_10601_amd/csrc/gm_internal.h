@@ -9,6 +9,7 @@
 namespace gm {
 
 constexpr int kMaxK = 32;  // largest query supported
+constexpr unsigned long long kScratchBytes = 64ull << 20;  // the allocation-free call's arena (per GPU)
 constexpr int kMaxMergeSlots = 8;      // LDS-staged intersection: largest staging entries per lane
 constexpr int kDefaultMergeSlots = 4;  // ... and the default (lists up to 4 x the run's candidates)
 constexpr int kWave = 64;  // CDNA wavefront width
@@ -271,6 +272,12 @@ hipError_t launch_level1(const int32_t *roots, int32_t R, unsigned long long per
 // Wavefronts a depth-first search launch for a query of `levels` positions keeps resident.
 int search_waves(int levels, int num_cu, int waves_per_cu, bool slim, int merge_slots);
 hipError_t launch_steal_init(Mailbox *mail, unsigned long long *idle_bits, int32_t n, hipStream_t s);
+
+// Allocation-free count (scratch.hip): device address of this device's
+// kScratchBytes arena (looked up once per device, which must be current), and
+// a kernel that zeroes words of it.
+hipError_t scratch_area(int device, void **out);
+hipError_t launch_zero_words(void *p, unsigned long long words, hipStream_t s);
 
 // Graph load (graph_build.hip).  Error bits of the checks:
 enum : unsigned int { kGraphBadRowPtr = 1, kGraphBadEntry = 2, kGraphBadDegree = 4, kGraphAsymmetric = 8 };
