@@ -181,6 +181,36 @@ def pmc_per_kernel(root: str, counter: str) -> dict:
     return out
 
 
+def summarize_pmc(root: str) -> str:
+    """Counters of a rocprofv3 --pmc run, summed over the search kernel's dispatches,
+    with the ratios used to read them: the fraction of wave-cycles spent waiting,
+    and instructions per wave."""
+    import csv
+    sums, dispatches, key = {}, {}, None
+    for path in _csvs(root, "counter_collection.csv"):
+        for row in csv.DictReader(open(path)):
+            k = kernel_key(row.get("Kernel_Name", ""))
+            if not k.startswith("search<"):
+                continue
+            key = k
+            name = row["Counter_Name"]
+            sums[name] = sums.get(name, 0.0) + float(row["Counter_Value"])
+            dispatches.setdefault(name, set()).add(row.get("Dispatch_Id", row.get("Correlation_Id", "")))
+    lines = [f"kernel: {key}", f"kernel_sha: {kernel_sha()}"]
+    for name in sorted(sums):
+        lines.append(f"{name}: {sums[name]:.0f}  (dispatches {len(dispatches[name])})")
+    if sums.get("SQ_WAVE_CYCLES"):
+        if "SQ_WAIT_ANY" in sums:
+            lines.append(f"wait_any_fraction: {sums['SQ_WAIT_ANY'] / sums['SQ_WAVE_CYCLES']:.4f}")
+        if "SQ_WAIT_INST_ANY" in sums:
+            lines.append(f"wait_inst_fraction: {sums['SQ_WAIT_INST_ANY'] / sums['SQ_WAVE_CYCLES']:.4f}")
+    if sums.get("SQ_WAVES"):
+        for name in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_LDS"):
+            if name in sums:
+                lines.append(f"{name.lower()}_per_wave: {sums[name] / sums['SQ_WAVES']:.0f}")
+    return "\n".join(lines)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -234,6 +264,7 @@ def main() -> int:
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB device-to-device (counter calibration)")
     ap.add_argument("--summarize-stats", metavar="DIR", help="print the kernel table of a rocprofv3 --stats run")
+    ap.add_argument("--summarize-pmc", metavar="DIR", help="print the search kernel's counters of a rocprofv3 --pmc run")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print HBM traffic per search launch from two rocprofv3 --pmc runs")
     ap.add_argument("--copy-bytes", type=int, default=0, help="size of the calibration copy in those runs")
@@ -241,6 +272,9 @@ def main() -> int:
 
     if args.summarize_stats:
         print(summarize_stats(args.summarize_stats))
+        return 0
+    if args.summarize_pmc:
+        print(summarize_pmc(args.summarize_pmc))
         return 0
     if args.summarize_traffic:
         fetch = pmc_per_kernel(args.summarize_traffic[0], "FETCH_SIZE")

@@ -131,7 +131,7 @@ typedef struct {
      * lanes and intersected there by merge path when n <= merge_ratio * r (it
      * must also fit the run's share of the staging buffer, 8 entries per lane);
      * longer lists are bisected in device memory by each lane (or answered by a
-     * hub bitmap).  0 = default 4, -1 = never stage. */
+     * hub bitmap).  0 = default 1, -1 = never stage. */
     int32_t merge_ratio;
     int32_t reserved[2];
 } gm_options;
@@ -328,7 +328,7 @@ typedef struct {
  * value before moving on: streams (queries in flight) over 1, 16, 64, 256;
  * wavefronts per CU over as-many-as-fit, 12, 8; stack layout (LDS bytes per
  * wavefront) slim, full; steal threshold 32, 128, 512; LDS staging of short
- * lists (merge_ratio: the staging buffer, 2, 4 or 8 entries per lane, or
+ * lists (merge_ratio: the staging buffer, 1, 2 or 4 entries per lane, or
  * none); launch grouping.  The
  * measure is the device time of the batch's launches.  The result stays in
  * the engine's options and is reported in *out.  Every setting must give the
@@ -353,8 +353,10 @@ gm_status gm_get_options(const gm_engine *engine, gm_options *out);
  * run on the GPU at the same time, each with its share of the wavefronts, so
  * requests that arrive while others run are admitted as soon as a slot frees
  * up and their work overlaps with the work in flight.  Admission is bounded by
- * slot memory: each slot holds at most max_batch plans and result blocks, and
- * its wavefronts' stacks are sized for its largest query.  Results come back
+ * memory: a launch holds at most max_batch requests, its wavefronts' LDS stacks
+ * are sized for its largest query, and the device memory of the launches in
+ * flight (plans, result blocks, stealing mailboxes and parked task groups)
+ * stays within memory_mib.  Results come back
  * through gm_serve_poll with their submit, start and completion times.
  * Each result equals what gm_count gives for the query with the same cap and
  * time limit (exact when it finishes; with GM_TIMEOUT a lower bound).
@@ -370,7 +372,16 @@ typedef struct {
     int32_t waves_per_cu;   /* wavefronts per CU of each launch; 0 = an equal share of what fits */
     int32_t batch_streams;  /* work-item streams per launch (queries in flight); 0 = the engine's */
     int64_t max_pending;    /* queued requests beyond which submit returns GM_ERR_BUFFER; 0 = no limit */
-    int32_t reserved[6];
+    /* Device memory for the working state of the launches in flight, in MiB;
+     * 0 = default 1024.  A launch's state is its requests' plans and result
+     * blocks and, for each of its wavefronts, a stealing mailbox and the parked
+     * task groups of as many levels as its largest query has.  A free slot
+     * admits the oldest requests while the launches in flight plus the new one
+     * fit; a request that does not fit waits (in order) for memory to free up,
+     * and one that could not fit even alone is refused by gm_serve_submit with
+     * GM_ERR_BUFFER. */
+    int64_t memory_mib;
+    int32_t reserved[4];
 } gm_serve_options;
 
 typedef struct {
@@ -381,6 +392,8 @@ typedef struct {
     double start_ms;        /* launch of its batch queued */
     double done_ms;         /* its batch's results read back */
     gm_result result;
+    int32_t status;         /* GM_OK, or the error that stopped its launch (result then invalid) */
+    int32_t reserved;
 } gm_serve_result;
 
 /* Start a server on an engine with a loaded graph.  opt may be NULL. */
@@ -396,6 +409,10 @@ gm_status gm_serve_submit(gm_server *server, int32_t qid, uint64_t cap, double t
  * *n_out receives the number written. */
 gm_status gm_serve_poll(gm_server *server, gm_serve_result *out, int32_t max_results, double wait_s,
                         int32_t *n_out);
+
+/* Device memory (bytes) of the working state a launch holding only query qid
+ * takes on this server: what admission charges a request that runs alone. */
+gm_status gm_serve_request_bytes(gm_server *server, int32_t qid, int64_t *bytes);
 
 /* Numbers of requests queued, running and finished-but-not-polled. */
 gm_status gm_serve_stats(gm_server *server, int64_t *pending, int64_t *running, int64_t *ready);

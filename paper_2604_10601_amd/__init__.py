@@ -24,7 +24,8 @@ GM_DONE, GM_CAPPED, GM_TIMEOUT = 0, 1, 2
 ABI_FUNCTIONS = ("gm_create", "gm_destroy", "gm_load_graph", "gm_load_graph_device", "gm_load_query", "gm_set_order",
                  "gm_get_order", "gm_count", "gm_enumerate", "gm_count_batch", "gm_tune_batch",
                  "gm_get_options", "gm_serve_open", "gm_serve_submit", "gm_serve_poll", "gm_serve_stats",
-                 "gm_serve_close", "gm_order_features", "gm_candidate_orders", "gm_model_create",
+                 "gm_serve_close", "gm_serve_request_bytes", "gm_order_features", "gm_candidate_orders",
+                 "gm_model_create",
                  "gm_model_destroy", "gm_model_predict", "gm_model_train", "gm_model_get_params",
                  "gm_model_set_params", "gm_model_last_error", "gm_choose_order", "gm_set_symmetry_breaking", "gm_free_query",
                  "gm_candidate_sets", "gm_count_noalloc", "gm_last_error")
@@ -137,7 +138,8 @@ class ServeOptions(ctypes.Structure):
         ("waves_per_cu", ctypes.c_int32),
         ("batch_streams", ctypes.c_int32),
         ("max_pending", ctypes.c_int64),
-        ("reserved", ctypes.c_int32 * 6),
+        ("memory_mib", ctypes.c_int64),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -184,6 +186,8 @@ class _CServeResult(ctypes.Structure):
         ("start_ms", ctypes.c_double),
         ("done_ms", ctypes.c_double),
         ("result", _CResult),
+        ("status", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -196,6 +200,7 @@ class ServeResult:
     start_ms: float
     done_ms: float
     result: "Result"
+    status: int = 0
 
     @property
     def latency_ms(self) -> float:
@@ -245,6 +250,7 @@ def load_library():
     lib.gm_serve_stats.argtypes = [p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_int64)]
     lib.gm_serve_close.argtypes = [p]
+    lib.gm_serve_request_bytes.argtypes = [p, i32, ctypes.POINTER(ctypes.c_int64)]
     lib.gm_order_features.argtypes = [p, i32, p, p]
     lib.gm_candidate_orders.argtypes = [p, i32, i32, u64, p, ctypes.POINTER(i32)]
     lib.gm_model_create.argtypes = [i32, i32, i32, u64, ctypes.POINTER(p)]
@@ -264,7 +270,8 @@ def load_library():
     lib.gm_last_error.restype = ctypes.c_char_p
     for name in ("gm_create", "gm_load_graph", "gm_load_graph_device", "gm_load_query", "gm_set_order", "gm_get_order", "gm_count",
                  "gm_enumerate", "gm_count_batch", "gm_tune_batch", "gm_get_options", "gm_serve_open",
-                 "gm_serve_submit", "gm_serve_poll", "gm_serve_stats", "gm_serve_close", "gm_order_features",
+                 "gm_serve_submit", "gm_serve_poll", "gm_serve_stats", "gm_serve_close", "gm_serve_request_bytes",
+                 "gm_order_features",
                  "gm_candidate_orders", "gm_model_create", "gm_model_predict", "gm_model_train",
                  "gm_model_get_params", "gm_model_set_params", "gm_choose_order", "gm_set_symmetry_breaking",
                  "gm_free_query", "gm_candidate_sets", "gm_count_noalloc"):
@@ -454,9 +461,9 @@ class Engine:
         return sets.astype(bool), edges.value, rounds.value
 
     def serve(self, slots: int = 0, max_batch: int = 0, waves_per_cu: int = 0, batch_streams: int = 0,
-              max_pending: int = 0) -> "Server":
+              max_pending: int = 0, memory_mib: int = 0) -> "Server":
         """Open a continuous-batching server on this engine's resident graph."""
-        return Server(self, slots, max_batch, waves_per_cu, batch_streams, max_pending)
+        return Server(self, slots, max_batch, waves_per_cu, batch_streams, max_pending, memory_mib)
 
     def free_query(self, qid: int) -> None:
         self._check(self._lib.gm_free_query(self._h, qid))
@@ -474,12 +481,13 @@ class Server:
     """Continuous batching over the engine's resident graph (gm_serve_*)."""
 
     def __init__(self, engine: Engine, slots: int = 0, max_batch: int = 0, waves_per_cu: int = 0,
-                 batch_streams: int = 0, max_pending: int = 0):
+                 batch_streams: int = 0, max_pending: int = 0, memory_mib: int = 0):
         self._engine = engine
         self._lib = engine._lib
         o = ServeOptions()
         o.slots, o.max_batch, o.waves_per_cu = slots, max_batch, waves_per_cu
         o.batch_streams, o.max_pending = batch_streams, max_pending
+        o.memory_mib = memory_mib
         h = ctypes.c_void_p()
         engine._check(self._lib.gm_serve_open(engine._h, ctypes.byref(o), ctypes.byref(h)))
         self._h = h
@@ -499,8 +507,14 @@ class Server:
         for i in range(n.value):
             r = self._buf[i]
             out.append(ServeResult(int(r.ticket), int(r.qid), int(r.slot), float(r.submit_ms), float(r.start_ms),
-                                   float(r.done_ms), Engine._result(r.result)))
+                                   float(r.done_ms), Engine._result(r.result), int(r.status)))
         return out
+
+    def request_bytes(self, qid: int) -> int:
+        """Launch-state bytes admission charges for qid running alone (gm_serve_request_bytes)."""
+        b = ctypes.c_int64()
+        self._engine._check(self._lib.gm_serve_request_bytes(self._h, qid, ctypes.byref(b)))
+        return b.value
 
     def stats(self):
         p, r, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()

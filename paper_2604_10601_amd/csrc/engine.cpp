@@ -1649,7 +1649,7 @@ gm_status run_tune(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t cap, 
         {&gm_options::waves_per_cu, {0, 12, 8}},
         {&gm_options::stack_layout, {2, 1}},
         {&gm_options::steal_threshold, {32, 128, 512}},
-        {&gm_options::merge_ratio, {-1, 2, 4, 8}},
+        {&gm_options::merge_ratio, {-1, 1, 2, 4}},
         {&gm_options::batch_single_launch, {0, 1}},
     };
     for (const Knob &kb : knobs) {
@@ -1800,6 +1800,7 @@ struct gm_server {
         LaunchCtx c;
         GroupLaunch gl;
         bool busy = false;
+        size_t bytes = 0;       // device memory of its launch's working state
         std::vector<Request> reqs;
         std::vector<Plan> plans;
         std::vector<int32_t> members;
@@ -1821,6 +1822,7 @@ struct gm_server {
     gm_status error = GM_OK;
     std::string err;
     std::thread worker;
+    size_t budget = 0;  // device memory of the launches in flight, in bytes
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
     double now_ms() const {
@@ -1831,8 +1833,27 @@ struct gm_server {
 
 namespace {
 
-// Results of a slot's finished (or empty) launch into the ready queue.
-void publish(gm_server *s, gm_server::Slot &sl, double done_ms, int32_t slot_id) {
+// Wavefronts of a slot's launch whose largest query has `levels` positions.
+int64_t slot_waves(const gm_server *s, int32_t levels) {
+    const gm_engine *e = s->e;
+    int32_t wpc = s->opt.waves_per_cu;
+    if (wpc <= 0)
+        wpc = std::max(1, residency(e, levels) / std::max(1, e->num_cu) / static_cast<int32_t>(s->slots.size()));
+    return static_cast<int64_t>(e->num_cu) * wpc;
+}
+
+// Device memory of a launch's working state: g requests (plan, result block,
+// work stream) and, per wavefront, a stealing mailbox and the parked task
+// groups of `levels` levels.
+size_t launch_state_bytes(const gm_server *s, size_t g, int32_t levels) {
+    const bool steal = s->e->opt.disable_stealing == 0;
+    const size_t per_wave = (steal ? sizeof(gm::Mailbox) : 0) + static_cast<size_t>(levels) * gm::kWave * sizeof(uint2);
+    return g * (sizeof(Plan) + sizeof(gm::QCtl) + sizeof(gm::StreamCtl)) +
+           static_cast<size_t>(slot_waves(s, levels)) * per_wave;
+}
+
+// Results of a slot's finished (or empty, or failed) launch into the ready queue.
+void publish(gm_server *s, gm_server::Slot &sl, double done_ms, int32_t slot_id, gm_status status = GM_OK) {
     for (size_t j = 0; j < sl.reqs.size(); ++j) {
         gm_serve_result r{};
         r.ticket = sl.reqs[j].ticket;
@@ -1843,11 +1864,25 @@ void publish(gm_server *s, gm_server::Slot &sl, double done_ms, int32_t slot_id)
         r.done_ms = done_ms;
         r.result = sl.res[j];
         r.result.search_ms = done_ms - sl.start_ms;
+        r.status = status;
         s->ready.push_back(r);
     }
     s->running -= static_cast<int64_t>(sl.reqs.size());
     sl.reqs.clear();
     sl.busy = false;
+    sl.bytes = 0;
+}
+
+// A request that never ran (the server failed before admitting it).
+void publish_unrun(gm_server *s, const gm_server::Request &q, gm_status status) {
+    gm_serve_result r{};
+    r.ticket = q.ticket;
+    r.qid = q.qid;
+    r.slot = -1;
+    r.submit_ms = q.submit_ms;
+    r.start_ms = r.done_ms = s->now_ms();
+    r.status = status;
+    s->ready.push_back(r);
 }
 
 void serve_loop(gm_server *s) {
@@ -1857,30 +1892,52 @@ void serve_loop(gm_server *s) {
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         bool progress = false;
-        // harvest finished launches
+        // harvest finished launches; a launch whose end event reports an error
+        // is finished too, and its requests come back with that error
         for (int32_t i = 0; i < nslots; ++i) {
             gm_server::Slot &sl = s->slots[i];
-            if (!sl.busy || hipEventQuery(sl.c.ev1) != hipSuccess) continue;
-            lk.unlock();
-            const gm_status st = harvest_group(e, sl.c, sl.gl, sl.res.data(), nullptr);
-            lk.lock();
+            if (!sl.busy) continue;
+            const hipError_t q = hipEventQuery(sl.c.ev1);
+            if (q == hipErrorNotReady) continue;
+            gm_status st = GM_OK;
+            if (q != hipSuccess) {
+                st = hip_fail(e, q, "server launch");
+            } else {
+                lk.unlock();
+                st = harvest_group(e, sl.c, sl.gl, sl.res.data(), nullptr);
+                lk.lock();
+            }
             if (st && !s->error) {
                 s->error = st;
                 s->err = e->last_error();
             }
-            publish(s, sl, s->now_ms(), i);
+            publish(s, sl, s->now_ms(), i, st);
             progress = true;
         }
         if (progress) s->ready_cv.notify_all();
-        // admit queued requests into free slots, oldest first
+        // admit queued requests into free slots, oldest first, while the working
+        // state of the launches in flight and of the new one fits the budget
         for (int32_t i = 0; i < nslots && !s->pending.empty() && !s->error; ++i) {
             gm_server::Slot &sl = s->slots[i];
             if (sl.busy) continue;
-            const size_t g = std::min<size_t>(s->pending.size(), static_cast<size_t>(s->opt.max_batch));
+            size_t inflight = 0;
+            for (const gm_server::Slot &x : s->slots) inflight += x.busy ? x.bytes : 0;
+            size_t g = 0, bytes = 0;
+            int32_t lv = 0;
+            while (g < s->pending.size() && g < static_cast<size_t>(s->opt.max_batch)) {
+                const int32_t next = std::max(lv, s->pending[g].plan.k);
+                const size_t b = launch_state_bytes(s, g + 1, next);
+                if (inflight + b > s->budget) break;
+                lv = next;
+                bytes = b;
+                ++g;
+            }
+            if (g == 0) break;  // the oldest request waits until launches in flight free memory
             sl.reqs.assign(s->pending.begin(), s->pending.begin() + static_cast<long>(g));
             s->pending.erase(s->pending.begin(), s->pending.begin() + static_cast<long>(g));
             s->running += static_cast<int64_t>(g);
             sl.busy = true;
+            sl.bytes = bytes;
             sl.start_ms = s->now_ms();
             lk.unlock();
             sl.plans.resize(g);
@@ -1896,8 +1953,7 @@ void serve_loop(gm_server *s) {
                 r.pool_rows = sl.plans[j].rows;
                 r.outcome = GM_DONE;
             }
-            int32_t wpc = s->opt.waves_per_cu;
-            if (wpc <= 0) wpc = std::max(1, residency(e, levels) / std::max(1, e->num_cu) / nslots);
+            const int32_t wpc = static_cast<int32_t>(slot_waves(s, levels) / std::max(1, e->num_cu));
             const int32_t streams = s->opt.batch_streams > 0 ? s->opt.batch_streams : batch_streams(e);
             const gm_status st = launch_group(e, sl.c, sl.plans, sl.members.data(), static_cast<int32_t>(g), streams,
                                               wpc, sl.gl);
@@ -1907,7 +1963,7 @@ void serve_loop(gm_server *s) {
                 s->err = e->last_error();
             }
             if (st || !sl.gl.launched) {  // nothing to run (or a failure): results as they stand
-                publish(s, sl, s->now_ms(), i);
+                publish(s, sl, s->now_ms(), i, st);
                 s->ready_cv.notify_all();
             }
             progress = true;
@@ -1915,8 +1971,12 @@ void serve_loop(gm_server *s) {
         bool busy = false;
         for (const gm_server::Slot &sl : s->slots) busy |= sl.busy;
         if (s->stop && s->pending.empty() && !busy) break;
-        if (s->error && !busy) {  // fail what is still queued
-            while (!s->pending.empty()) s->pending.pop_front();
+        if (s->error && !busy) {  // what is still queued comes back with the error
+            while (!s->pending.empty()) {
+                publish_unrun(s, s->pending.front(), s->error);
+                s->pending.pop_front();
+            }
+            s->ready_cv.notify_all();
             if (s->stop) break;
         }
         if (!progress) {
@@ -2413,7 +2473,7 @@ gm_status gm_serve_open(gm_engine *e, const gm_serve_options *opt, gm_server **o
     gm_serve_options o{};
     if (opt) o = *opt;
     if (o.slots < 0 || o.slots > 16 || o.max_batch < 0 || o.waves_per_cu < 0 || o.batch_streams < 0 ||
-        o.max_pending < 0)
+        o.max_pending < 0 || o.memory_mib < 0)
         return e->fail(GM_ERR_ARG, "serve option out of range");
     if (!e->has_graph) return e->fail(GM_ERR_STATE, "no data graph loaded");
     if (e->device < 0) return e->fail(GM_ERR_DEVICE, "host-only engine (created with device -1) cannot serve");
@@ -2426,6 +2486,7 @@ gm_status gm_serve_open(gm_engine *e, const gm_serve_options *opt, gm_server **o
     if (!s) return e->fail(GM_ERR_NOMEM, "out of host memory");
     s->e = e;
     s->opt = o;
+    s->budget = static_cast<size_t>(o.memory_mib > 0 ? o.memory_mib : 1024) << 20;
     s->slots.resize(static_cast<size_t>(o.slots));
     for (gm_server::Slot &sl : s->slots) {
         const hipError_t h = ctx_create(sl.c);
@@ -2463,6 +2524,11 @@ gm_status gm_serve_submit(gm_server *s, int32_t qid, uint64_t cap, double time_l
         if (!missing) root_share(e, p, &p.row0, &p.rows);
         p.perm_mul = root_order(p.rows);
         r.plan = p;
+        const size_t need = launch_state_bytes(s, 1, p.k);
+        if (need > s->budget)
+            return e->fail(GM_ERR_BUFFER, "request needs " + std::to_string(need >> 20) + " MiB of launch state, "
+                                              "more than the server's memory budget of " +
+                                              std::to_string(s->budget >> 20) + " MiB");
     }
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -2491,6 +2557,18 @@ gm_status gm_serve_poll(gm_server *s, gm_serve_result *out, int32_t max_results,
     }
     *n_out = n;
     if (s->error && n == 0) return s->e->fail(s->error, "server failed: " + s->err);
+    return GM_OK;
+}
+
+gm_status gm_serve_request_bytes(gm_server *s, int32_t qid, int64_t *bytes) {
+    if (!s) return GM_ERR_ARG;
+    gm_engine *e = s->e;
+    if (!bytes) return e->fail(GM_ERR_ARG, "bytes is null");
+    std::lock_guard<std::mutex> lk(e->mu);
+    const QueryRec *q = nullptr;
+    gm_status st = get_query(e, qid, &q);
+    if (st) return st;
+    *bytes = static_cast<int64_t>(launch_state_bytes(s, 1, q->k));
     return GM_OK;
 }
 

@@ -11,7 +11,7 @@ namespace gm {
 constexpr int kMaxK = 32;  // largest query supported
 constexpr unsigned long long kScratchBytes = 64ull << 20;  // the allocation-free call's arena (per GPU)
 constexpr int kMaxMergeSlots = 8;      // LDS-staged intersection: largest staging entries per lane
-constexpr int kDefaultMergeSlots = 4;  // ... and the default (lists up to 4 x the run's candidates)
+constexpr int kDefaultMergeSlots = 1;  // ... and the default (lists no longer than the run of candidates)
 constexpr int kWave = 64;  // CDNA wavefront width
 
 // Packed per-vertex record, one 8-byte load per candidate:

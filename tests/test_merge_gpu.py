@@ -4,7 +4,7 @@ A list is staged in LDS and intersected by merge path when it is short against
 the run of candidates testing it (n <= merge_ratio x the run's lanes); longer
 lists are bisected in device memory.  Counts, outcomes and the paper's work
 counters (groups, tasks) must not depend on that choice: every case runs with
-staging never (-1), by default (0 = 4 entries per lane) and at the largest
+staging never (-1), by default (0 = 1 entry per lane) and at the largest
 buffer (8), with hub bitmaps on and off, and matches the oracle.
 """
 import sys

@@ -8,6 +8,7 @@ import time
 import numpy as np
 import pytest
 
+import oracle
 import paper_2604_10601_amd as gm
 from paper_2604_10601_amd import workloads as wl
 from tests.test_batch_gpu import mixed_er_case, rmat16_case, union
@@ -82,11 +83,23 @@ def test_results_equal_alone_with_arrivals_during_work(slots, max_batch):
             got = drain(srv, tickets)
             assert srv.stats() == (0, 0, 0)
         alone = {}
+        exact = {}
         for t, req in tickets.items():
             r = got[t]
+            assert r.status == gm.GM_OK
             assert r.qid == req[0] and 0 <= r.slot < slots
             assert r.submit_ms <= r.start_ms + 1e-6 <= r.done_ms + 2e-6
             check_same(e, req, r, alone)
+            # the ER part's queries finish: every finished result equals the oracle's
+            i = qids.index(req[0])
+            if i < n_light and r.result.outcome == gm.GM_DONE:
+                key = (req[0], req[1])
+                if key not in exact:
+                    exact[key] = oracle.count(g, qs[i], order=e.get_order(req[0]), cap=req[1])
+                o = exact[key]
+                assert (r.result.count, r.result.outcome, r.result.groups, r.result.tasks) == \
+                    (o.count, o.outcome, o.groups, o.tasks), key
+        assert len(exact) >= 5
 
 
 def test_time_limits_in_the_mix():
@@ -142,3 +155,36 @@ def test_engine_state_while_serving_and_close_drains():
         e.load(g)                                    # allowed again
         with pytest.raises(gm.GmError):
             e.serve(slots=99)
+
+
+def test_admission_by_memory():
+    """A request that fits the memory budget alone but not beside a launch in
+    flight waits for that launch to end although a slot is free; one that
+    cannot fit even alone is refused at submit."""
+    g, qs, n_light = mixed_graph()
+    with gm.Engine(device=0) as e:
+        e.load(g)
+        qids = [e.add(q) for q in qs]
+        heavy = [qid for qid, q in zip(qids[n_light:], qs[n_light:]) if q.k >= 16][0]
+        with e.serve(slots=2, max_batch=1, memory_mib=1) as small:
+            need = small.request_bytes(heavy)
+            assert need > (1 << 20)
+            with pytest.raises(gm.GmError) as ei:
+                small.submit(heavy)
+            assert ei.value.status == gm.GM_ERR_BUFFER
+        budget_mib = (need * 3 // 2) >> 20   # one such launch fits, two do not
+        assert need <= budget_mib << 20 < 2 * need
+        with e.serve(slots=2, max_batch=1, memory_mib=budget_mib) as srv:
+            assert srv.request_bytes(heavy) == need
+            t1 = srv.submit(heavy, time_limit_s=0.3)
+            t2 = srv.submit(heavy, time_limit_s=0.3)
+            t3 = srv.submit(qids[0], cap=1000)    # light, but queued behind t2 (oldest first)
+            got = drain(srv, {t1, t2, t3})
+        r1, r2, r3 = got[t1], got[t2], got[t3]
+        assert all(r.status == gm.GM_OK for r in (r1, r2, r3))
+        assert r2.start_ms >= r1.done_ms - 1e-3, (r1.done_ms, r2.start_ms)
+        assert r3.start_ms >= r1.done_ms - 1e-3
+        for r in (r1, r2):
+            assert r.result.outcome in (gm.GM_TIMEOUT, gm.GM_DONE, gm.GM_CAPPED)
+        a = e.count(qids[0], cap=1000)
+        assert (r3.result.count, r3.result.outcome) == (a.count, a.outcome)
