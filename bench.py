@@ -216,14 +216,14 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--train-queries", type=int, default=6250,
-                    help="learned: training queries per run (8 candidate orders each, half on each graph)")
+    ap.add_argument("--train-queries", type=int, default=3126,
+                    help="learned: training queries (4 candidate orders x 4 splits each, half on each graph)")
     ap.add_argument("--eval-queries", type=int, default=1000, help="learned: held-out queries")
     ap.add_argument("--eval-scale", type=int, default=24, choices=[20, 22, 24], help="learned: held-out graph")
     ap.add_argument("--train-cap", type=int, default=1_000_000, help="learned: cap of the training runs")
     ap.add_argument("--train-limit", type=float, default=0.05, help="learned: time limit of the training runs (s)")
-    ap.add_argument("--eval-cap", type=int, default=1_000_000, help="learned: cap of the evaluation runs")
-    ap.add_argument("--eval-limit", type=float, default=1.0, help="learned: time limit of the evaluation runs (s)")
+    ap.add_argument("--eval-cap", type=int, default=100_000_000, help="learned: cap of the evaluation runs")
+    ap.add_argument("--eval-limit", type=float, default=2.0, help="learned: time limit of the evaluation runs (s)")
     ap.add_argument("--workload", default="large",
                     choices=["medium", "small", "large", "batch", "serve", "learned", "cg"],
                     help="batch = 10,000 mixed-size queries in shared launches (autotuned); "
@@ -651,13 +651,16 @@ def bench_serve(args, gm) -> int:
 
 
 def bench_learned(args, gm) -> int:
-    """Learned matching order: (query, order) search times measured by the engine
-    on R-MAT scale-20 and scale-22 graphs train the cost model; held-out queries
-    on a larger graph then run with the heuristic order and with the order the
-    model picks.  Counts must not change; total time and p99 are compared."""
+    """Learned plan (matching order and task split): (query, order, split) search
+    times measured by the engine on R-MAT scale-20 and scale-22 graphs train the
+    cost model; held-out queries on the scale-24 graph then run with the
+    heuristic plan (RI order, default split) and with the plan the model picks,
+    one query at a time (gm_count) and all together in batched launches
+    (gm_count_batch, where the order matters and the split does not).  Counts
+    must not change; total time, p50 and p99 are compared."""
     from paper_2604_10601_amd import workloads as wl
-    # training runs: a bad random order only needs to be seen as slow, so a short limit
-    train_cap, train_limit, cap, limit, n_orders = args.train_cap, args.train_limit, args.eval_cap, args.eval_limit, 8
+    train_cap, train_limit, cap, limit = args.train_cap, args.train_limit, args.eval_cap, args.eval_limit
+    n_orders, splits = 4, (8, 16, 32, 64)
     xs, ys = [], []
     half = max(1, args.train_queries // 2)
     for scale, seed in ((20, 60), (22, 61)):
@@ -672,11 +675,13 @@ def bench_learned(args, gm) -> int:
                 qid = e.add(q)
                 for o in e.candidate_orders(qid, max_orders=n_orders, seed=i):
                     e.set_order(qid, o)
-                    r = e.count(qid, cap=train_cap, time_limit_s=train_limit)
-                    xs.append(e.order_features(qid))
-                    ys.append(np.log2(max(r.search_ms, 1e-3)))
+                    for sp in splits:
+                        e.set_split(qid, sp)
+                        r = e.count(qid, cap=train_cap, time_limit_s=train_limit)
+                        xs.append(e.order_features(qid))
+                        ys.append(np.log2(max(r.search_ms, 1e-3)))
                 e.free_query(qid)
-                if (i + 1) % 25 == 0:
+                if (i + 1) % 250 == 0:
                     log(f"  scale {scale}: {i + 1} queries, {len(ys)} samples ({time.time() - t:.0f} s)")
         del g
     x = np.stack(xs).astype(np.float32)
@@ -697,33 +702,64 @@ def bench_learned(args, gm) -> int:
     g = {20: wl.rmat20_graph, 22: wl.rmat22_graph, 24: wl.rmat24_graph}[args.eval_scale]()
     qs = wl.walk_queries(g, wl.order_sizes(args.eval_queries, 62), 62)
     log(f"evaluation graph scale {args.eval_scale}: |E|={g.num_edges}, {len(qs)} queries ({time.time() - t:.1f} s)")
-    plain, learned, chosen, same = [], [], 0, True
+    plain, learned, other_order, other_split, same = [], [], 0, 0, True
     with gm.Engine(device=0) as e:
         e.load(g)
-        for i, q in enumerate(qs):
-            qid = e.add(q)
-            heuristic = e.get_order(qid)
-            c, _ = e.choose_order(model, qid, max_orders=n_orders, seed=i, margin=0.25)
-            mine = e.get_order(qid)
-            # alternate which order runs first, so neither gains from the other's warm caches
+        qids = [e.add(q) for q in qs]
+        heuristic = {}
+        mine = {}
+        for i, qid in enumerate(qids):
+            heuristic[qid] = (e.get_order(qid), e.get_split(qid))
+            co, cs, _ = e.choose_plan(model, qid, splits=splits, max_orders=n_orders, seed=i, margin=0.25)
+            mine[qid] = (e.get_order(qid), e.get_split(qid))
+            other_order += co != 0
+            other_split += cs != heuristic[qid][1]
+
+        def use(qid, plan):
+            e.set_order(qid, plan[0])
+            e.set_split(qid, plan[1])
+
+        # one query at a time; alternate which plan runs first (neither gains from warm caches)
+        for i, qid in enumerate(qids):
             runs = {}
             for which in (("h", "l") if i % 2 == 0 else ("l", "h")):
-                e.set_order(qid, heuristic if which == "h" else mine)
+                use(qid, heuristic[qid] if which == "h" else mine[qid])
                 runs[which] = e.count(qid, cap=cap, time_limit_s=limit)
             a, b = runs["h"], runs["l"]
-            chosen += c != 0
             if a.outcome != gm.GM_TIMEOUT and b.outcome != gm.GM_TIMEOUT:
                 same &= (a.count, a.outcome) == (b.count, b.outcome)
             plain.append(a)
             learned.append(b)
-            e.free_query(qid)
-            if (i + 1) % 25 == 0:
-                log(f"  evaluated {i + 1} queries ({time.time() - t:.0f} s)")
+            if (i + 1) % 250 == 0:
+                log(f"  evaluated {i + 1} queries one at a time ({time.time() - t:.0f} s)")
+        # batched launches: every query in one gm_count_batch call per plan, twice each, alternating
+        batched = {"h": [], "l": []}
+        for rep in range(2):
+            for which in (("h", "l") if rep == 0 else ("l", "h")):
+                for qid in qids:
+                    use(qid, heuristic[qid] if which == "h" else mine[qid])
+                t0 = time.perf_counter()
+                res, info = e.count_batch(qids, cap=cap, time_limit_s=limit)
+                batched[which].append((time.perf_counter() - t0, info, res))
+        bh, bl = batched["h"][-1][2], batched["l"][-1][2]
+        same_batched = all((a.count, a.outcome) == (b.count, b.outcome) for a, b in zip(bh, bl)
+                           if a.outcome != gm.GM_TIMEOUT and b.outcome != gm.GM_TIMEOUT)
+        same_batched &= all((a.count, a.outcome) == (b.count, b.outcome) for a, b in zip(bh, plain)
+                            if a.outcome != gm.GM_TIMEOUT and b.outcome != gm.GM_TIMEOUT)
     model.close()
     lp = np.array([r.search_ms for r in plain])
     ll = np.array([r.search_ms for r in learned])
+
+    def batch_summary(which):
+        walls = [w for w, _, _ in batched[which]]
+        res = batched[which][-1][2]
+        qms = np.array([r.query_ms for r in res])
+        return {"wall_ms": 1000.0 * float(min(walls)), "kernel_ms": float(min(i.kernel_ms for _, i, _ in batched[which])),
+                "query_p50_ms": float(np.percentile(qms, 50)), "query_p99_ms": float(np.percentile(qms, 99)),
+                "timeouts": int(sum(r.outcome == gm.GM_TIMEOUT for r in res))}
+
     out = {
-        "metric": "query-set time (ms), learned vs heuristic order",
+        "metric": "query-set time (ms), learned vs heuristic plan",
         "value": float(ll.sum()),
         "unit": "ms",
         "n_gpus": 1,
@@ -735,17 +771,18 @@ def bench_learned(args, gm) -> int:
         "vs_baseline": None,
         "dtype": "int32 search, bf16/fp32 model",
         "data": "synthetic",
-        "config": {"workload": f"learned order: train R-MAT 20+22, evaluate R-MAT {args.eval_scale}",
-                   "train_queries": 2 * half, "orders_per_query": n_orders, "samples": int(len(y)),
-                   "train_cap": train_cap, "train_time_limit_s": train_limit, "eval_queries": len(qs), "cap": cap,
-                   "time_limit_s": limit, "margin_log2": 0.25},
+        "config": {"workload": f"learned plan: train R-MAT 20+22, evaluate R-MAT {args.eval_scale}",
+                   "train_queries": 2 * half, "orders_per_query": n_orders, "splits": list(splits),
+                   "samples": int(len(y)), "train_cap": train_cap, "train_time_limit_s": train_limit,
+                   "eval_queries": len(qs), "cap": cap, "time_limit_s": limit, "margin_log2": 0.25},
         "heuristic": {"total_ms": float(lp.sum()), "p50_ms": float(np.percentile(lp, 50)),
                       "p99_ms": float(np.percentile(lp, 99)),
                       "timeouts": int(sum(r.outcome == gm.GM_TIMEOUT for r in plain))},
         "learned": {"total_ms": float(ll.sum()), "p50_ms": float(np.percentile(ll, 50)),
                     "p99_ms": float(np.percentile(ll, 99)),
                     "timeouts": int(sum(r.outcome == gm.GM_TIMEOUT for r in learned)),
-                    "queries_with_another_order": int(chosen)},
+                    "queries_with_another_order": int(other_order), "queries_with_another_split": int(other_split)},
+        "batched": {"heuristic": batch_summary("h"), "learned": batch_summary("l"), "same_counts": bool(same_batched)},
         "model": {"train_mse": loss, "heldout_mse": val_mse, "target_variance": float(np.var(y))},
         "same_counts": bool(same),
     }

@@ -170,6 +170,8 @@ typedef struct {
                                 this query: every load it issued (list entries, vertex records,
                                 slice bounds, bisection and tail probes, bitmap words, pool rows)
                                 and every row it wrote, counted where issued */
+    double query_ms;         /* batched launches: device time from the query's first work item to
+                                the last time a wavefront reported work on it (0 elsewhere) */
     uint64_t kernel_bytes_late; /* part of kernel_bytes from the last 32-round window of each
                                 wavefront that saw the cap or time limit: an upper bound on the
                                 bytes spent after the query was decided */
@@ -486,6 +488,28 @@ const char *gm_model_last_error(const gm_model *model);
  * predictions. */
 gm_status gm_choose_order(gm_engine *engine, gm_model *model, int32_t qid, int32_t max_orders, uint64_t seed,
                           float margin, int32_t *chosen, float *predicted);
+
+/* Task split of query qid's initial pool (Sec. 4.3 splits the search into
+ * tasks before the depth-first phase): with the default two-phase pool, the
+ * number of a first-vertex candidate's position-1 tasks that stay with it in
+ * its first-phase work item; the rest of them become second-phase items of 64
+ * tasks that any wavefront can take.  0 = the engine's pool_hub_cut (default
+ * 16).  Counts do not depend on it.  GM_ERR_ARG outside [0, 2^24]. */
+gm_status gm_set_split(gm_engine *engine, int32_t qid, int32_t split);
+/* The split a count of qid uses now (its own, else the engine's). */
+gm_status gm_get_split(const gm_engine *engine, int32_t qid, int32_t *split);
+
+/* Let the model pick query qid's plan: its matching order among
+ * gm_candidate_orders(max_orders, seed) and its task split among
+ * splits[nsplits].  Candidate 0 is the heuristic order with the current split;
+ * then every (order, split) pair in order-major order.  The candidate
+ * predicted cheapest is set if it beats candidate 0's prediction by more than
+ * `margin` (log2 units), else candidate 0 stays.  *chosen_order receives the
+ * order's index (0 = heuristic), *chosen_split the split, and
+ * predicted[1 + orders * nsplits] (may be NULL) the predictions. */
+gm_status gm_choose_plan(gm_engine *engine, gm_model *model, int32_t qid, int32_t max_orders, uint64_t seed,
+                         const int32_t *splits, int32_t nsplits, float margin, int32_t *chosen_order,
+                         int32_t *chosen_split, float *predicted);
 
 /* Opt-in symmetry breaking.  By default every injective map is counted (Def.
  * 1).  The paper's comparison runs give all systems the same symmetry-breaking

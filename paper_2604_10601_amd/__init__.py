@@ -28,7 +28,8 @@ ABI_FUNCTIONS = ("gm_create", "gm_destroy", "gm_load_graph", "gm_load_graph_devi
                  "gm_model_create",
                  "gm_model_destroy", "gm_model_predict", "gm_model_train", "gm_model_get_params",
                  "gm_model_set_params", "gm_model_last_error", "gm_choose_order", "gm_set_symmetry_breaking", "gm_free_query",
-                 "gm_candidate_sets", "gm_count_noalloc", "gm_last_error")
+                 "gm_candidate_sets", "gm_count_noalloc", "gm_set_split", "gm_get_split",
+                 "gm_choose_plan", "gm_last_error")
 
 ORDER_FEATURES = 192
 
@@ -127,6 +128,7 @@ class _CResult(ctypes.Structure):
         ("candidate_ms", ctypes.c_double),
         ("candidate_edges", ctypes.c_uint64),
         ("kernel_bytes", ctypes.c_uint64),
+        ("query_ms", ctypes.c_double),
         ("kernel_bytes_late", ctypes.c_uint64),
     ]
 
@@ -171,6 +173,7 @@ class Result:
     candidate_edges: int = 0
     kernel_bytes: int = 0
     kernel_bytes_late: int = 0
+    query_ms: float = 0.0
 
     @property
     def idle_rate(self) -> float:
@@ -264,6 +267,10 @@ def load_library():
     lib.gm_model_last_error.restype = ctypes.c_char_p
     lib.gm_choose_order.argtypes = [p, p, i32, i32, u64, ctypes.c_float, ctypes.POINTER(i32), p]
     lib.gm_set_symmetry_breaking.argtypes = [p, i32, i32, ctypes.POINTER(u64)]
+    lib.gm_set_split.argtypes = [p, i32, i32]
+    lib.gm_get_split.argtypes = [p, i32, ctypes.POINTER(i32)]
+    lib.gm_choose_plan.argtypes = [p, p, i32, i32, u64, p, i32, ctypes.c_float, ctypes.POINTER(i32),
+                                   ctypes.POINTER(i32), p]
     lib.gm_free_query.argtypes = [p, i32]
     lib.gm_candidate_sets.argtypes = [p, i32, p, ctypes.POINTER(u64), ctypes.POINTER(i32)]
     lib.gm_last_error.argtypes = [p]
@@ -274,7 +281,8 @@ def load_library():
                  "gm_order_features",
                  "gm_candidate_orders", "gm_model_create", "gm_model_predict", "gm_model_train",
                  "gm_model_get_params", "gm_model_set_params", "gm_choose_order", "gm_set_symmetry_breaking",
-                 "gm_free_query", "gm_candidate_sets", "gm_count_noalloc"):
+                 "gm_free_query", "gm_candidate_sets", "gm_count_noalloc", "gm_set_split", "gm_get_split",
+                 "gm_choose_plan"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -380,7 +388,7 @@ class Engine:
                       int(r.steals), int(r.rows), float(r.kernel_ms), int(r.grid_waves), int(r.kernel_tasks),
                       int(r.kernel_probes), int(r.kernel_groups), int(r.scanned), int(r.kernel_scanned),
                       int(r.kernel_lookups), matches, int(r.candidate_rounds), float(r.candidate_ms),
-                      int(r.candidate_edges), int(r.kernel_bytes), int(r.kernel_bytes_late))
+                      int(r.candidate_edges), int(r.kernel_bytes), int(r.kernel_bytes_late), float(r.query_ms))
 
     def count(self, qid: int, cap: int = 0, time_limit_s: float = 0.0) -> Result:
         r = _CResult()
@@ -443,6 +451,25 @@ class Engine:
         self._check(self._lib.gm_choose_order(self._h, model._h, qid, max_orders, seed, float(margin),
                                               ctypes.byref(chosen), _ptr(pred)))
         return chosen.value, pred
+
+    def set_split(self, qid: int, split: int) -> None:
+        """Task split of the query's two-phase pool (0 = the engine's; gm_set_split)."""
+        self._check(self._lib.gm_set_split(self._h, qid, int(split)))
+
+    def get_split(self, qid: int) -> int:
+        s = ctypes.c_int32()
+        self._check(self._lib.gm_get_split(self._h, qid, ctypes.byref(s)))
+        return s.value
+
+    def choose_plan(self, model: "Model", qid: int, splits=(8, 16, 32, 64), max_orders: int = 4, seed: int = 0,
+                    margin: float = 0.0):
+        """Let the model pick order and split (gm_choose_plan): (order index, split, predictions)."""
+        sp = np.ascontiguousarray(splits, dtype=np.int32)
+        pred = np.zeros(1 + max_orders * sp.shape[0], dtype=np.float32)
+        co, cs = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self._lib.gm_choose_plan(self._h, model._h, qid, max_orders, seed, _ptr(sp), sp.shape[0],
+                                             float(margin), ctypes.byref(co), ctypes.byref(cs), _ptr(pred)))
+        return co.value, cs.value, pred
 
     def set_symmetry_breaking(self, qid: int, enable: bool = True) -> int:
         """Count one map per automorphism class of the query; returns |Aut(Q)|."""

@@ -41,6 +41,7 @@ constexpr int32_t kHubDefaultMiB = 1024;
 struct QueryRec {
     bool live = false;
     int32_t k = 0;
+    int32_t split = 0;  // task split of the two-phase pool (position-1 tasks kept with a root); 0 = engine's
     std::vector<int32_t> labels;
     uint32_t adj[kMaxK] = {};
     std::vector<int32_t> order;
@@ -856,6 +857,12 @@ bool has_sb(const Plan &p) {
 // Two-phase pool: tasks of position 1 a root keeps in its first-phase item (default).
 constexpr uint32_t kHubCut = 16;
 
+// Task split of a query's two-phase pool: its own setting, else the engine's, else the default.
+int32_t query_split(const gm_engine *e, const QueryRec &q) {
+    if (q.split > 0) return q.split;
+    return e->opt.pool_hub_cut > 0 ? e->opt.pool_hub_cut : static_cast<int32_t>(kHubCut);
+}
+
 // A query is finished when every work item of it was claimed (its stream's
 // counter passed them) and every unit of its work (item or donation) ran to its end.
 bool query_finished(const Plan &p, const gm::QCtl &qc, const gm::StreamCtl &sc) {
@@ -1092,7 +1099,7 @@ gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, ui
     p.item0 = 0;
     p.item_end = 0;  // set on the device from the level-1 total
     p.vmode = 1;
-    p.hub_cut = e->opt.pool_hub_cut > 0 ? static_cast<uint32_t>(e->opt.pool_hub_cut) : kHubCut;
+    p.hub_cut = static_cast<uint32_t>(query_split(e, *q));
     p.vrow0 = 0;
     p.perm_mul = root_order(R);
     if (e->opt.pool_roots_per_item > 0) {
@@ -1526,6 +1533,9 @@ gm_status harvest_group(gm_engine *e, LaunchCtx &c, const GroupLaunch &gl, gm_re
             r.kernel_lookups = qc.lookups;
             r.kernel_bytes = qc.bytes;
             r.kernel_bytes_late = qc.bytes_late;
+            r.query_ms = qc.t_start && qc.t_last > qc.t_start
+                             ? static_cast<double>(qc.t_last - qc.t_start) / static_cast<double>(e->wall_khz)
+                             : 0.0;
             r.kernel_ms = kernel_ms;
             r.grid_waves = gl.grid_waves;
             if (sum) {
@@ -1735,6 +1745,7 @@ void order_features(const gm_engine *e, const QueryRec &q, const int32_t *order,
     }
     out[160] = static_cast<float>(q.k) / 32.f;
     out[161] = static_cast<float>(edges) / 64.f;
+    out[162] = static_cast<float>(std::log2(static_cast<double>(query_split(e, q)))) / 8.f;
 }
 
 // Candidate orders: the heuristic order, the fewest-candidates greedy order,
@@ -2647,6 +2658,70 @@ gm_status gm_choose_order(gm_engine *e, gm_model *model, int32_t qid, int32_t ma
     if (!(y[best] < y[0] - margin)) best = 0;  // keep the heuristic order unless clearly beaten
     e->queries[qid].order = cands[best];
     *chosen = static_cast<int32_t>(best);
+    if (predicted) std::copy(y.begin(), y.end(), predicted);
+    return GM_OK;
+}
+
+gm_status gm_set_split(gm_engine *e, int32_t qid, int32_t split) {
+    if (!e) return GM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (split < 0 || split > (1 << 24)) return e->fail(GM_ERR_ARG, "split must lie in [0, 2^24]");
+    const QueryRec *q = nullptr;
+    gm_status st = get_query(e, qid, &q);
+    if (st) return st;
+    e->queries[qid].split = split;
+    return GM_OK;
+}
+
+gm_status gm_get_split(const gm_engine *e, int32_t qid, int32_t *split) {
+    if (!e) return GM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (!split) return e->fail(GM_ERR_ARG, "split is null");
+    const QueryRec *q = nullptr;
+    gm_status st = get_query(e, qid, &q);
+    if (st) return st;
+    *split = query_split(e, *q);
+    return GM_OK;
+}
+
+gm_status gm_choose_plan(gm_engine *e, gm_model *model, int32_t qid, int32_t max_orders, uint64_t seed,
+                         const int32_t *splits, int32_t nsplits, float margin, int32_t *chosen_order,
+                         int32_t *chosen_split, float *predicted) {
+    if (!e) return GM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (!model || !chosen_order || !chosen_split || max_orders < 1 || nsplits < 1 || !splits)
+        return e->fail(GM_ERR_ARG, "bad arguments");
+    for (int32_t j = 0; j < nsplits; ++j)
+        if (splits[j] < 1 || splits[j] > (1 << 24)) return e->fail(GM_ERR_ARG, "splits must lie in [1, 2^24]");
+    const QueryRec *q = nullptr;
+    gm_status st = get_query(e, qid, &q);
+    if (st) return st;
+    if (!e->has_graph) return e->fail(GM_ERR_STATE, "no data graph loaded");
+    QueryRec &rec = e->queries[qid];
+    const int32_t split0 = query_split(e, rec);  // the fallback keeps the current split
+    const auto cands = candidate_orders(e, *q, max_orders, seed);
+    // candidate 0: heuristic order with the current split; then every (order, split) pair
+    std::vector<std::pair<int32_t, int32_t>> plan{{0, split0}};
+    for (int32_t o = 0; o < static_cast<int32_t>(cands.size()); ++o)
+        for (int32_t j = 0; j < nsplits; ++j)
+            if (!(o == 0 && splits[j] == split0)) plan.emplace_back(o, splits[j]);
+    std::vector<float> x(plan.size() * GM_ORDER_FEATURES), y(plan.size());
+    const int32_t saved = rec.split;
+    for (size_t i = 0; i < plan.size(); ++i) {
+        rec.split = plan[i].second;
+        order_features(e, rec, cands[plan[i].first].data(), x.data() + i * GM_ORDER_FEATURES);
+    }
+    rec.split = saved;
+    st = gm_model_predict(model, x.data(), static_cast<int32_t>(plan.size()), GM_ORDER_FEATURES, y.data());
+    if (st) return e->fail(st, std::string("model: ") + gm_model_last_error(model));
+    size_t best = 0;
+    for (size_t i = 1; i < plan.size(); ++i)
+        if (y[i] < y[best]) best = i;
+    if (!(y[best] < y[0] - margin)) best = 0;  // keep the heuristic plan unless clearly beaten
+    rec.order = cands[plan[best].first];
+    rec.split = plan[best].second == split0 && best == 0 ? saved : plan[best].second;
+    *chosen_order = plan[best].first;
+    *chosen_split = plan[best].second;
     if (predicted) std::copy(y.begin(), y.end(), predicted);
     return GM_OK;
 }

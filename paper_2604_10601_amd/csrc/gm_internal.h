@@ -88,6 +88,9 @@ struct alignas(128) QCtl {
     unsigned long long lanes_active;
     unsigned long long lanes_issued;
     unsigned long long steals;
+    // device wall clock of the last flush of this query's counters by any
+    // wavefront (with t_start, the query's device time in a batched launch)
+    unsigned long long t_last;
     // bytes the search kernel requested from device memory (reads and writes)
     // for this query; bytes_late: those of the last 32-round window of each
     // wavefront in which it saw the query's (or the launch's) abort word, an
@@ -95,7 +98,7 @@ struct alignas(128) QCtl {
     unsigned long long bytes;
     unsigned long long bytes_late;
     int live;                        // work units (items, donations) taken and not finished
-    int pad3[11];
+    int pad3[9];
 };
 
 static_assert(sizeof(QCtl) == 384 && offsetof(QCtl, abort) == 128 && offsetof(QCtl, groups) == 256,

@@ -890,6 +890,7 @@ __device__ __forceinline__ void tally_flush(const SearchArgs &a, PlanPtr P, int3
         if (t.active) atomicAdd(&c.lanes_active, t.active);
         if (t.issued) atomicAdd(&c.lanes_issued, t.issued);
         if (t.steals) atomicAdd(&c.steals, t.steals);
+        if (a.nq > 1) atomicMax(&c.t_last, static_cast<unsigned long long>(wall_clock64()));
         if (t.bytes) atomicAdd(&c.bytes, static_cast<unsigned long long>(t.bytes));
         if (t.bytes_late) atomicAdd(&c.bytes_late, static_cast<unsigned long long>(t.bytes_late));
     }
@@ -961,7 +962,7 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                 if (lane == 0) atomicMax(&sc.next, static_cast<unsigned long long>(P->item_end));
                 continue;
             }
-            if (P->budget) {  // the query's clock starts with its first claimed item
+            if (P->budget || a.nq > 1) {  // the query's clock starts with its first claimed item
                 unsigned long long old = 0;
                 if (lane == 0) {
                     const unsigned long long now = wall_clock64();

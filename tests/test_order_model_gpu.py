@@ -110,3 +110,37 @@ def test_chosen_orders_keep_counts():
         qid = e.add(qs[0])
         chosen, _ = e.choose_order(m, qid, max_orders=6, seed=0, margin=100.0)  # never beaten by 100
         assert chosen == 0 and list(e.get_order(qid)) == list(oracle.ri_order(qs[0].k, qs[0].edges))
+
+
+def test_splits_keep_counts_and_the_model_picks_plans():
+    """The task split changes how the pool is cut into work items, never the
+    matches or the paper's work counters; the plan the model picks (order and
+    split) is the one applied, and its counts equal the oracle's."""
+    rp, col = wl.rmat(13, 16, seed=4501)
+    g = wl.Graph(rp, col, wl.zipf_labels(1 << 13, 12, 0.5, seed=4502))
+    qs = wl.extract_queries_any(g, 4, 3, seed=4503) + wl.extract_queries_any(g, 6, 3, seed=4504)
+    rng = np.random.default_rng(45)
+    splits = (8, 16, 32, 64)
+    with gm.Engine(device=0) as e, gm.Model(D, H, seed=4) as m:
+        e.load(g)
+        load(m, params(rng, scale=0.3))
+        for i, q in enumerate(qs):
+            qid = e.add(q)
+            o = oracle.count(g, q, order=e.get_order(qid), cap=2_000_000)
+            for sp in (1, 8, 64, 5000):
+                e.set_split(qid, sp)
+                r = e.count(qid, cap=2_000_000)
+                assert (r.count, r.outcome) == (o.count, o.outcome), (i, sp)
+                if r.outcome == gm.GM_DONE:
+                    assert (r.groups, r.tasks) == (o.groups, o.tasks), (i, sp)
+            e.set_split(qid, 0)
+            co, cs, pred = e.choose_plan(m, qid, splits=splits, max_orders=4, seed=i, margin=-10.0)
+            cands = e.candidate_orders(qid, max_orders=4, seed=i)
+            assert list(e.get_order(qid)) == list(cands[co]) and e.get_split(qid) == cs
+            n = 1 + len(cands) * len(splits)
+            assert np.isfinite(pred[:n]).all()
+            r = e.count(qid, cap=2_000_000)
+            assert (r.count, r.outcome) == (o.count, o.outcome), i
+        qid = e.add(qs[0])
+        co, cs, _ = e.choose_plan(m, qid, splits=splits, max_orders=4, seed=0, margin=100.0)
+        assert (co, cs) == (0, 16) and e.get_split(qid) == 16
