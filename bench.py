@@ -224,6 +224,11 @@ def main() -> int:
     ap.add_argument("--train-limit", type=float, default=0.05, help="learned: time limit of the training runs (s)")
     ap.add_argument("--eval-cap", type=int, default=100_000_000, help="learned: cap of the evaluation runs")
     ap.add_argument("--eval-limit", type=float, default=2.0, help="learned: time limit of the evaluation runs (s)")
+    ap.add_argument("--margin", type=float, default=0.25,
+                    help="learned: predicted log2 gain a plan needs over the heuristic one to be proposed")
+    ap.add_argument("--probe-cap", type=int, default=1_000_000,
+                    help="learned: matches each plan counts when measured runtime judges a proposal (0 = no judge)")
+    ap.add_argument("--probe-limit", type=float, default=0.05, help="learned: time limit of each judging run (s)")
     ap.add_argument("--workload", default="large",
                     choices=["medium", "small", "large", "batch", "serve", "learned", "cg"],
                     help="batch = 10,000 mixed-size queries in shared launches (autotuned); "
@@ -661,7 +666,7 @@ def bench_learned(args, gm) -> int:
     from paper_2604_10601_amd import workloads as wl
     train_cap, train_limit, cap, limit = args.train_cap, args.train_limit, args.eval_cap, args.eval_limit
     n_orders, splits = 4, (8, 16, 32, 64)
-    xs, ys = [], []
+    xs, ys, starts = [], [], []
     half = max(1, args.train_queries // 2)
     for scale, seed in ((20, 60), (22, 61)):
         t = time.time()
@@ -673,6 +678,7 @@ def bench_learned(args, gm) -> int:
             t = time.time()
             for i, q in enumerate(qs):
                 qid = e.add(q)
+                starts.append(len(ys))
                 for o in e.candidate_orders(qid, max_orders=n_orders, seed=i):
                     e.set_order(qid, o)
                     for sp in splits:
@@ -685,7 +691,12 @@ def bench_learned(args, gm) -> int:
                     log(f"  scale {scale}: {i + 1} queries, {len(ys)} samples ({time.time() - t:.0f} s)")
         del g
     x = np.stack(xs).astype(np.float32)
-    y = np.asarray(ys, dtype=np.float32)
+    y_abs = np.asarray(ys, dtype=np.float32)
+    # the model only ranks plans of one query, so it learns each plan's time
+    # relative to the mean over that query's plans (log2 units)
+    y = y_abs.copy()
+    for a, b in zip(starts, starts[1:] + [len(ys)]):
+        y[a:b] -= y_abs[a:b].mean()
     rng = np.random.default_rng(7)
     perm = rng.permutation(len(y))
     n_val = max(1, len(y) // 10)
@@ -708,12 +719,15 @@ def bench_learned(args, gm) -> int:
         qids = [e.add(q) for q in qs]
         heuristic = {}
         mine = {}
+        probe_ms = np.zeros(len(qids))
         for i, qid in enumerate(qids):
             heuristic[qid] = (e.get_order(qid), e.get_split(qid))
-            co, cs, _ = e.choose_plan(model, qid, splits=splits, max_orders=n_orders, seed=i, margin=0.25)
+            co, cs, _, probe_ms[i] = e.choose_plan(model, qid, splits=splits, max_orders=n_orders, seed=i,
+                                                   margin=args.margin, probe_cap=args.probe_cap,
+                                                   probe_limit_s=args.probe_limit)
             mine[qid] = (e.get_order(qid), e.get_split(qid))
-            other_order += co != 0
-            other_split += cs != heuristic[qid][1]
+            other_order += not np.array_equal(mine[qid][0], heuristic[qid][0])
+            other_split += mine[qid][1] != heuristic[qid][1]
 
         def use(qid, plan):
             e.set_order(qid, plan[0])
@@ -748,7 +762,7 @@ def bench_learned(args, gm) -> int:
                             if a.outcome != gm.GM_TIMEOUT and b.outcome != gm.GM_TIMEOUT)
     model.close()
     lp = np.array([r.search_ms for r in plain])
-    ll = np.array([r.search_ms for r in learned])
+    ll = np.array([r.search_ms for r in learned]) + probe_ms   # the judge's probes are the learned plan's cost
 
     def batch_summary(which):
         walls = [w for w, _, _ in batched[which]]
@@ -774,13 +788,17 @@ def bench_learned(args, gm) -> int:
         "config": {"workload": f"learned plan: train R-MAT 20+22, evaluate R-MAT {args.eval_scale}",
                    "train_queries": 2 * half, "orders_per_query": n_orders, "splits": list(splits),
                    "samples": int(len(y)), "train_cap": train_cap, "train_time_limit_s": train_limit,
-                   "eval_queries": len(qs), "cap": cap, "time_limit_s": limit, "margin_log2": 0.25},
+                   "eval_queries": len(qs), "cap": cap, "time_limit_s": limit, "margin_log2": args.margin,
+                   "target": "log2 search ms minus the query's mean over its plans",
+                   "judge": {"probe_cap": args.probe_cap, "probe_time_limit_s": args.probe_limit}},
         "heuristic": {"total_ms": float(lp.sum()), "p50_ms": float(np.percentile(lp, 50)),
                       "p99_ms": float(np.percentile(lp, 99)),
                       "timeouts": int(sum(r.outcome == gm.GM_TIMEOUT for r in plain))},
         "learned": {"total_ms": float(ll.sum()), "p50_ms": float(np.percentile(ll, 50)),
                     "p99_ms": float(np.percentile(ll, 99)),
                     "timeouts": int(sum(r.outcome == gm.GM_TIMEOUT for r in learned)),
+                    "probe_ms_included": float(probe_ms.sum()),
+                    "queries_probed": int((probe_ms > 0).sum()),
                     "queries_with_another_order": int(other_order), "queries_with_another_split": int(other_split)},
         "batched": {"heuristic": batch_summary("h"), "learned": batch_summary("l"), "same_counts": bool(same_batched)},
         "model": {"train_mse": loss, "heldout_mse": val_mse, "target_variance": float(np.var(y))},

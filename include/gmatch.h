@@ -503,13 +503,18 @@ gm_status gm_get_split(const gm_engine *engine, int32_t qid, int32_t *split);
  * gm_candidate_orders(max_orders, seed) and its task split among
  * splits[nsplits].  Candidate 0 is the heuristic order with the current split;
  * then every (order, split) pair in order-major order.  The candidate
- * predicted cheapest is set if it beats candidate 0's prediction by more than
- * `margin` (log2 units), else candidate 0 stays.  *chosen_order receives the
- * order's index (0 = heuristic), *chosen_split the split, and
- * predicted[1 + orders * nsplits] (may be NULL) the predictions. */
+ * predicted cheapest is proposed if it beats candidate 0's prediction by more
+ * than `margin` (log2 units), else candidate 0 stays.  With probe_cap > 0 the
+ * measured runtime judges the proposal: the query is counted under both plans
+ * up to probe_cap (and probe_limit_s, <= 0 = none), and the proposal is kept
+ * only if it got there faster; *probe_ms (may be NULL) receives those runs'
+ * search time.  *chosen_order receives the order's index (0 = heuristic),
+ * *chosen_split the split, and predicted[1 + orders * nsplits] (may be NULL)
+ * the predictions. */
 gm_status gm_choose_plan(gm_engine *engine, gm_model *model, int32_t qid, int32_t max_orders, uint64_t seed,
-                         const int32_t *splits, int32_t nsplits, float margin, int32_t *chosen_order,
-                         int32_t *chosen_split, float *predicted);
+                         const int32_t *splits, int32_t nsplits, float margin, uint64_t probe_cap,
+                         double probe_limit_s, int32_t *chosen_order, int32_t *chosen_split, float *predicted,
+                         double *probe_ms);
 
 /* Opt-in symmetry breaking.  By default every injective map is counted (Def.
  * 1).  The paper's comparison runs give all systems the same symmetry-breaking

@@ -269,8 +269,8 @@ def load_library():
     lib.gm_set_symmetry_breaking.argtypes = [p, i32, i32, ctypes.POINTER(u64)]
     lib.gm_set_split.argtypes = [p, i32, i32]
     lib.gm_get_split.argtypes = [p, i32, ctypes.POINTER(i32)]
-    lib.gm_choose_plan.argtypes = [p, p, i32, i32, u64, p, i32, ctypes.c_float, ctypes.POINTER(i32),
-                                   ctypes.POINTER(i32), p]
+    lib.gm_choose_plan.argtypes = [p, p, i32, i32, u64, p, i32, ctypes.c_float, u64, dbl, ctypes.POINTER(i32),
+                                   ctypes.POINTER(i32), p, ctypes.POINTER(dbl)]
     lib.gm_free_query.argtypes = [p, i32]
     lib.gm_candidate_sets.argtypes = [p, i32, p, ctypes.POINTER(u64), ctypes.POINTER(i32)]
     lib.gm_last_error.argtypes = [p]
@@ -462,14 +462,16 @@ class Engine:
         return s.value
 
     def choose_plan(self, model: "Model", qid: int, splits=(8, 16, 32, 64), max_orders: int = 4, seed: int = 0,
-                    margin: float = 0.0):
-        """Let the model pick order and split (gm_choose_plan): (order index, split, predictions)."""
+                    margin: float = 0.0, probe_cap: int = 0, probe_limit_s: float = 0.0):
+        """Let the model pick order and split (gm_choose_plan), judged by a measured probe when
+        probe_cap > 0: (order index, split, predictions, probe ms)."""
         sp = np.ascontiguousarray(splits, dtype=np.int32)
         pred = np.zeros(1 + max_orders * sp.shape[0], dtype=np.float32)
-        co, cs = ctypes.c_int32(), ctypes.c_int32()
+        co, cs, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         self._check(self._lib.gm_choose_plan(self._h, model._h, qid, max_orders, seed, _ptr(sp), sp.shape[0],
-                                             float(margin), ctypes.byref(co), ctypes.byref(cs), _ptr(pred)))
-        return co.value, cs.value, pred
+                                             float(margin), int(probe_cap), float(probe_limit_s), ctypes.byref(co),
+                                             ctypes.byref(cs), _ptr(pred), ctypes.byref(ms)))
+        return co.value, cs.value, pred, ms.value
 
     def set_symmetry_breaking(self, qid: int, enable: bool = True) -> int:
         """Count one map per automorphism class of the query; returns |Aut(Q)|."""

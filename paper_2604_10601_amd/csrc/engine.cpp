@@ -2685,8 +2685,9 @@ gm_status gm_get_split(const gm_engine *e, int32_t qid, int32_t *split) {
 }
 
 gm_status gm_choose_plan(gm_engine *e, gm_model *model, int32_t qid, int32_t max_orders, uint64_t seed,
-                         const int32_t *splits, int32_t nsplits, float margin, int32_t *chosen_order,
-                         int32_t *chosen_split, float *predicted) {
+                         const int32_t *splits, int32_t nsplits, float margin, uint64_t probe_cap,
+                         double probe_limit_s, int32_t *chosen_order, int32_t *chosen_split, float *predicted,
+                         double *probe_ms) {
     if (!e) return GM_ERR_ARG;
     std::lock_guard<std::mutex> lk(e->mu);
     if (!model || !chosen_order || !chosen_split || max_orders < 1 || nsplits < 1 || !splits)
@@ -2718,11 +2719,34 @@ gm_status gm_choose_plan(gm_engine *e, gm_model *model, int32_t qid, int32_t max
     for (size_t i = 1; i < plan.size(); ++i)
         if (y[i] < y[best]) best = i;
     if (!(y[best] < y[0] - margin)) best = 0;  // keep the heuristic plan unless clearly beaten
+    if (predicted) std::copy(y.begin(), y.end(), predicted);
+    if (probe_ms) *probe_ms = 0.0;
+    if (best != 0 && probe_cap > 0) {
+        // measured runtime as the judge: both plans counted up to probe_cap; the
+        // model's plan is kept only if it reached that point faster
+        if (e->device < 0) return e->fail(GM_ERR_DEVICE, "host-only engine cannot measure plans");
+        const std::vector<int32_t> order0 = rec.order;
+        double ms[2] = {0.0, 0.0};
+        for (int32_t which = 0; which < 2; ++which) {
+            const size_t c = which == 0 ? 0 : best;
+            rec.order = cands[plan[c].first];
+            rec.split = c == 0 ? saved : plan[c].second;
+            gm_result r{};
+            st = run_search(e, qid, probe_cap, probe_limit_s, nullptr, &r);
+            if (st) {
+                rec.order = order0;
+                rec.split = saved;
+                return st;
+            }
+            ms[which] = r.search_ms;
+        }
+        if (probe_ms) *probe_ms = ms[0] + ms[1];
+        if (!(ms[1] < ms[0])) best = 0;
+    }
     rec.order = cands[plan[best].first];
-    rec.split = plan[best].second == split0 && best == 0 ? saved : plan[best].second;
+    rec.split = best == 0 ? saved : plan[best].second;
     *chosen_order = plan[best].first;
     *chosen_split = plan[best].second;
-    if (predicted) std::copy(y.begin(), y.end(), predicted);
     return GM_OK;
 }
 

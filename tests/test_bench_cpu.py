@@ -87,3 +87,19 @@ def test_more_than_one_gpu_is_refused():
                          text=True)
     assert res.returncode == 2
     assert "exactly one GPU" in res.stderr
+
+
+def test_counter_summary_of_the_search_kernel(tmp_path):
+    rows = []
+    for d, (waves, cycles, wait, valu) in enumerate([(100, 1000, 600, 5000), (300, 3000, 1500, 15000)]):
+        for name, v in (("SQ_WAVES", waves), ("SQ_WAVE_CYCLES", cycles), ("SQ_WAIT_ANY", wait),
+                        ("SQ_INSTS_VALU", valu)):
+            rows.append([d, SEARCH.format(0, "true", "false", "false", 4), name, v])
+        rows.append([d, "__amd_rocclr_copyBuffer", "SQ_WAVES", 7])
+    _write_csv(str(tmp_path / "pmc" / "run_counter_collection.csv"),
+               ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"], rows)
+    kv = dict(line.split(": ", 1) for line in bench.summarize_pmc(str(tmp_path / "pmc")).splitlines())
+    assert kv["kernel"] == "search<slim>"
+    assert kv["SQ_WAVES"].startswith("400") and "(dispatches 2)" in kv["SQ_WAVES"]
+    assert float(kv["wait_any_fraction"]) == 0.525   # (600 + 1500) / (1000 + 3000)
+    assert kv["sq_insts_valu_per_wave"] == "50"

@@ -134,7 +134,7 @@ def test_splits_keep_counts_and_the_model_picks_plans():
                 if r.outcome == gm.GM_DONE:
                     assert (r.groups, r.tasks) == (o.groups, o.tasks), (i, sp)
             e.set_split(qid, 0)
-            co, cs, pred = e.choose_plan(m, qid, splits=splits, max_orders=4, seed=i, margin=-10.0)
+            co, cs, pred, _ = e.choose_plan(m, qid, splits=splits, max_orders=4, seed=i, margin=-10.0)
             cands = e.candidate_orders(qid, max_orders=4, seed=i)
             assert list(e.get_order(qid)) == list(cands[co]) and e.get_split(qid) == cs
             n = 1 + len(cands) * len(splits)
@@ -142,5 +142,14 @@ def test_splits_keep_counts_and_the_model_picks_plans():
             r = e.count(qid, cap=2_000_000)
             assert (r.count, r.outcome) == (o.count, o.outcome), i
         qid = e.add(qs[0])
-        co, cs, _ = e.choose_plan(m, qid, splits=splits, max_orders=4, seed=0, margin=100.0)
-        assert (co, cs) == (0, 16) and e.get_split(qid) == 16
+        co, cs, _, probe = e.choose_plan(m, qid, splits=splits, max_orders=4, seed=0, margin=100.0, probe_cap=1000)
+        assert (co, cs) == (0, 16) and e.get_split(qid) == 16 and probe == 0.0   # nothing to judge
+        # a proposal judged by measured runtime: whichever plan stays, counts are the oracle's
+        for i, q in enumerate(qs):
+            qid = e.add(q)
+            co, cs, _, probe = e.choose_plan(m, qid, splits=splits, max_orders=4, seed=i, margin=-10.0,
+                                             probe_cap=10_000, probe_limit_s=1.0)
+            assert probe >= 0.0 and e.get_split(qid) in (16, cs)
+            o = oracle.count(g, q, order=e.get_order(qid), cap=2_000_000)
+            r = e.count(qid, cap=2_000_000)
+            assert (r.count, r.outcome) == (o.count, o.outcome), i
