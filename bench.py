@@ -220,8 +220,12 @@ def main() -> int:
                     help="learned: training queries (4 candidate orders x 4 splits each, half on each graph)")
     ap.add_argument("--eval-queries", type=int, default=1000, help="learned: held-out queries")
     ap.add_argument("--eval-scale", type=int, default=24, choices=[20, 22, 24], help="learned: held-out graph")
-    ap.add_argument("--train-cap", type=int, default=1_000_000, help="learned: cap of the training runs")
-    ap.add_argument("--train-limit", type=float, default=0.05, help="learned: time limit of the training runs (s)")
+    ap.add_argument("--train-cap", type=int, default=100_000_000,
+                    help="learned: cap of the training runs (the evaluation's, so the times mean the same)")
+    ap.add_argument("--train-limit", type=float, default=0.1, help="learned: time limit of the training runs (s)")
+    ap.add_argument("--plan-table", action="store_true",
+                    help="learned: also time every (order, split) plan of every held-out query once, for the "
+                         "best plan per query and the model's pick measured side by side")
     ap.add_argument("--eval-cap", type=int, default=100_000_000, help="learned: cap of the evaluation runs")
     ap.add_argument("--eval-limit", type=float, default=2.0, help="learned: time limit of the evaluation runs (s)")
     ap.add_argument("--margin", type=float, default=0.25,
@@ -755,6 +759,30 @@ def bench_learned(args, gm) -> int:
                 t0 = time.perf_counter()
                 res, info = e.count_batch(qids, cap=cap, time_limit_s=limit)
                 batched[which].append((time.perf_counter() - t0, info, res))
+        table = None
+        if args.plan_table:
+            # every plan of every query once: what the best choice per query would save
+            tot = {"heuristic": 0.0, "model": 0.0, "best": 0.0}
+            pick_rank = []
+            for i, qid in enumerate(qids):
+                times = []
+                for o in e.candidate_orders(qid, max_orders=n_orders, seed=i):
+                    for sp in splits:
+                        e.set_order(qid, o)
+                        e.set_split(qid, sp)
+                        r = e.count(qid, cap=cap, time_limit_s=limit)
+                        times.append((r.search_ms, np.array_equal(o, heuristic[qid][0]) and sp == heuristic[qid][1],
+                                      np.array_equal(o, mine[qid][0]) and sp == mine[qid][1]))
+                ts = np.array([x[0] for x in times])
+                tot["heuristic"] += float(ts[[x[1] for x in times]].min())
+                tot["model"] += float(ts[[x[2] for x in times]].min())
+                tot["best"] += float(ts.min())
+                pick_rank.append(int((ts < ts[[x[2] for x in times]].min()).sum()))
+                if (i + 1) % 250 == 0:
+                    log(f"  timed every plan of {i + 1} queries ({time.time() - t:.0f} s)")
+            table = {"total_ms": tot, "plans_per_query": len(times),
+                     "model_pick_rank_mean": float(np.mean(pick_rank)),
+                     "note": "each plan timed once, one query at a time; rank 0 = the fastest plan"}
         bh, bl = batched["h"][-1][2], batched["l"][-1][2]
         same_batched = all((a.count, a.outcome) == (b.count, b.outcome) for a, b in zip(bh, bl)
                            if a.outcome != gm.GM_TIMEOUT and b.outcome != gm.GM_TIMEOUT)
@@ -802,6 +830,7 @@ def bench_learned(args, gm) -> int:
                     "queries_with_another_order": int(other_order), "queries_with_another_split": int(other_split)},
         "batched": {"heuristic": batch_summary("h"), "learned": batch_summary("l"), "same_counts": bool(same_batched)},
         "model": {"train_mse": loss, "heldout_mse": val_mse, "target_variance": float(np.var(y))},
+        "plan_table": table,
         "same_counts": bool(same),
     }
     print(json.dumps(out), flush=True)

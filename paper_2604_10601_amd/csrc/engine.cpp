@@ -656,7 +656,7 @@ gm_status install_device(gm_engine *e, HostGraph &hg, const void *d_row_ptr, int
     h = hipMalloc(reinterpret_cast<void **>(&vinfo), std::max<size_t>(n, 1) * sizeof(VInfo));
     if (h == hipSuccess) h = hipMalloc(reinterpret_cast<void **>(&loff), std::max<size_t>(loff_len, 1) * sizeof(uint32_t));
     if (h == hipSuccess && stride > 1)
-        h = hipMalloc(reinterpret_cast<void **>(&lcol), std::max<uint64_t>(hg.nnz, 1) * sizeof(int32_t));
+        h = hipMalloc(reinterpret_cast<void **>(&lcol), std::max<uint64_t>(hg.nnz, gm::kListWindow) * sizeof(int32_t));
     if (h == hipSuccess) h = hipMalloc(reinterpret_cast<void **>(&bylabel_d), std::max<size_t>(n, 1) * sizeof(int32_t));
     if (h == hipSuccess)
         h = gm::launch_graph_build(d_row_ptr, rp_bytes, d_col, d_clab, n, stride, vinfo, loff, stride > 1 ? lcol : nullptr,
@@ -1021,7 +1021,7 @@ gm_status build_candidate_graph(gm_engine *e, const Plan &p, CandInfo *ci, uint3
     if (total >= (1ull << 32)) return e->fail(GM_ERR_NOMEM, "candidate graph holds 2^32 list entries or more");
     ci->edges = total;
     HIP_TRY(e, gm::launch_exclusive_scan(scratch, first, tmp, s));
-    st = ensure_buffer(e, &e->d_gcol, &e->gcol_cap, static_cast<size_t>(std::max<unsigned long long>(total, 1)));
+    st = ensure_buffer(e, &e->d_gcol, &e->gcol_cap, static_cast<size_t>(std::max<unsigned long long>(total, gm::kListWindow)));
     if (st) return st;
     HIP_TRY(e, gm::launch_cand_fill(e->d_lcol, e->d_loff, e->loff_stride, n, cq, bits, d_edges, m, most, e->d_clist,
                                     scratch, e->d_gcol, reinterpret_cast<uint32_t *>(e->d_gbounds), e->num_cu, s));
@@ -2124,7 +2124,8 @@ gm_status gm_load_graph(gm_engine *e, int32_t n, const int64_t *row_ptr, const i
         if (d_clab) (void)hipFree(d_clab);
     };
     hipError_t h = hipMalloc(reinterpret_cast<void **>(&d_rp), (static_cast<size_t>(n) + 1) * sizeof(int64_t));
-    if (h == hipSuccess) h = hipMalloc(reinterpret_cast<void **>(&d_col), std::max<uint64_t>(hg.nnz, 1) * sizeof(int32_t));
+    if (h == hipSuccess)
+        h = hipMalloc(reinterpret_cast<void **>(&d_col), std::max<uint64_t>(hg.nnz, gm::kListWindow) * sizeof(int32_t));
     if (h == hipSuccess) h = hipMalloc(reinterpret_cast<void **>(&d_clab), std::max<size_t>(n, 1));
     if (h == hipSuccess) h = hipMemcpyAsync(d_rp, row_ptr, (static_cast<size_t>(n) + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
     if (h == hipSuccess && hg.nnz) h = hipMemcpyAsync(d_col, col, hg.nnz * sizeof(int32_t), hipMemcpyHostToDevice, s);
@@ -2211,7 +2212,25 @@ gm_status gm_load_graph_device(gm_engine *e, int32_t n, const void *row_ptr, int
         release();
         return hip_fail(e, h, "label compaction");
     }
-    gm_status st = install_device(e, hg, row_ptr, row_ptr_bytes, const_cast<int32_t *>(col), false, d_clab, s);
+    // the membership test reads windows of gm::kListWindow entries: a shorter array
+    // is copied into one of the engine's own that long
+    int32_t *d_col = const_cast<int32_t *>(col);
+    bool owned = false;
+    if (hg.nnz < gm::kListWindow) {
+        h = hipMalloc(reinterpret_cast<void **>(&d_col), gm::kListWindow * sizeof(int32_t));
+        if (h == hipSuccess) {
+            owned = true;
+            h = hipMemsetAsync(d_col, 0, gm::kListWindow * sizeof(int32_t), s);
+        }
+        if (h == hipSuccess && hg.nnz)
+            h = hipMemcpyAsync(d_col, col, hg.nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+        if (h != hipSuccess) {
+            if (owned) (void)hipFree(d_col);
+            release();
+            return hip_fail(e, h, "adjacency copy");
+        }
+    }
+    gm_status st = install_device(e, hg, row_ptr, row_ptr_bytes, d_col, owned, d_clab, s);
     (void)hipStreamSynchronize(s);
     release();
     return st;

@@ -13,6 +13,11 @@ constexpr unsigned long long kScratchBytes = 64ull << 20;  // the allocation-fre
 constexpr int kMaxMergeSlots = 8;      // LDS-staged intersection: largest staging entries per lane
 constexpr int kDefaultMergeSlots = 1;  // ... and the default (lists no longer than the run of candidates)
 constexpr int kWave = 64;  // CDNA wavefront width
+// The membership test reads the end of a list as one window of this many
+// consecutive entries, so every adjacency array it searches (the adjacency, its
+// label-sorted copy, the candidate graph's lists) is allocated with at least
+// this many entries.
+constexpr uint64_t kListWindow = 8;
 
 // Packed per-vertex record, one 8-byte load per candidate:
 //   x = first adjacency slot of v in col[], y = (degree << 8) | compact label.

@@ -100,69 +100,51 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
     return x;
 }
 
-// Membership of v in the ascending lists col[lo[s], lo[s] + n[s]), s < kLists
-// (n[s] == 0 marks an unused slot).  kLists is 1: the caller tests one list
-// at a time.  (The code can bisect several lists in lockstep, one round trip
-// for all of them, but on this hardware that cost more instructions per
-// candidate than the round trips it saved: same box, the 8-vertex workload ran
-// at 34.7, 37.1 and 38.5 G embeddings/s with four, two and one lists, the
-// 12-32-vertex sample at 14.6, 15.4 and 15.7.)  A range is bisected until at
-// most kTail entries remain, and the tail is read with kTail independent loads
-// (indices clamped into the list).  Returns true iff v is in every used list;
-// adds the list entries examined to probes and the bytes of the loads issued
-// to bytes.
-constexpr int kLists = 1;
+// Membership of v in the ascending list col[lo, lo + n) (Sec. 5.2 costs each
+// test as one binary search).  A lower-bound bisection with no early exit keeps
+// the invariant "the first entry >= v lies in [lo, lo + n]" and halves n until
+// fewer than kTail entries remain; the step is a select, not a branch, so a
+// wavefront pays one compare and two selects per probe and no per-lane control
+// flow.  The tail is then read as one window of kTail consecutive entries that
+// ends at min(lo + kTail - 1, last entry) (starting at index 0 if that is
+// lower); only window entries inside [lo, last entry] count.  Every array
+// searched here holds at least kTail entries, so the window stays inside it,
+// and one base address with constant offsets lets all kTail loads be in flight
+// together (a clamped index per load costs an address pair each, and under
+// register pressure the loads were issued one round trip at a time).
+// (Bisecting several lists in lockstep, one round trip for all of them, cost
+// more instructions per candidate than it saved: same box, the 8-vertex
+// workload ran at 34.7, 37.1 and 38.5 G embeddings/s with four, two and one
+// lists, the 12-32-vertex sample at 14.6, 15.4 and 15.7.)  Adds the entries
+// examined to probes and the bytes of the loads issued to bytes.
 // Tail of 8 entries (one or two 64-byte sectors): against 4, +1 % on the
 // 8-vertex workload and +3 % on the 12-32-vertex sample.
-constexpr uint32_t kTail = 8;
+constexpr uint32_t kTail = static_cast<uint32_t>(kListWindow);
 
-__device__ __forceinline__ bool in_all_lists(const int32_t *__restrict__ col, uint32_t (&lo)[kLists],
-                                             uint32_t (&n)[kLists], int32_t v, uint32_t &probes, uint32_t &bytes) {
-    bool found[kLists];
-#pragma unroll
-    for (int s = 0; s < kLists; ++s) found[s] = n[s] == 0u;
-    for (;;) {
-        bool more = false;
-#pragma unroll
-        for (int s = 0; s < kLists; ++s) more |= !found[s] && n[s] > kTail;
-        if (!more) break;
-        int32_t x[kLists];
-        uint32_t h[kLists];
-#pragma unroll
-        for (int s = 0; s < kLists; ++s) {
-            h[s] = n[s] >> 1;
-            const bool act = !found[s] && n[s] > kTail;
-            x[s] = act ? col[lo[s] + h[s]] : 0;
-            probes += act;
-            bytes += act ? 4u : 0u;
-        }
-#pragma unroll
-        for (int s = 0; s < kLists; ++s) {
-            if (found[s] || n[s] <= kTail) continue;
-            if (x[s] == v) {
-                found[s] = true;
-            } else if (x[s] < v) {
-                lo[s] += h[s] + 1u;
-                n[s] -= h[s] + 1u;
-            } else {
-                n[s] = h[s];
-            }
-        }
+__device__ __forceinline__ bool in_list(const int32_t *__restrict__ col, uint32_t lo, uint32_t n, int32_t v,
+                                        uint32_t &probes, uint32_t &bytes) {
+    const uint32_t last = lo + n - 1u;  // callers pass n >= 1
+    while (n >= kTail) {
+        const uint32_t h = n >> 1;
+        const int32_t x = col[lo + h];
+        lo = x < v ? lo + h : lo;
+        n -= h;
+        ++probes;
+        bytes += 4u;
     }
-    bool all = true;
+    const uint32_t hi = lo + (kTail - 1u) < last ? lo + (kTail - 1u) : last;
+    const uint32_t p = hi >= kTail - 1u ? hi - (kTail - 1u) : 0u;
+    const int32_t *w = col + p;
+    int32_t x[kTail];
 #pragma unroll
-    for (int s = 0; s < kLists; ++s) {
-        if (found[s]) continue;
-        bool f = false;
-        if (n[s] != 0u) {
+    for (uint32_t j = 0; j < kTail; ++j) x[j] = w[j];
+    const uint32_t jlo = lo - p, span = hi - lo;  // counted entries: j in [jlo, jlo + span]
+    uint32_t hit = 0;
 #pragma unroll
-            for (uint32_t i = 0; i < kTail; ++i) f |= col[lo[s] + (i < n[s] ? i : n[s] - 1u)] == v;
-            probes += n[s];
-            bytes += 4u * kTail;  // every tail load is issued, clamped ones included
-        }
-        all &= f;
-    }
-    return all;
+    for (uint32_t j = 0; j < kTail; ++j) hit |= static_cast<uint32_t>(x[j] == v) << j;
+    probes += span + 1u;
+    bytes += 4u * kTail;  // the whole window is read
+    return ((hit >> jlo) & ((2u << span) - 1u)) != 0u;
 }
 
 // Per-wavefront stack in LDS (Sec. 5.1: S is |V(Q)| x warp width) for exactly k
@@ -299,11 +281,16 @@ __device__ __forceinline__ Gen generate_tasks(WaveStack &S, const SearchArgs &a,
                     ++g.lookups;
                     g.bytes += 8u;
                 } else if (SLIM) {
+                    // list bounds and slice bounds: three independent loads (the slice's
+                    // two bounds are adjacent), all issued before any is used
                     const uint32_t *o = a.loff + static_cast<unsigned long long>(S.v[i * kWave + q]) * stride;
+                    uint2 sb;
+                    __builtin_memcpy(&sb, o + lab, sizeof(sb));
                     const uint32_t row0 = o[0];
-                    d = o[stride - 1 + (sliced ? 0 : 1)] - row0;  // whole list: first to last bound
-                    sa = o[lab];
-                    sn = o[lab + 1] - sa;
+                    const uint32_t rowe = o[stride - 1 + (sliced ? 0 : 1)];
+                    d = rowe - row0;  // whole list: first to last bound
+                    sa = sb.x;
+                    sn = sb.y - sb.x;
                     ++g.lookups;
                     g.bytes += 16u;  // list bounds and slice bounds
                 } else {
@@ -504,7 +491,8 @@ __device__ __forceinline__ bool merge_member(const int32_t *__restrict__ list, u
 // empty list rejects v; a hub's list is answered by one bit of its adjacency
 // bitmap; a list short against its run (n <= slots x the run's lanes still
 // testing) is staged in LDS and intersected by merge path; any other list is
-// bisected in device memory lane by lane (in_all_lists).
+// bisected in device memory lane by lane (in_list).  Every lane of a run has
+// the same w, so the lanes of one run take the same branch.
 template <bool CG>
 __device__ __forceinline__ bool slim_member(const SearchArgs &a, uint8_t *marea, uint32_t run, uint32_t lab,
                                             uint32_t w, uint32_t edge, int32_t v, uint32_t &probes,
@@ -515,28 +503,38 @@ __device__ __forceinline__ bool slim_member(const SearchArgs &a, uint8_t *marea,
     const int32_t hub = a.hub_id ? a.hub_id[w] : -1;  // read in the same round as the bounds
     ++lookups;
     bytes += a.hub_id ? 12u : 8u;
-    if (b1 == b0) return false;
-    if (hub >= 0) {
-        const uint32_t word =
-            a.hub_bits[static_cast<unsigned long long>(hub) * a.hub_words + (static_cast<uint32_t>(v) >> 5)];
-        ++probes;
-        bytes += 4u;
-        return ((word >> (static_cast<uint32_t>(v) & 31u)) & 1u) != 0u;
-    }
     const uint32_t n = b1 - b0;
-    if (a.merge_slots > 0) {
-        // lanes of this run still testing here: all of them reached this point with the same list
-        const uint32_t live = static_cast<uint32_t>(__popcll(ballot(true) & lane_range(run & 0xffu, run >> 8)));
-        if (n <= static_cast<uint32_t>(a.merge_slots) * live)
-            return merge_member(a.lcol + b0, n, marea, static_cast<uint32_t>(a.merge_slots), run, v, probes, bytes);
+    bool in = false;
+    if (n != 0u) {
+        if (hub >= 0) {
+            const uint32_t word =
+                a.hub_bits[static_cast<unsigned long long>(hub) * a.hub_words + (static_cast<uint32_t>(v) >> 5)];
+            ++probes;
+            bytes += 4u;
+            in = ((word >> (static_cast<uint32_t>(v) & 31u)) & 1u) != 0u;
+        } else {
+            // lanes of this run still testing here: all of them reached this point with the same list
+            const uint32_t live =
+                a.merge_slots > 0 ? static_cast<uint32_t>(__popcll(ballot(true) & lane_range(run & 0xffu, run >> 8)))
+                                  : 0u;
+            if (n <= static_cast<uint32_t>(a.merge_slots) * live)
+                in = merge_member(a.lcol + b0, n, marea, static_cast<uint32_t>(a.merge_slots), run, v, probes, bytes);
+            else
+                in = in_list(a.lcol, b0, n, v, probes, bytes);
+        }
     }
-    uint32_t lo1[kLists] = {b0}, n1[kLists] = {n};
-    return in_all_lists(a.lcol, lo1, n1, v, probes, bytes);
+    return in;
 }
 
 // Process (Alg. 2): label and degree filters, then one walk down the parent
 // chain checking injectivity and membership in every backward neighbour's list
-// other than the one the candidate came from, one list at a time.
+// other than the one the candidate came from, one list at a time.  The walk is
+// wave-uniform: every lane steps down its chain (its chain index is always a
+// lane of the stack, so a lane that already failed reads inside the stack and
+// ignores what it reads), only the membership tests run under the lanes still
+// alive, and the wavefront leaves the walk once no lane is.  Keeping the loop
+// and the per-level branches scalar removes the per-lane exit masks a
+// data-dependent break costs at every level of the chain.
 template <bool SLIM, bool SB, bool CG = false>
 __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanPtr P, int l, const Round &r,
                                         uint32_t lane, VInfo &vi, uint32_t &probes, uint32_t &lookups,
@@ -554,42 +552,43 @@ __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanP
     }
     if (need)
         ok = ok && vi_lab(vi) == static_cast<uint32_t>(P->lab[l]) && vi_deg(vi) >= static_cast<uint32_t>(P->qdeg[l]);
-    if (ok) {
-        const uint32_t bw = P->bwd[l];
-        // symmetry-breaking conditions: only in launches that hold a query with them
-        const uint32_t sblt = SB ? P->sb_lt[l] : 0u, sbgt = SB ? P->sb_gt[l] : 0u;
-        // the backward neighbour whose list the candidate came from needs no
-        // test; it is the same for every lane of a run
-        const uint32_t js = r.js;
-        const uint32_t lab = a.loff_stride > 1 ? static_cast<uint32_t>(P->lab[l]) : 0u;
-        uint32_t q = r.owner;
-        for (int i = l - 1; i >= 0; --i) {
-            const int32_t w = S.v[i * kWave + q];
-            if (w == r.v) {
-                ok = false;
-                break;
-            }
-            if (SB && ((((sblt >> i) & 1u) && !(w < r.v)) || (((sbgt >> i) & 1u) && !(r.v < w)))) {
-                ok = false;
-                break;
-            }
-            if (((bw >> i) & 1u) && static_cast<uint32_t>(i) != js) {
+    if (ballot(ok) == 0ull) return false;
+    const uint32_t bw = P->bwd[l];
+    // symmetry-breaking conditions: only in launches that hold a query with them
+    const uint32_t sblt = SB ? P->sb_lt[l] : 0u, sbgt = SB ? P->sb_gt[l] : 0u;
+    // the backward neighbour whose list the candidate came from needs no test;
+    // it is the same for every lane of a run
+    const uint32_t js = r.js;
+    const uint32_t lab = a.loff_stride > 1 ? static_cast<uint32_t>(P->lab[l]) : 0u;
+    // the verdict is kept as data (0 or 1) rather than as
+    // a branch condition, so it is a plain register across the levels
+    uint32_t okv = ok ? 1u : 0u;
+    uint32_t q = r.owner;
+    for (int i = l - 1; i >= 0; --i) {
+        const int32_t w = S.v[i * kWave + q];
+        const uint32_t below = ent_pid<SLIM>(S, i, q);
+        okv = w != r.v ? okv : 0u;
+        if (SB) {
+            const bool lt = ((sblt >> i) & 1u) != 0u, gt = ((sbgt >> i) & 1u) != 0u;
+            okv = (!lt || w < r.v) && (!gt || r.v < w) ? okv : 0u;
+        }
+        if ((bw >> i) & 1u) {
+            if (okv != 0u && static_cast<uint32_t>(i) != js) {
                 bool in;
                 if (SLIM) {
-                    in = slim_member<CG>(a, marea, r.run, lab, static_cast<uint32_t>(w), CG ? cg_slot(P, l, bw, i) : 0u,
-                                         r.v, probes, lookups, bytes);
+                    in = slim_member<CG>(a, marea, r.run, lab, static_cast<uint32_t>(w),
+                                         CG ? cg_slot(P, l, bw, i) : 0u, r.v, probes, lookups, bytes);
                 } else {
-                    uint32_t lo1[kLists] = {S.st[i * kWave + q]}, n1[kLists] = {ent_deg(S, i, q)};
-                    in = in_all_lists(a.col, lo1, n1, r.v, probes, bytes);
+                    const uint32_t d = ent_deg(S, i, q);
+                    in = d != 0u && in_list(a.col, S.st[i * kWave + q], d, r.v, probes, bytes);
                 }
-                if (!in) {
-                    ok = false;
-                    break;
-                }
+                okv = in ? okv : 0u;
             }
-            q = ent_pid<SLIM>(S, i, q);
+            if (ballot(okv != 0u) == 0ull) break;
         }
+        q = below;
     }
+    ok = okv != 0u;
     return ok;
 }
 
