@@ -391,6 +391,10 @@ def main() -> int:
         "solved_queries": len(solved) // max(1, args.steps),
         "idle_rate": 1.0 - sum(r.lanes_active for r in flat) / max(1, sum(r.lanes_issued for r in flat)),
         "steals_per_step": sum(r.steals for r in flat) // max(1, args.steps),
+        # membership tests (list bounds read) and the list entries they examined
+        "membership": {"lookups_per_step": sum(r.kernel_lookups for r in flat) // max(1, args.steps),
+                       "probes_per_lookup": sum(r.kernel_probes for r in flat) /
+                       max(1, sum(r.kernel_lookups for r in flat))},
         "roofline": roofline(flat, traffic_file_for(w.name)),
     }
     if not args.no_batched:
