@@ -181,6 +181,39 @@ def pmc_per_kernel(root: str, counter: str) -> dict:
     return out
 
 
+def merge_means(parts) -> tuple:
+    """(mean, count) pairs -> the mean over all of them and the total count."""
+    n = sum(c for _, c in parts)
+    return (sum(m * c for m, c in parts) / n if n else 0.0), n
+
+
+def summarize_trace(root: str, skip: int, take: int) -> str:
+    """Durations of the search kernel's dispatches from a rocprofv3 --kernel-trace run,
+    in dispatch order: all of them, and the window [skip, skip + take) -- the timed
+    steps of a bench run when skip = warmup x queries and take = steps x queries."""
+    import csv
+    rows = []
+    for path in _csvs(root, "kernel_trace.csv"):
+        for row in csv.DictReader(open(path)):
+            k = kernel_key(row.get("Kernel_Name", ""))
+            if k.startswith("search<"):
+                rows.append((int(row["Dispatch_Id"]), k,
+                             (float(row["End_Timestamp"]) - float(row["Start_Timestamp"])) / 1e6))
+    rows.sort()
+    win = rows[skip:skip + take]
+    lines = [f"search dispatches: {len(rows)}"]
+    for name, part in (("all", rows), (f"window [{skip}, {skip + take})", win)):
+        if not part:
+            continue
+        ms = [d for _, _, d in part]
+        by = {}
+        for _, k, d in part:
+            by.setdefault(k, []).append(d)
+        lines.append(f"{name}: dispatches={len(ms)} avg_ms={sum(ms) / len(ms):.4f} total_ms={sum(ms):.3f} " +
+                     " ".join(f"{k}: n={len(v)} avg_ms={sum(v) / len(v):.4f}" for k, v in sorted(by.items())))
+    return "\n".join(lines)
+
+
 def summarize_pmc(root: str) -> str:
     """Counters of a rocprofv3 --pmc run, summed over the search kernel's dispatches,
     with the ratios used to read them: the fraction of wave-cycles spent waiting,
@@ -228,11 +261,11 @@ def main() -> int:
                          "best plan per query and the model's pick measured side by side")
     ap.add_argument("--eval-cap", type=int, default=100_000_000, help="learned: cap of the evaluation runs")
     ap.add_argument("--eval-limit", type=float, default=2.0, help="learned: time limit of the evaluation runs (s)")
-    ap.add_argument("--margin", type=float, default=0.25,
+    ap.add_argument("--margin", type=float, default=0.5,
                     help="learned: predicted log2 gain a plan needs over the heuristic one to be proposed")
-    ap.add_argument("--probe-cap", type=int, default=1_000_000,
+    ap.add_argument("--probe-cap", type=int, default=10_000_000,
                     help="learned: matches each plan counts when measured runtime judges a proposal (0 = no judge)")
-    ap.add_argument("--probe-limit", type=float, default=0.05, help="learned: time limit of each judging run (s)")
+    ap.add_argument("--probe-limit", type=float, default=0.2, help="learned: time limit of each judging run (s)")
     ap.add_argument("--workload", default="large",
                     choices=["medium", "small", "large", "batch", "serve", "learned", "cg"],
                     help="batch = 10,000 mixed-size queries in shared launches (autotuned); "
@@ -274,6 +307,10 @@ def main() -> int:
                     help="after the timed steps, copy this many MiB device-to-device (counter calibration)")
     ap.add_argument("--summarize-stats", metavar="DIR", help="print the kernel table of a rocprofv3 --stats run")
     ap.add_argument("--summarize-pmc", metavar="DIR", help="print the search kernel's counters of a rocprofv3 --pmc run")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="print the search kernel's dispatch durations of a rocprofv3 --kernel-trace run")
+    ap.add_argument("--trace-skip", type=int, default=0, help="summarize-trace: dispatches before the window")
+    ap.add_argument("--trace-take", type=int, default=0, help="summarize-trace: dispatches in the window")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print HBM traffic per search launch from two rocprofv3 --pmc runs")
     ap.add_argument("--copy-bytes", type=int, default=0, help="size of the calibration copy in those runs")
@@ -285,12 +322,17 @@ def main() -> int:
     if args.summarize_pmc:
         print(summarize_pmc(args.summarize_pmc))
         return 0
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace, args.trace_skip, args.trace_take))
+        return 0
     if args.summarize_traffic:
         fetch = pmc_per_kernel(args.summarize_traffic[0], "FETCH_SIZE")
         write = pmc_per_kernel(args.summarize_traffic[1], "WRITE_SIZE")
-        key = next(k for k in fetch if k.startswith("search<"))
-        f_search, n_f = fetch[key]
-        w_search, n_w = write[key]
+        # every build of the search kernel the run dispatched (register budgets differ by
+        # query size), weighted by its dispatches, as the bench averages all its launches
+        key = "+".join(sorted(k for k in fetch if k.startswith("search<")))
+        f_search, n_f = merge_means([fetch[k] for k in fetch if k.startswith("search<")])
+        w_search, n_w = merge_means([write[k] for k in write if k.startswith("search<")])
         f_copy = fetch["copy"][0]
         w_copy = write["copy"][0]
         kf = args.copy_bytes / (f_copy * 1024.0)

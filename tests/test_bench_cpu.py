@@ -78,6 +78,7 @@ def test_stats_and_counter_summaries(tmp_path):
                          capture_output=True, text=True, check=True)
     kv = dict(line.split(": ", 1) for line in res.stdout.splitlines())
     assert kv["kernel"] == "search<slim,5w>"
+    assert bench.merge_means([(1000.0, 2), (4000.0, 1)]) == (2000.0, 3)
     assert float(kv["fetch_scale"]) == pytest.approx(2.0) and float(kv["write_scale"]) == pytest.approx(1.0)
     assert int(kv["traffic_bytes_per_launch"]) == 1000 * 1024 * 2 + 20 * 1024
 
@@ -103,3 +104,20 @@ def test_counter_summary_of_the_search_kernel(tmp_path):
     assert kv["SQ_WAVES"].startswith("400") and "(dispatches 2)" in kv["SQ_WAVES"]
     assert float(kv["wait_any_fraction"]) == 0.525   # (600 + 1500) / (1000 + 3000)
     assert kv["sq_insts_valu_per_wave"] == "50"
+
+
+def test_trace_window_summary(tmp_path):
+    """The timed window of a kernel trace: search dispatches in dispatch order, skip then take."""
+    rows = []
+    for i in range(6):  # dispatch ids out of order in the file; copies are not search dispatches
+        d = [5, 0, 3, 1, 4, 2][i]
+        rows.append([d, SEARCH.format(0, "true", "false", "false", 4 if d % 2 else 5), 0, (d + 1) * 1e6])
+    rows.append([9, "__amd_rocclr_copyBuffer", 0, 5e6])
+    _write_csv(str(tmp_path / "trace" / "run_kernel_trace.csv"),
+               ["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"], rows)
+    out = bench.summarize_trace(str(tmp_path / "trace"), 2, 3).splitlines()
+    assert out[0] == "search dispatches: 6"
+    assert out[1].startswith("all: dispatches=6 avg_ms=3.5000")
+    # window: dispatches 2, 3, 4 -> 3, 4, 5 ms
+    assert out[2].startswith("window [2, 5): dispatches=3 avg_ms=4.0000")
+    assert "search<slim,5w>: n=2 avg_ms=4.0000" in out[2] and "search<slim>: n=1 avg_ms=4.0000" in out[2]
