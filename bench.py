@@ -253,9 +253,10 @@ def main() -> int:
                     help="learned: training queries (4 candidate orders x 4 splits each, half on each graph)")
     ap.add_argument("--eval-queries", type=int, default=1000, help="learned: held-out queries")
     ap.add_argument("--eval-scale", type=int, default=24, choices=[20, 22, 24], help="learned: held-out graph")
-    ap.add_argument("--train-cap", type=int, default=100_000_000,
-                    help="learned: cap of the training runs (the evaluation's, so the times mean the same)")
-    ap.add_argument("--train-limit", type=float, default=0.1, help="learned: time limit of the training runs (s)")
+    ap.add_argument("--train-cap", type=int, default=10_000_000,
+                    help="learned: cap of the training runs (a tenth of the evaluation's: past launch overhead, "
+                         "and 50,000 runs fit in minutes)")
+    ap.add_argument("--train-limit", type=float, default=0.05, help="learned: time limit of the training runs (s)")
     ap.add_argument("--plan-table", action="store_true",
                     help="learned: also time every (order, split) plan of every held-out query once, for the "
                          "best plan per query and the model's pick measured side by side")
