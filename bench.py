@@ -428,6 +428,10 @@ def main() -> int:
         "intersected_edges_per_s": tasks / wall,
         # candidates actually read (label slices of C^L)
         "scanned_candidates_per_s": sum(r.scanned for r in flat) / wall,
+        "metric_notes": {"intersected_edges_per_s": "the paper's task count: sum of |C^L| over task groups "
+                                                    "(Sec. 4.1), not list entries read",
+                         "scanned_candidates_per_s": "candidate ids the kernel actually read (the label "
+                                                     "slice of C^L that can match)"},
         "query_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                              "mean": float(lat.mean())},
         "outcomes_per_step": outcomes,
@@ -772,6 +776,8 @@ def bench_learned(args, gm) -> int:
         mine = {}
         probe_ms = np.zeros(len(qids))
         for i, qid in enumerate(qids):
+            if i % 100 == 0:
+                log(f"  choosing plans: {i} queries ({time.time() - t:.0f} s)")
             heuristic[qid] = (e.get_order(qid), e.get_split(qid))
             co, cs, _, probe_ms[i] = e.choose_plan(model, qid, splits=splits, max_orders=n_orders, seed=i,
                                                    margin=args.margin, probe_cap=args.probe_cap,
@@ -806,6 +812,8 @@ def bench_learned(args, gm) -> int:
                 t0 = time.perf_counter()
                 res, info = e.count_batch(qids, cap=cap, time_limit_s=limit)
                 batched[which].append((time.perf_counter() - t0, info, res))
+                log(f"  batched launch, {'heuristic' if which == 'h' else 'learned'} plans: "
+                    f"{batched[which][-1][0]:.1f} s")
         table = None
         if args.plan_table:
             # every plan of every query once: what the best choice per query would save
@@ -825,7 +833,7 @@ def bench_learned(args, gm) -> int:
                 tot["model"] += float(ts[[x[2] for x in times]].min())
                 tot["best"] += float(ts.min())
                 pick_rank.append(int((ts < ts[[x[2] for x in times]].min()).sum()))
-                if (i + 1) % 250 == 0:
+                if (i + 1) % 25 == 0:
                     log(f"  timed every plan of {i + 1} queries ({time.time() - t:.0f} s)")
             table = {"total_ms": tot, "plans_per_query": len(times),
                      "model_pick_rank_mean": float(np.mean(pick_rank)),
