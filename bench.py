@@ -257,9 +257,11 @@ def main() -> int:
                     help="learned: cap of the training runs (a tenth of the evaluation's: past launch overhead, "
                          "and 50,000 runs fit in minutes)")
     ap.add_argument("--train-limit", type=float, default=0.05, help="learned: time limit of the training runs (s)")
-    ap.add_argument("--plan-table", action="store_true",
-                    help="learned: also time every (order, split) plan of every held-out query once, for the "
-                         "best plan per query and the model's pick measured side by side")
+    ap.add_argument("--plan-table", type=int, default=0, metavar="N",
+                    help="learned: also time every (order, split) plan of every N-th held-out query once "
+                         "(0 = off), for the best plan per query and the model's pick measured side by side")
+    ap.add_argument("--plan-table-limit", type=float, default=0.5,
+                    help="learned: time limit of each plan-table run (s); a plan cut off counts at the limit")
     ap.add_argument("--eval-cap", type=int, default=100_000_000, help="learned: cap of the evaluation runs")
     ap.add_argument("--eval-limit", type=float, default=2.0, help="learned: time limit of the evaluation runs (s)")
     ap.add_argument("--margin", type=float, default=0.5,
@@ -815,17 +817,18 @@ def bench_learned(args, gm) -> int:
                 log(f"  batched launch, {'heuristic' if which == 'h' else 'learned'} plans: "
                     f"{batched[which][-1][0]:.1f} s")
         table = None
-        if args.plan_table:
-            # every plan of every query once: what the best choice per query would save
+        if args.plan_table > 0:
+            # every plan of a sample of the queries once: what the best choice per query would save
             tot = {"heuristic": 0.0, "model": 0.0, "best": 0.0}
             pick_rank = []
-            for i, qid in enumerate(qids):
+            sample = list(enumerate(qids))[::args.plan_table]
+            for n_done, (i, qid) in enumerate(sample):
                 times = []
                 for o in e.candidate_orders(qid, max_orders=n_orders, seed=i):
                     for sp in splits:
                         e.set_order(qid, o)
                         e.set_split(qid, sp)
-                        r = e.count(qid, cap=cap, time_limit_s=limit)
+                        r = e.count(qid, cap=cap, time_limit_s=args.plan_table_limit)
                         times.append((r.search_ms, np.array_equal(o, heuristic[qid][0]) and sp == heuristic[qid][1],
                                       np.array_equal(o, mine[qid][0]) and sp == mine[qid][1]))
                 ts = np.array([x[0] for x in times])
@@ -833,11 +836,14 @@ def bench_learned(args, gm) -> int:
                 tot["model"] += float(ts[[x[2] for x in times]].min())
                 tot["best"] += float(ts.min())
                 pick_rank.append(int((ts < ts[[x[2] for x in times]].min()).sum()))
-                if (i + 1) % 25 == 0:
-                    log(f"  timed every plan of {i + 1} queries ({time.time() - t:.0f} s)")
-            table = {"total_ms": tot, "plans_per_query": len(times),
+                if (n_done + 1) % 10 == 0:
+                    log(f"  timed every plan of {n_done + 1} queries ({time.time() - t:.0f} s)")
+            # the pick of the last evaluation, for the queries sampled
+            table = {"queries": len(sample), "total_ms": tot, "plans_per_query": len(times),
                      "model_pick_rank_mean": float(np.mean(pick_rank)),
-                     "note": "each plan timed once, one query at a time; rank 0 = the fastest plan"}
+                     "time_limit_s": args.plan_table_limit,
+                     "note": "every plan of every sampled query timed once, one query at a time, with the "
+                             "time limit above; rank 0 = the fastest plan"}
         bh, bl = batched["h"][-1][2], batched["l"][-1][2]
         same_batched = all((a.count, a.outcome) == (b.count, b.outcome) for a, b in zip(bh, bl)
                            if a.outcome != gm.GM_TIMEOUT and b.outcome != gm.GM_TIMEOUT)
