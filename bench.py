@@ -219,17 +219,17 @@ def summarize_pmc(root: str) -> str:
     with the ratios used to read them: the fraction of wave-cycles spent waiting,
     and instructions per wave."""
     import csv
-    sums, dispatches, key = {}, {}, None
+    sums, dispatches, keys = {}, {}, set()
     for path in _csvs(root, "counter_collection.csv"):
         for row in csv.DictReader(open(path)):
             k = kernel_key(row.get("Kernel_Name", ""))
             if not k.startswith("search<"):
                 continue
-            key = k
+            keys.add(k)  # every build of the search kernel the run dispatched
             name = row["Counter_Name"]
             sums[name] = sums.get(name, 0.0) + float(row["Counter_Value"])
             dispatches.setdefault(name, set()).add(row.get("Dispatch_Id", row.get("Correlation_Id", "")))
-    lines = [f"kernel: {key}", f"kernel_sha: {kernel_sha()}"]
+    lines = [f"kernel: {'+'.join(sorted(keys)) or None}", f"kernel_sha: {kernel_sha()}"]
     for name in sorted(sums):
         lines.append(f"{name}: {sums[name]:.0f}  (dispatches {len(dispatches[name])})")
     if sums.get("SQ_WAVE_CYCLES"):
