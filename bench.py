@@ -270,11 +270,14 @@ def main() -> int:
                     help="learned: matches each plan counts when measured runtime judges a proposal (0 = no judge)")
     ap.add_argument("--probe-limit", type=float, default=0.2, help="learned: time limit of each judging run (s)")
     ap.add_argument("--workload", default="large",
-                    choices=["medium", "small", "large", "batch", "serve", "learned", "cg"],
+                    choices=["medium", "small", "large", "batch", "serve", "learned", "cg", "dense"],
                     help="batch = 10,000 mixed-size queries in shared launches (autotuned); "
                          "serve = the same queries as a Poisson request stream through the server; "
-                         "cg = large queries searched on G and on the candidate graph G'")
+                         "cg = large queries searched on G and on the candidate graph G'; "
+                         "dense = small dense queries on a dense graph under each LDS-staging ratio")
     ap.add_argument("--cg-per-size", type=int, default=20, help="cg: queries of each size (16, 24, 32)")
+    ap.add_argument("--dense-vertices", type=int, default=8192,
+                    help="dense: vertices of the G(n, M) graph (average degree 192)")
     ap.add_argument("--cg-graph", default="rmat", choices=["rmat", "er"],
                     help="cg: R-MAT scale 20 (hubs) or G(n, M) with 2^20 vertices and average degree 16")
     ap.add_argument("--load", type=float, default=0.7,
@@ -366,6 +369,8 @@ def main() -> int:
         return bench_learned(args, gm)
     if args.workload == "cg":
         return bench_cg(args, gm)
+    if args.workload == "dense":
+        return bench_dense(args, gm)
 
     t = time.time()
     w = make_workload(args.workload, args.queries, args.query_stride)
@@ -892,6 +897,71 @@ def bench_learned(args, gm) -> int:
         "batched": {"heuristic": batch_summary("h"), "learned": batch_summary("l"), "same_counts": bool(same_batched)},
         "model": {"train_mse": loss, "heldout_mse": val_mse, "target_variance": float(np.var(y))},
         "plan_table": table,
+        "same_counts": bool(same),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_dense(args, gm) -> int:
+    """LDS-staged intersection where it applies: G(n, M) with 8,192 vertices (or
+    --dense-vertices), average degree 192 (no vertex reaches the hub degree) and one
+    label, so every list is a
+    whole neighbour list of about 192 entries and a parent's candidates fill runs of
+    64 lanes; dense queries of 4 and 5 vertices.  Every query is counted alone under
+    merge ratios never, 1, 2, 4 and 8; counts must agree, total time is compared."""
+    from paper_2604_10601_amd import workloads as wl
+    n, deg = args.dense_vertices, 192
+    rp, col = wl.erdos_renyi(n, n * deg // 2, seed=7301)
+    g = wl.Graph(rp, col, np.zeros(n, dtype=np.int32))
+    shapes = {"triangle": [(0, 1), (1, 2), (2, 0)],
+              "4-cycle": [(0, 1), (1, 2), (2, 3), (3, 0)],
+              "diamond": [(0, 1), (1, 2), (2, 3), (3, 0), (0, 2)],
+              "4-clique": [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)],
+              "5-cycle with chord": [(0, 1), (1, 2), (2, 3), (3, 4), (4, 0), (0, 2)]}
+    queries = []
+    for name, edges in shapes.items():
+        k = 1 + max(max(e) for e in edges)
+        pairs = np.asarray([sorted(e) for e in edges], dtype=np.int32)
+        queries.append((name, wl.Query(k, pairs, np.zeros(k, dtype=np.int32))))
+    cap, limit = 10**10, 20.0
+    runs = {}
+    for ratio in (-1, 1, 2, 4, 8):
+        with gm.Engine(device=0, merge_ratio=ratio) as e:
+            e.load(g)
+            qids = [e.add(q) for _, q in queries]
+            e.count(qids[0], cap=cap, time_limit_s=limit)  # warm-up
+            res = [e.count(qid, cap=cap, time_limit_s=limit) for qid in qids]
+        runs[ratio] = res
+        log(f"merge ratio {ratio}: {sum(r.search_ms for r in res):.1f} ms")
+    base = runs[-1]
+    same = all((a.count, a.outcome) == (b.count, b.outcome) for r in runs.values() for a, b in zip(base, r))
+    per = {str(ratio): {"total_ms": float(sum(r.search_ms for r in res)),
+                        "per_query_ms": {name: float(r.search_ms) for (name, _), r in zip(queries, res)},
+                        "probes_per_lookup": float(sum(r.kernel_probes for r in res) /
+                                                   max(1, sum(r.kernel_lookups for r in res)))}
+           for ratio, res in runs.items()}
+    best = min(runs, key=lambda x: per[str(x)]["total_ms"])
+    out = {
+        "metric": "embeddings/s",
+        "value": sum(r.count for r in runs[best]) / (per[str(best)]["total_ms"] / 1000.0),
+        "unit": "embeddings/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": per[str(best)]["total_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"er{n}_d192_1label_dense4-5", "graph_vertices": n, "graph_edges": g.num_edges,
+                   "queries": [name for name, _ in queries], "cap": cap, "time_limit_s": limit},
+        "by_merge_ratio": per,
+        "counts": {name: int(r.count) for (name, _), r in zip(queries, base)},
+        "outcomes": {name: int(r.outcome) for (name, _), r in zip(queries, base)},
+        "best_ratio": best,
+        "speedup_best_vs_never": per["-1"]["total_ms"] / per[str(best)]["total_ms"],
         "same_counts": bool(same),
     }
     print(json.dumps(out), flush=True)
