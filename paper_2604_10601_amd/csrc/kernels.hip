@@ -442,9 +442,11 @@ __device__ __forceinline__ uint64_t lane_range(uint32_t lo, uint32_t hi) {
 // its diagonal, then walks the segment.  When the walk takes A[x] it has just
 // passed every entry of B below A[x], so A[x] is in B iff the next entry of B
 // equals it; lane j writes that into flag x, and each lane reads its own flag.
-// One wavefront's LDS operations complete in issue order, so the writes of one
-// step are seen by the reads of the next.  Adds the entries this lane loaded to
-// probes and their bytes to bytes.
+// A list longer than twice the run makes that walk long, so there each lane
+// bisects the staged copy instead: merge path or binary search, picked by the
+// ratio of list length to run.  One wavefront's LDS operations complete in
+// issue order, so the writes of one step are seen by the reads of the next.
+// Adds the entries this lane loaded to probes and their bytes to bytes.
 __device__ __forceinline__ bool merge_member(const int32_t *__restrict__ list, uint32_t n, uint8_t *area,
                                              uint32_t slots, uint32_t run, int32_t v, uint32_t &probes,
                                              uint32_t &bytes) {
@@ -460,6 +462,18 @@ __device__ __forceinline__ bool merge_member(const int32_t *__restrict__ list, u
         B[k] = list[k];
         ++probes;
         bytes += 4u;
+    }
+    if (n > 2u * r) {
+        // a list long against the run: each lane bisects the staged copy in LDS
+        // (branch-free lower bound), which costs log2(n) LDS reads instead of the
+        // merge walk's (n + r) / r steps after a diagonal search
+        uint32_t lo = 0, len = n;
+        while (len > 1u) {
+            const uint32_t h = len >> 1;
+            lo = B[lo + h - 1u] < v ? lo + h : lo;
+            len -= h;
+        }
+        return B[lo] == v;
     }
     const uint32_t total = r + n;
     const uint32_t seg = (total + r - 1u) / r;
