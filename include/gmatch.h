@@ -76,10 +76,13 @@ typedef struct {
     int32_t waves_per_cu;
     /* 1 = skip the symmetry check of gm_load_graph (trusted input). */
     int32_t skip_symmetry_check;
-    /* Per-wavefront stack layout in LDS: 1 = full (20 B per level and lane;
-     * entries cache their neighbour-list range), 2 = slim (13 B; membership
-     * tests bisect label slices, whose bounds cost one load), 0 = default
-     * (slim: it keeps more wavefronts per CU and bisects shorter ranges). */
+    /* Per-wavefront stack layout in LDS: 1 = full (12 B per level and lane;
+     * entries cache their neighbour-list range), 2 = slim (4 B: vertex and
+     * parent lane in one word; membership tests bisect label slices, whose
+     * bounds cost one load), 0 = default (slim: it keeps more wavefronts per CU
+     * and bisects shorter ranges).  The slim layout holds vertex ids below
+     * 2^24; on a graph with more vertices every search uses the full layout,
+     * and a candidate-graph engine (which needs slim) refuses to load it. */
     int32_t stack_layout;
     /* 1 = do not build label-partitioned neighbour lists (every task group then
      * scans its whole list and the label filter rejects the rest). */

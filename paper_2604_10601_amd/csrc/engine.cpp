@@ -439,9 +439,11 @@ void free_graph(gm_engine *e) {
 }
 
 // Stack layout: the option, else slim (measured faster at 8 and at 12-32 vertices).
+// A slim stack entry holds a vertex id in 24 bits, so larger graphs use the full one.
+constexpr int32_t kSlimMaxVertices = 1 << 24;
 bool use_slim(const gm_engine *e, int32_t k) {
     (void)k;
-    return e->opt.stack_layout != 1;
+    return e->opt.stack_layout != 1 && e->n <= kSlimMaxVertices;
 }
 
 
@@ -2084,6 +2086,8 @@ gm_status gm_load_graph(gm_engine *e, int32_t n, const int64_t *row_ptr, const i
     if (!e) return GM_ERR_ARG;
     std::lock_guard<std::mutex> lk(e->mu);
     if (n < 0) return e->fail(GM_ERR_ARG, "n must be >= 0");
+    if (e->opt.candidate_graph && n > kSlimMaxVertices)
+        return e->fail(GM_ERR_GRAPH, "the candidate-graph search holds vertex ids in 24 bits: at most 2^24 vertices");
     if (!row_ptr || (n > 0 && !labels)) return e->fail(GM_ERR_ARG, "row_ptr and labels must not be null");
     if (e->servers.load() > 0) return e->fail(GM_ERR_STATE, "a server is open on this engine");
     if (row_ptr[0] != 0) return e->fail(GM_ERR_GRAPH, "row_ptr[0] must be 0");
@@ -2148,6 +2152,8 @@ gm_status gm_load_graph_device(gm_engine *e, int32_t n, const void *row_ptr, int
     std::lock_guard<std::mutex> lk(e->mu);
     if (e->device < 0) return e->fail(GM_ERR_DEVICE, "a host-only engine cannot load device buffers");
     if (n < 0) return e->fail(GM_ERR_ARG, "n must be >= 0");
+    if (e->opt.candidate_graph && n > kSlimMaxVertices)
+        return e->fail(GM_ERR_GRAPH, "the candidate-graph search holds vertex ids in 24 bits: at most 2^24 vertices");
     if (row_ptr_bytes != 4 && row_ptr_bytes != 8) return e->fail(GM_ERR_ARG, "row_ptr_bytes must be 4 or 8");
     if (!row_ptr || (n > 0 && !labels)) return e->fail(GM_ERR_ARG, "row_ptr and labels must not be null");
     if (e->servers.load() > 0) return e->fail(GM_ERR_STATE, "a server is open on this engine");

@@ -152,22 +152,22 @@ __device__ __forceinline__ bool in_list(const int32_t *__restrict__ col, uint32_
 // lane q) of a plane is at [i * 64 + q].  Two layouts:
 //   full (12 B per (level, lane)): the entry caches its vertex's id-sorted list
 //     start and degree, so membership tests bisect N(w) with no extra load;
-//   slim (5 B): the entry keeps only its vertex and parent lane; membership
-//     tests bisect the label slice of N(w) in lcol (ids ascending within a
-//     label), whose bounds cost one 8-byte load per list but which is shorter
-//     than N(w).
+//   slim (4 B): the entry keeps only its vertex and parent lane, packed in one
+//     word (graphs of at most 2^24 vertices); membership tests bisect the
+//     label slice of N(w) in lcol (ids ascending within a label), whose bounds
+//     cost one 8-byte load per list but which is shorter than N(w).
 // The task group of each parent lane (its candidate slice: start in lcol and
 // length << 8 | source level) is needed only while its level is the one being
 // scattered, so the current level's sits in two registers per lane, and a
 // descent parks it in the wavefront's area of device memory (Slice, 8 B per
 // (level, lane), one coalesced 512-byte store) until the backtrack that loads
 // it again.  That keeps 512 B per level out of LDS: a 32-vertex query's stack
-// takes 10.8 KB instead of 27 KB, so 14 wavefronts fit per CU instead of 5.
+// takes 8.8 KB instead of 27 KB, so 17 wavefronts fit per CU instead of 5.
 struct WaveStack {
-    int32_t *v;       // data vertex of the task at (level, lane)
+    uint32_t *e;      // slim: data vertex | lane of the parent entry at level - 1 << 24
+    int32_t *v;       // full: data vertex of the task at (level, lane)
     uint32_t *st;     // full: start of N(v) in col[] (ids ascending)
     uint32_t *dp;     // full: |N(v)| << 8 | lane of the parent entry at level - 1
-    uint8_t *pid;     // slim: lane of the parent entry at level - 1
     uint32_t *cur_j;  // per level: scatter cursor, offset in the current parent's slice
     uint32_t *cur_i;  //   ... current parent lane (64 = level exhausted)
     uint32_t *end_j;  // per level: end of the task range, offset in parent end_i's slice
@@ -176,7 +176,7 @@ struct WaveStack {
 };
 
 __host__ __device__ constexpr size_t stack_bytes(int levels, bool slim) {
-    return static_cast<size_t>(levels) * (kWave * (slim ? 5u : 12u) + 16u) + kWave;
+    return static_cast<size_t>(levels) * (kWave * (slim ? 4u : 12u) + 16u) + kWave;
 }
 
 // Task group of one parent lane at one level: cs = start of its candidate slice
@@ -190,18 +190,18 @@ __device__ __forceinline__ WaveStack carve_stack(uint8_t *base, int levels) {
     WaveStack S;
     const size_t plane = static_cast<size_t>(levels) * kWave * 4u;
     uint8_t *p = base;
-    S.v = reinterpret_cast<int32_t *>(p);
-    p += plane;
     if (SLIM) {
+        S.e = reinterpret_cast<uint32_t *>(p);
+        S.v = nullptr;
         S.st = nullptr;
         S.dp = nullptr;
-        S.pid = p;
-        p += static_cast<size_t>(levels) * kWave;
+        p += plane;
     } else {
-        S.st = reinterpret_cast<uint32_t *>(p);
-        S.dp = reinterpret_cast<uint32_t *>(p + plane);
-        S.pid = nullptr;
-        p += 2 * plane;
+        S.e = nullptr;
+        S.v = reinterpret_cast<int32_t *>(p);
+        S.st = reinterpret_cast<uint32_t *>(p + plane);
+        S.dp = reinterpret_cast<uint32_t *>(p + 2 * plane);
+        p += 3 * plane;
     }
     p = base + (static_cast<size_t>(p - base) + 3u) / 4u * 4u;
     uint32_t *lv = reinterpret_cast<uint32_t *>(p);
@@ -215,18 +215,30 @@ __device__ __forceinline__ WaveStack carve_stack(uint8_t *base, int levels) {
 
 __device__ __forceinline__ uint32_t ent_deg(const WaveStack &S, int i, uint32_t q) { return S.dp[i * kWave + q] >> 8; }
 
+// The slim entry packs the vertex (ids below 2^24: the engine picks the full
+// layout for larger graphs) and the parent lane into one word, so one LDS read
+// gives both.
+constexpr uint32_t kSlimVertexMask = 0xffffffu;
+
+template <bool SLIM>
+__device__ __forceinline__ int32_t ent_v(const WaveStack &S, int i, uint32_t q) {
+    if (SLIM) return static_cast<int32_t>(S.e[i * kWave + q] & kSlimVertexMask);
+    return S.v[i * kWave + q];
+}
+
 template <bool SLIM>
 __device__ __forceinline__ uint32_t ent_pid(const WaveStack &S, int i, uint32_t q) {
-    if (SLIM) return S.pid[i * kWave + q];
+    if (SLIM) return S.e[i * kWave + q] >> 24;
     return S.dp[i * kWave + q] & 0xffu;
 }
 
 template <bool SLIM>
 __device__ __forceinline__ void push_entry(WaveStack &S, int i, uint32_t lane, int32_t v, VInfo vi, uint32_t pid) {
-    S.v[i * kWave + lane] = v;
     if (SLIM) {
-        S.pid[i * kWave + lane] = static_cast<uint8_t>(pid);
+        // lanes without a task push -1: masked, never read as a match
+        S.e[i * kWave + lane] = (static_cast<uint32_t>(v) & kSlimVertexMask) | (pid << 24);
     } else {
+        S.v[i * kWave + lane] = v;
         S.st[i * kWave + lane] = vi.x;
         S.dp[i * kWave + lane] = (vi_deg(vi) << 8) | pid;
     }
@@ -274,7 +286,7 @@ __device__ __forceinline__ Gen generate_tasks(WaveStack &S, const SearchArgs &a,
                     // candidate graph: N(w) restricted to C(phi[l]), one list per query edge
                     const uint32_t *o =
                         a.gbounds + 2ull * (static_cast<unsigned long long>(cg_slot(P, l, bw, i)) * a.gn +
-                                            static_cast<uint32_t>(S.v[i * kWave + q]));
+                                            static_cast<uint32_t>(ent_v<SLIM>(S, i, q)));
                     sa = o[0];
                     sn = o[1] - sa;
                     d = sn;
@@ -283,7 +295,7 @@ __device__ __forceinline__ Gen generate_tasks(WaveStack &S, const SearchArgs &a,
                 } else if (SLIM) {
                     // list bounds and slice bounds: three independent loads (the slice's
                     // two bounds are adjacent), all issued before any is used
-                    const uint32_t *o = a.loff + static_cast<unsigned long long>(S.v[i * kWave + q]) * stride;
+                    const uint32_t *o = a.loff + static_cast<unsigned long long>(ent_v<SLIM>(S, i, q)) * stride;
                     uint2 sb;
                     __builtin_memcpy(&sb, o + lab, sizeof(sb));
                     const uint32_t row0 = o[0];
@@ -296,7 +308,7 @@ __device__ __forceinline__ Gen generate_tasks(WaveStack &S, const SearchArgs &a,
                 } else {
                     d = ent_deg(S, i, q);
                     if (sliced) {
-                        const uint32_t *o = a.loff + static_cast<unsigned long long>(S.v[i * kWave + q]) * stride + lab;
+                        const uint32_t *o = a.loff + static_cast<unsigned long long>(ent_v<SLIM>(S, i, q)) * stride + lab;
                         sa = o[0];
                         sn = o[1] - sa;
                         ++g.lookups;
@@ -579,7 +591,7 @@ __device__ __forceinline__ bool process(WaveStack &S, const SearchArgs &a, PlanP
     uint32_t okv = ok ? 1u : 0u;
     uint32_t q = r.owner;
     for (int i = l - 1; i >= 0; --i) {
-        const int32_t w = S.v[i * kWave + q];
+        const int32_t w = ent_v<SLIM>(S, i, q);
         const uint32_t below = ent_pid<SLIM>(S, i, q);
         okv = w != r.v ? okv : 0u;
         if (SB) {
@@ -737,7 +749,7 @@ __device__ uint32_t donate(WaveStack &S, const SearchArgs &a, PlanPtr P, int32_t
         if (mine) {
             uint32_t q = lane;
             for (int i = L - 1; i >= 0; --i) {
-                store_agent(&mb.rows[lane * kMaxK + i], S.v[(i) * kWave + (q)]);
+                store_agent(&mb.rows[lane * kMaxK + i], ent_v<SLIM>(S, i, q));
                 q = ent_pid<SLIM>(S, i, q);
             }
         }
@@ -772,6 +784,7 @@ enum Mode { kCount = 0, kEnumerate = 1, kExpand = 2 };
 // Size bound of the level after an expansion, for one new row (positions 0..d,
 // position d being the row's candidate): its smallest label slice for position
 // d + 1 among that position's backward neighbours.
+template <bool SLIM>
 __device__ __forceinline__ uint32_t next_level_bound(const WaveStack &S, const SearchArgs &a, PlanPtr P, int d,
                                                      const Round &r) {
     const uint32_t bw = P->bwd[d + 1];
@@ -779,7 +792,7 @@ __device__ __forceinline__ uint32_t next_level_bound(const WaveStack &S, const S
     uint32_t best = 0xffffffffu;
     for (int i = 0; i <= d; ++i) {
         if (!((bw >> i) & 1u)) continue;
-        const int32_t w = i == d ? r.v : S.v[(i) * kWave + (r.owner)];
+        const int32_t w = i == d ? r.v : ent_v<SLIM>(S, i, r.owner);
         const uint32_t *o = a.loff + static_cast<unsigned long long>(w) * a.loff_stride + lab;
         const uint32_t n = o[1] - o[0];
         best = n < best ? n : best;
@@ -1203,9 +1216,9 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                         if (staged + nv > static_cast<uint32_t>(kStageRows)) flush_stage(stage, staged, d + 1, a);
                         if (ok) {
                             int32_t *row = stage + (staged + popc_below(m)) * static_cast<uint32_t>(d + 1);
-                            for (int i = 0; i < d; ++i) row[i] = S.v[(i) * kWave + (r.owner)];
+                            for (int i = 0; i < d; ++i) row[i] = ent_v<SLIM>(S, i, r.owner);
                             row[d] = r.v;
-                            if (a.measure_next) my_bound += next_level_bound(S, a, P, d, r);
+                            if (a.measure_next) my_bound += next_level_bound<SLIM>(S, a, P, d, r);
                             t.bytes_run += 4u * static_cast<uint32_t>(d + 1);  // the row, written at the flush
                         }
                         staged += nv;
@@ -1214,11 +1227,11 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                         const unsigned long long slot = b0 + popc_below(m);
                         if (ok && slot < a.out_cap) {
                             int32_t *row = a.out + slot * static_cast<unsigned long long>(d + 1);
-                            for (int i = 0; i < d; ++i) row[i] = S.v[(i) * kWave + (r.owner)];
+                            for (int i = 0; i < d; ++i) row[i] = ent_v<SLIM>(S, i, r.owner);
                             row[d] = r.v;
                             t.bytes_run += 4u * static_cast<uint32_t>(d + 1);
                         }
-                        if (ok && a.measure_next) my_bound += next_level_bound(S, a, P, d, r);
+                        if (ok && a.measure_next) my_bound += next_level_bound<SLIM>(S, a, P, d, r);
                     }
                 }
             } else if (l == k - 1) {
@@ -1230,7 +1243,7 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                         row[P->phi[l]] = r.v;
                         uint32_t q = r.owner;
                         for (int i = l - 1; i >= 0; --i) {
-                            row[P->phi[i]] = S.v[(i) * kWave + (q)];
+                            row[P->phi[i]] = ent_v<SLIM>(S, i, q);
                             q = ent_pid<SLIM>(S, i, q);
                         }
                         t.bytes_run += 4u * static_cast<uint32_t>(k);
