@@ -72,3 +72,44 @@ def test_large_queries_both_layouts(layout):
         for i, q in enumerate(qs):
             qid = e.add(q)
             same(e.count(qid), oracle.count(g, q, order=e.get_order(qid)), (layout, i, q.k))
+
+
+def test_graph_above_2_24_vertices_takes_the_full_layout():
+    """The slim stack keeps vertex ids in 24 bits, so a graph of more than 2^24
+    vertices must be searched with the full layout.  Matches here use vertices
+    above 2^24 (a dense random cluster placed there, joined to a few low ids), so
+    truncated ids would change counts and rows; both are compared with the
+    oracle, and a candidate-graph engine refuses the graph."""
+    n = (1 << 24) + 64
+    rng = np.random.default_rng(2424)
+    hi = np.arange((1 << 24), n, dtype=np.int64)
+    lo = np.arange(0, 16, dtype=np.int64)
+    verts = np.concatenate([lo, hi])
+    pairs = set()
+    for _ in range(900):
+        a, b = rng.choice(verts, size=2, replace=False)
+        pairs.add((int(min(a, b)), int(max(a, b))))
+    src = np.array([a for a, b in pairs], dtype=np.int64)
+    dst = np.array([b for a, b in pairs], dtype=np.int64)
+    rp, col = wl.csr_from_pairs(n, src, dst)
+    labels = np.zeros(n, dtype=np.int32)
+    labels[verts] = rng.integers(0, 2, size=verts.shape[0])
+    g = wl.Graph(rp, col, labels)
+    qs = [S.query(3, [(0, 1), (1, 2), (2, 0)], [0, 0, 1]), S.query(4, [(0, 1), (1, 2), (2, 3), (3, 0)], [0, 1, 0, 1]),
+          S.query(4, [(0, 1), (1, 2), (2, 3), (3, 0), (0, 2)], [1, 1, 0, 0])]
+    with gm.Engine(device=0) as e:
+        e.load(g)
+        for i, q in enumerate(qs):
+            qid = e.add(q)
+            r = e.count(qid)
+            o = oracle.count(g, q, order=e.get_order(qid))
+            same(r, o, ("above 2^24", i))
+            assert o.count > 0
+            rows = e.enumerate(qid, o.count + 1).matches
+            want = oracle.enumerate_sorted(g, q, o.count + 1, order=e.get_order(qid))
+            assert np.array_equal(rows[np.lexsort(rows.T[::-1])], want), i
+            assert rows.max() >= (1 << 24), "the matches should reach the ids above 2^24"
+    with gm.Engine(device=0, candidate_graph=True) as e:
+        with pytest.raises(gm.GmError) as ei:
+            e.load(g)
+        assert ei.value.status == gm.GM_ERR_GRAPH
