@@ -162,7 +162,7 @@ __device__ __forceinline__ bool in_list(const int32_t *__restrict__ col, uint32_
 // descent parks it in the wavefront's area of device memory (Slice, 8 B per
 // (level, lane), one coalesced 512-byte store) until the backtrack that loads
 // it again.  That keeps 512 B per level out of LDS: a 32-vertex query's stack
-// takes 8.8 KB instead of 27 KB, so 17 wavefronts fit per CU instead of 5.
+// takes 8.6 KB instead of 27 KB, so 18 wavefronts fit per CU instead of 5.
 struct WaveStack {
     uint32_t *e;      // slim: data vertex | lane of the parent entry at level - 1 << 24
     int32_t *v;       // full: data vertex of the task at (level, lane)
@@ -175,8 +175,15 @@ struct WaveStack {
     uint8_t *own;     // scatter scratch: parent starting at each slot
 };
 
+// Entry planes of a stack for queries of up to `levels` positions: the last
+// position is counted (or written out) where it is tested and never pushed, so
+// levels - 1 planes hold every entry (one for a one-vertex query, whose pool rows
+// are its matches).  The scatter cursors are per position, the last included.
+__host__ __device__ constexpr int stack_planes(int levels) { return levels > 1 ? levels - 1 : 1; }
+
 __host__ __device__ constexpr size_t stack_bytes(int levels, bool slim) {
-    return static_cast<size_t>(levels) * (kWave * (slim ? 4u : 12u) + 16u) + kWave;
+    return static_cast<size_t>(stack_planes(levels)) * kWave * (slim ? 4u : 12u) +
+           static_cast<size_t>(levels) * 16u + kWave;
 }
 
 // Task group of one parent lane at one level: cs = start of its candidate slice
@@ -188,7 +195,7 @@ struct Slice {
 template <bool SLIM>
 __device__ __forceinline__ WaveStack carve_stack(uint8_t *base, int levels) {
     WaveStack S;
-    const size_t plane = static_cast<size_t>(levels) * kWave * 4u;
+    const size_t plane = static_cast<size_t>(stack_planes(levels)) * kWave * 4u;
     uint8_t *p = base;
     if (SLIM) {
         S.e = reinterpret_cast<uint32_t *>(p);
