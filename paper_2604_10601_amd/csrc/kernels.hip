@@ -857,31 +857,57 @@ __device__ __forceinline__ int32_t find_query(const SearchArgs &a, PlanPtr P, in
     return lo;
 }
 
-// Work counters of the query a wavefront is on; per-lane fields are summed over
-// the wavefront when flushed.
+// Indices of a wavefront's 64-bit counter totals.
+enum { kTotTasks, kTotScanned, kTotLookups, kTotProbes, kTotGroups, kTotActive, kTotIssued, kTotSteals,
+       kTotBytes, kTotBytesLate, kTotals };
+
+// Work counters of the query a wavefront is on.  The per-lane and per-window
+// counters are 32-bit and cover at most 32 rounds (a task group's |C^L| is below
+// 2^24, so 32 of them fit); every 32 rounds, and when a work item is claimed or
+// the wavefront moves to another query, they are summed over the wavefront and
+// added to its 64-bit totals.  The totals and the match count are wave-uniform,
+// so they sit in scalar registers and cost no vector registers per lane.
 struct Tally {
-    uint64_t tasks, scanned, lookups, probes;  // per lane
-    uint32_t probes_run, lookups_run;          // per lane, folded into the above every 32 rounds
+    uint32_t tasks_run, scanned_run;           // per lane since the last fold
+    uint32_t probes_run, lookups_run;          // per lane since the last fold
     uint32_t bytes_run;                        // per lane: device-memory bytes requested since the last fold
-    uint64_t groups, active, issued, count, steals;  // wave-uniform
-    uint64_t bytes, bytes_late;                // wave-uniform: folded bytes; those of windows that saw an abort
+    uint32_t groups_run, active_run, issued_run;  // wave-uniform, since the last fold
+    uint64_t count;                            // wave-uniform: matches not yet added to the query's count
+    uint64_t tot[kTotals];                     // wave-uniform totals
 };
+
+// Sum over the wavefront as a wave-uniform (scalar) value.
+__device__ __forceinline__ uint64_t wave_total64(uint64_t x) {
+    x = wave_sum64(x);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x >> 32));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
 
 __device__ __forceinline__ uint32_t wave_sum32(uint32_t x) {
     for (int off = 32; off >= 1; off >>= 1) x += shfl(x, lane_id() ^ static_cast<uint32_t>(off));
     return __builtin_amdgcn_readfirstlane(x);
 }
 
-// Folds the per-lane run counters; late: this window saw the abort word set.
+// Adds the window's counters to the wavefront's totals; late: this window saw
+// the abort word set.
 __device__ __forceinline__ void fold_run(Tally &t, bool late = false) {
-    t.probes += t.probes_run;
-    t.lookups += t.lookups_run;
-    t.probes_run = 0;
-    t.lookups_run = 0;
-    const uint64_t b = wave_sum32(t.bytes_run);
-    if (late) t.bytes_late += b;
-    else t.bytes += b;
-    t.bytes_run = 0;
+    const uint64_t tasks = wave_total64(t.tasks_run), scanned = wave_total64(t.scanned_run);
+    const uint32_t probes = wave_sum32(t.probes_run), lookups = wave_sum32(t.lookups_run);
+    const uint32_t b = wave_sum32(t.bytes_run);
+    {
+        uint64_t *x = t.tot;
+        x[kTotTasks] += tasks;
+        x[kTotScanned] += scanned;
+        x[kTotProbes] += probes;
+        x[kTotLookups] += lookups;
+        x[kTotGroups] += t.groups_run;
+        x[kTotActive] += t.active_run;
+        x[kTotIssued] += t.issued_run;
+        x[late ? kTotBytesLate : kTotBytes] += b;
+    }
+    t.tasks_run = t.scanned_run = t.probes_run = t.lookups_run = t.bytes_run = 0;
+    t.groups_run = t.active_run = t.issued_run = 0;
 }
 
 // Adds the wavefront's matches to query q's count; returns true once the count
@@ -909,25 +935,22 @@ __device__ __forceinline__ void tally_flush(const SearchArgs &a, PlanPtr P, int3
         ab = __hip_atomic_load(&a.qctl[q].abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) |
              __hip_atomic_load(&a.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     fold_run(t, read_lane(ab, 0) != kAbortNone);
-    const uint64_t tasks = wave_sum64(t.tasks);
-    const uint64_t scanned = wave_sum64(t.scanned);
-    const uint64_t lookups = wave_sum64(t.lookups);
-    const uint64_t probes = wave_sum64(t.probes);
     if (lane_id() == 0) {
         QCtl &c = a.qctl[q];
-        if (t.groups) atomicAdd(&c.groups, t.groups);
-        if (tasks) atomicAdd(&c.tasks, tasks);
-        if (scanned) atomicAdd(&c.scanned, scanned);
-        if (lookups) atomicAdd(&c.lookups, lookups);
-        if (probes) atomicAdd(&c.probes, probes);
-        if (t.active) atomicAdd(&c.lanes_active, t.active);
-        if (t.issued) atomicAdd(&c.lanes_issued, t.issued);
-        if (t.steals) atomicAdd(&c.steals, t.steals);
+        const uint64_t *x = t.tot;
+        if (x[kTotGroups]) atomicAdd(&c.groups, x[kTotGroups]);
+        if (x[kTotTasks]) atomicAdd(&c.tasks, x[kTotTasks]);
+        if (x[kTotScanned]) atomicAdd(&c.scanned, x[kTotScanned]);
+        if (x[kTotLookups]) atomicAdd(&c.lookups, x[kTotLookups]);
+        if (x[kTotProbes]) atomicAdd(&c.probes, x[kTotProbes]);
+        if (x[kTotActive]) atomicAdd(&c.lanes_active, x[kTotActive]);
+        if (x[kTotIssued]) atomicAdd(&c.lanes_issued, x[kTotIssued]);
+        if (x[kTotSteals]) atomicAdd(&c.steals, x[kTotSteals]);
         if (a.nq > 1) atomicMax(&c.t_last, static_cast<unsigned long long>(wall_clock64()));
-        if (t.bytes) atomicAdd(&c.bytes, static_cast<unsigned long long>(t.bytes));
-        if (t.bytes_late) atomicAdd(&c.bytes_late, static_cast<unsigned long long>(t.bytes_late));
+        if (x[kTotBytes]) atomicAdd(&c.bytes, x[kTotBytes]);
+        if (x[kTotBytesLate]) atomicAdd(&c.bytes_late, x[kTotBytesLate]);
     }
-    t = Tally{};
+    for (int i = 0; i < kTotals; ++i) t.tot[i] = 0ull;
 }
 
 __device__ __forceinline__ unsigned int load_word(unsigned int *p) {
@@ -1041,8 +1064,8 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                 const bool ok = process<SLIM, SB, CG>(S, a, P, 1, r1, lane, vi, t.probes_run, t.lookups_run,
                                                       t.bytes_run, marea);
                 const uint64_t m = ballot(ok);
-                t.active += ntask;
-                t.issued += kWave;
+                t.active_run += ntask;
+                t.issued_run += kWave;
                 if (P->k == 2) {
                     if (MODE == kEnumerate && m) {
                         const unsigned long long b0 = lane0_atomic_add(&ctl->out_rows, __popcll(m));
@@ -1063,11 +1086,12 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                 push_entry<SLIM>(S, 1, lane, v, vi, lane);
                 const Gen g = generate_tasks<SLIM, CG>(S, a, P, 2, m, lane);
                 cur = g.sl;
-                t.tasks += g.tasks;
-                t.scanned += g.scanned;
-                t.lookups += g.lookups;
+                t.tasks_run += g.tasks;
+                t.scanned_run += g.scanned;
+                t.lookups_run += g.lookups;
                 t.bytes_run += g.bytes;
-                t.groups += __popcll(m);
+                t.groups_run += __popcll(m);
+                fold_run(t);  // a claimed item's group can be as large as 2^24: fold at once
                 open_level(S, 2, lane);
                 base = 2;
                 have = true;
@@ -1105,10 +1129,11 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                 first_phase_cut(cur, P);
                 g.scanned = g.scanned < P->hub_cut ? g.scanned : P->hub_cut;
             }
-            t.tasks += g.tasks;
-            t.scanned += g.scanned;
-            t.lookups += g.lookups;
-            t.groups += __popcll(F0);
+            t.tasks_run += g.tasks;
+            t.scanned_run += g.scanned;
+            t.lookups_run += g.lookups;
+            t.groups_run += __popcll(F0);
+            fold_run(t);  // a claimed item's group can be as large as 2^24: fold at once
             open_level(S, d, lane);
             base = d;
             have = true;
@@ -1190,7 +1215,7 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
             wait_memory();
             if (lane == 0) store_agent(&mb.status, static_cast<unsigned int>(kMailEmpty));
             base = L;
-            ++t.steals;
+            t.tot[kTotSteals] += 1ull;
         }
         // the unit's query, made provably wave-uniform so that every plan field
         // in the loop below is a scalar load
@@ -1209,8 +1234,8 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                 }
                 continue;
             }
-            t.active += r.ntask;
-            t.issued += kWave;
+            t.active_run += r.ntask;
+            t.issued_run += kWave;
             t.bytes_run += lane < r.ntask ? 4u : 0u;  // the candidate's id
             VInfo vi;
             const bool ok = process<SLIM, SB, CG>(S, a, P, l, r, lane, vi, t.probes_run, t.lookups_run, t.bytes_run,
@@ -1263,11 +1288,11 @@ __global__ __launch_bounds__(kBlock, OCC) void search_kernel(SearchArgs a) {
                 const Gen g = generate_tasks<SLIM, CG>(S, a, P, l + 1, m, lane);
                 cur = g.sl;
                 t.bytes_run += 8u;
-                t.tasks += g.tasks;
-                t.scanned += g.scanned;
-                t.lookups += g.lookups;
+                t.tasks_run += g.tasks;
+                t.scanned_run += g.scanned;
+                t.lookups_run += g.lookups;
                 t.bytes_run += g.bytes;
-                t.groups += __popcll(m);
+                t.groups_run += __popcll(m);
                 open_level(S, l + 1, lane);
                 ++l;
             }
