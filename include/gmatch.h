@@ -134,7 +134,10 @@ typedef struct {
      * lanes and intersected there by merge path when n <= merge_ratio * r (it
      * must also fit the run's share of the staging buffer, 8 entries per lane);
      * longer lists are bisected in device memory by each lane (or answered by a
-     * hub bitmap).  0 = default 1, -1 = never stage. */
+     * hub bitmap).  0 = default: ratio 1 unless the staging area would lower
+     * the wavefronts a CU keeps resident (the deepest queries, about 29
+     * vertices and more, where LDS bounds residency; those then never stage);
+     * -1 = never stage; 1..8 = that ratio, always. */
     int32_t merge_ratio;
     int32_t reserved[2];
 } gm_options;
@@ -324,7 +327,7 @@ typedef struct {
     int32_t trials;              /* settings measured */
     double best_ms;              /* device time of the chosen setting on the sample */
     double default_ms;           /* device time of the engine's settings before tuning */
-    int32_t merge_ratio;         /* as in gm_options: LDS staging of short lists (-1 = never) */
+    int32_t merge_ratio;         /* as in gm_options: LDS staging of short lists (0 = default, -1 = never) */
     int32_t reserved;
 } gm_tuning;
 
@@ -333,8 +336,8 @@ typedef struct {
  * value before moving on: streams (queries in flight) over 1, 16, 64, 256;
  * wavefronts per CU over as-many-as-fit, 12, 8; stack layout (LDS bytes per
  * wavefront) slim, full; steal threshold 32, 128, 512; LDS staging of short
- * lists (merge_ratio: the staging buffer, 1, 2 or 4 entries per lane, or
- * none); launch grouping.  The
+ * lists (merge_ratio: the default, none, or a staging buffer of 1, 2 or 4
+ * entries per lane); launch grouping.  The
  * measure is the device time of the batch's launches.  The result stays in
  * the engine's options and is reported in *out.  Every setting must give the
  * same count for each query that finishes under both; a difference returns

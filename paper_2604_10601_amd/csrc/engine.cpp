@@ -844,6 +844,7 @@ SearchArgs graph_args(const gm_engine *e, const LaunchCtx &c) {
     a.qctl = c.d_qctl;
     a.streams = c.d_streams;
     a.merge_slots = merge_slots(e);
+    a.merge_auto = e->opt.merge_ratio == 0 ? 1 : 0;
     return a;
 }
 
@@ -1112,7 +1113,8 @@ gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, ui
         // few).  Otherwise 64: measured on the scale-20 workload, items of R /
         // wavefronts roots (about 3) ran 3 % slower than 64.
         const unsigned long long waves = static_cast<unsigned long long>(
-            std::max(1, gm::search_waves(q->k, e->num_cu, e->opt.waves_per_cu, cg || use_slim(e, q->k), merge_slots(e))));
+            std::max(1, gm::search_waves(q->k, e->num_cu, e->opt.waves_per_cu, cg || use_slim(e, q->k), merge_slots(e),
+                                             e->opt.merge_ratio == 0)));
         p.rpi = R < waves ? 1u : static_cast<uint32_t>(gm::kWave);
     }
     p.item_split = (R + p.rpi - 1) / p.rpi;
@@ -1417,7 +1419,8 @@ gm_status run_search(gm_engine *e, int32_t qid, uint64_t cap, double time_limit_
 
 // Wavefronts per CU a search launch for a query of k vertices keeps resident.
 int residency(const gm_engine *e, int32_t k) {
-    return gm::search_waves(k, e->num_cu, e->opt.waves_per_cu, use_slim(e, k), merge_slots(e));
+    return gm::search_waves(k, e->num_cu, e->opt.waves_per_cu, use_slim(e, k), merge_slots(e),
+                            e->opt.merge_ratio == 0);
 }
 
 // Work-item streams of a batched launch: the option, else 64 (queries in flight).
@@ -1648,7 +1651,7 @@ gm_status run_tune(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t cap, 
     best.steal_threshold = saved.steal_threshold > 0 ? saved.steal_threshold : 128;
     best.stack_layout = saved.stack_layout == 1 ? 1 : 2;
     best.batch_streams = batch_streams(e);
-    best.merge_ratio = saved.merge_ratio != 0 ? saved.merge_ratio : gm::kDefaultMergeSlots;
+    best.merge_ratio = saved.merge_ratio;  // 0 (stage where it costs no residency) is a setting of its own
     double best_ms = info.kernel_ms;
     const double default_ms = info.kernel_ms;
     int32_t trials = 1;
@@ -1661,7 +1664,7 @@ gm_status run_tune(gm_engine *e, int32_t nq, const int32_t *qids, uint64_t cap, 
         {&gm_options::waves_per_cu, {0, 12, 8}},
         {&gm_options::stack_layout, {2, 1}},
         {&gm_options::steal_threshold, {32, 128, 512}},
-        {&gm_options::merge_ratio, {-1, 1, 2, 4}},
+        {&gm_options::merge_ratio, {0, -1, 1, 2, 4}},
         {&gm_options::batch_single_launch, {0, 1}},
     };
     for (const Knob &kb : knobs) {

@@ -197,6 +197,7 @@ struct SearchArgs {
     int32_t measure_next;      // expansion: add the next level's size bound to ctl->measure
     int32_t merge_slots;       // LDS-staged intersection: staging entries per lane, 0 = off (slim
                                // layout only); a run of r candidates stages a list of n <= slots * r
+    int32_t merge_auto;        // 1: the launch drops the staging area where it costs residency
     // parked task groups: levels x 64 entries of 8 bytes per wavefront, for up to
     // park_waves wavefronts (a launch never has more)
     uint2 *parked;
@@ -278,7 +279,7 @@ hipError_t launch_level1(const int32_t *roots, int32_t R, unsigned long long per
                          uint32_t *voff, uint32_t *tmp, QCtl *qc, Plan *plan, StreamCtl *sc, int num_cu,
                          hipStream_t s);
 // Wavefronts a depth-first search launch for a query of `levels` positions keeps resident.
-int search_waves(int levels, int num_cu, int waves_per_cu, bool slim, int merge_slots);
+int search_waves(int levels, int num_cu, int waves_per_cu, bool slim, int merge_slots, bool merge_auto);
 hipError_t launch_steal_init(Mailbox *mail, unsigned long long *idle_bits, int32_t n, hipStream_t s);
 
 // Allocation-free count (scratch.hip): device address of this device's

@@ -1575,7 +1575,25 @@ hipError_t launch_expand(const SearchArgs &a, int num_cu, hipStream_t s) {
     return launch_mode<kExpand>(a, num_cu, 0, s, nullptr);
 }
 
-int search_waves(int levels, int num_cu, int waves_per_cu, bool slim, int merge_slots) {
+// Wavefronts per CU a slim plain-graph count launch keeps resident with
+// `slots` staging entries per lane, in the build the launch would take.
+int slim_residency(int levels, int waves_per_cu, int slots) {
+    if (five_waves_fit<kCount, false>(levels, waves_per_cu, slots))
+        return blocks_per_cu<kCount, true, false, false, 5>(levels, waves_per_cu, slots);
+    return blocks_per_cu<kCount, true, false, false, 4>(levels, waves_per_cu, slots);
+}
+
+// The default staging: the staging area is kept unless it lowers the
+// wavefronts a CU keeps resident, which happens only for the deepest queries,
+// where LDS and not registers bounds residency.  Latency hiding is worth more
+// there than staging, which the search then does without.
+int auto_merge_slots(int levels, int waves_per_cu, int slots) {
+    if (slots <= 0) return 0;
+    return slim_residency(levels, waves_per_cu, slots) < slim_residency(levels, waves_per_cu, 0) ? 0 : slots;
+}
+
+int search_waves(int levels, int num_cu, int waves_per_cu, bool slim, int merge_slots, bool merge_auto) {
+    if (slim && merge_auto) merge_slots = auto_merge_slots(levels, waves_per_cu, merge_slots);
     int per_cu = slim ? blocks_per_cu<kCount, true, false, false, 4>(levels, waves_per_cu, merge_slots)
                       : blocks_per_cu<kCount, false, false, false, 4>(levels, waves_per_cu, 0);
     if (slim && five_waves_fit<kCount, false>(levels, waves_per_cu, merge_slots))
@@ -1585,8 +1603,10 @@ int search_waves(int levels, int num_cu, int waves_per_cu, bool slim, int merge_
 
 hipError_t launch_search(const SearchArgs &a, bool enumerate, int num_cu, int waves_per_cu, hipStream_t s,
                          int *grid_waves_out) {
-    if (enumerate) return launch_mode<kEnumerate>(a, num_cu, waves_per_cu, s, grid_waves_out);
-    return launch_mode<kCount>(a, num_cu, waves_per_cu, s, grid_waves_out);
+    SearchArgs b = a;
+    if (b.slim && b.merge_auto) b.merge_slots = auto_merge_slots(b.levels, waves_per_cu, b.merge_slots);
+    if (enumerate) return launch_mode<kEnumerate>(b, num_cu, waves_per_cu, s, grid_waves_out);
+    return launch_mode<kCount>(b, num_cu, waves_per_cu, s, grid_waves_out);
 }
 
 hipError_t launch_level1(const int32_t *roots, int32_t R, unsigned long long perm_mul, uint32_t hub_cut,

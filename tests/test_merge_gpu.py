@@ -4,8 +4,10 @@ A list is staged in LDS and intersected by merge path when it is short against
 the run of candidates testing it (n <= merge_ratio x the run's lanes); longer
 lists are bisected in device memory.  Counts, outcomes and the paper's work
 counters (groups, tasks) must not depend on that choice: every case runs with
-staging never (-1), by default (0 = 1 entry per lane) and at the largest
-buffer (8), with hub bitmaps on and off, and matches the oracle.
+staging never (-1), by default (0: 1 entry per lane unless the staging area
+would lower the wavefronts a CU keeps resident, as for the deepest queries),
+always at 1 entry per lane (1) and at the largest buffer (8), with hub bitmaps
+on and off, and matches the oracle.
 """
 import sys
 
@@ -19,7 +21,7 @@ from tests import shapes as S
 
 pytestmark = pytest.mark.gpu
 
-RATIOS = (-1, 0, 8)
+RATIOS = (-1, 0, 1, 8)
 
 
 def _say(msg):
@@ -61,6 +63,14 @@ def test_four_cycles_in_complete_bipartite_graphs(a, b):
         assert e.count(e.add(S.cycle_q(4))).count == 2 * a * (a - 1) * b * (b - 1)
     if min(a, b) >= 20:
         assert probes[-1] != probes[8], "staging should change the membership reads"
+
+
+def test_deep_cycles_under_each_setting():
+    """30- and 32-vertex cycles in K_{40,40}: the depths at which the default
+    drops the staging area (LDS bounds residency there) while ratio 1 keeps it.
+    Both stop at the cap; the count must be the cap under every setting."""
+    _say("K_40,40 deep cycles")
+    _check(S.complete_bipartite(40, 40), [S.cycle_q(30), S.cycle_q(32)], cap=1_000_000, tag="K40,40 C30/C32")
 
 
 def test_cliques_and_labelled_cliques():
