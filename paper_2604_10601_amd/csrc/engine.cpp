@@ -857,8 +857,11 @@ bool has_sb(const Plan &p) {
     return false;
 }
 
-// Two-phase pool: tasks of position 1 a root keeps in its first-phase item (default).
-constexpr uint32_t kHubCut = 16;
+// Two-phase pool: tasks of position 1 a root keeps in its first-phase item
+// (default).  Measured one query per launch: 8 ran the 12-32-vertex queries on
+// R-MAT scale 24 1 % faster than 16 and the 8-vertex ones on scale 20 1 %
+// faster; 32 and more were slower on the latter.
+constexpr uint32_t kHubCut = 8;
 
 // Task split of a query's two-phase pool: its own setting, else the engine's, else the default.
 int32_t query_split(const gm_engine *e, const QueryRec &q) {
