@@ -304,7 +304,7 @@ def main() -> int:
     ap.add_argument("--disable-stealing", action="store_true")
     ap.add_argument("--stack-layout", type=int, default=0, help="0 auto, 1 full, 2 slim")
     ap.add_argument("--steal-threshold", type=int, default=0)
-    ap.add_argument("--hub-cut", type=int, default=0, help="first-phase tasks per root (0 = default 8)")
+    ap.add_argument("--hub-cut", type=int, default=0, help="first-phase tasks per root (0 = default 1)")
     ap.add_argument("--no-hub-bitmaps", action="store_true", help="bisect hub lists instead of reading bitmaps")
     ap.add_argument("--hub-mib", type=int, default=0, help="device memory for hub bitmaps in MiB (0 = default)")
     ap.add_argument("--roots-per-item", type=int, default=0,

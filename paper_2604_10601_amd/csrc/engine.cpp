@@ -858,10 +858,13 @@ bool has_sb(const Plan &p) {
 }
 
 // Two-phase pool: tasks of position 1 a root keeps in its first-phase item
-// (default).  Measured one query per launch: 8 ran the 12-32-vertex queries on
-// R-MAT scale 24 1 % faster than 16 and the 8-vertex ones on scale 20 1 %
-// faster; 32 and more were slower on the latter.
-constexpr uint32_t kHubCut = 8;
+// (default).  Measured one query per launch on the 12-32-vertex queries on
+// R-MAT scale 24: 16, 8, 4, 2 and 1 gave 54.6, 56.2, 57.1, 58.0 and 58.8 G
+// embeddings/s, with the slowest query and p99 falling too; the 8-vertex
+// queries on scale 20 ran level (within 1 %) from 8 down to 1, and 32 and more
+// were slower there.  Every root still gets one task in the first phase, so it
+// is sampled early; the rest of its list spreads over second-phase items.
+constexpr uint32_t kHubCut = 1;
 
 // Task split of a query's two-phase pool: its own setting, else the engine's, else the default.
 int32_t query_split(const gm_engine *e, const QueryRec &q) {

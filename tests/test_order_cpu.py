@@ -38,13 +38,13 @@ def test_features_worked_by_hand(eng):
     want[5:10] = [lg(4), 1 / 8, 1 / 8, lg(1), lg(4)]
     want[10:15] = [lg(2), 1 / 8, 1 / 8, lg(1), lg(2)]
     want[160], want[161] = 3 / 32, 2 / 64
-    want[162] = math.log2(8) / 8           # the task split: the default 8
+    want[162] = math.log2(1) / 8           # the task split: the default 1
     assert np.allclose(f, want, atol=1e-7)
     eng.set_split(qid, 64)
     assert eng.get_split(qid) == 64
     assert abs(eng.order_features(qid, [1, 0, 2])[162] - 6 / 8) < 1e-7
     eng.set_split(qid, 0)                  # back to the engine's setting
-    assert eng.get_split(qid) == 8
+    assert eng.get_split(qid) == 1
     with pytest.raises(gm.GmError):
         eng.set_split(qid, -1)
 

@@ -143,13 +143,13 @@ def test_splits_keep_counts_and_the_model_picks_plans():
             assert (r.count, r.outcome) == (o.count, o.outcome), i
         qid = e.add(qs[0])
         co, cs, _, probe = e.choose_plan(m, qid, splits=splits, max_orders=4, seed=0, margin=100.0, probe_cap=1000)
-        assert (co, cs) == (0, 8) and e.get_split(qid) == 8 and probe == 0.0   # nothing to judge
+        assert (co, cs) == (0, 1) and e.get_split(qid) == 1 and probe == 0.0   # nothing to judge
         # a proposal judged by measured runtime: whichever plan stays, counts are the oracle's
         for i, q in enumerate(qs):
             qid = e.add(q)
             co, cs, _, probe = e.choose_plan(m, qid, splits=splits, max_orders=4, seed=i, margin=-10.0,
                                              probe_cap=10_000, probe_limit_s=1.0)
-            assert probe >= 0.0 and e.get_split(qid) in (8, cs)
+            assert probe >= 0.0 and e.get_split(qid) in (1, cs)
             o = oracle.count(g, q, order=e.get_order(qid), cap=2_000_000)
             r = e.count(qid, cap=2_000_000)
             assert (r.count, r.outcome) == (o.count, o.outcome), i
