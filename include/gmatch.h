@@ -97,7 +97,8 @@ typedef struct {
     int32_t batch_streams;
     /* Default pool (tau = 0): position-1 tasks a first-vertex candidate keeps
      * in its first-phase work item; the rest of a hub's tasks go to the second
-     * phase.  0 = default 1. */
+     * phase.  0 = default 1, or 8 for a query whose first-phase items hold
+     * one root each (fewer roots than resident wavefronts). */
     int32_t pool_hub_cut;
     /* 1 = no adjacency bitmaps.  By default gm_load_graph keeps one bit per
      * vertex of G for each of the highest-degree vertices (at least 256
@@ -500,7 +501,7 @@ gm_status gm_choose_order(gm_engine *engine, gm_model *model, int32_t qid, int32
  * number of a first-vertex candidate's position-1 tasks that stay with it in
  * its first-phase work item; the rest of them become second-phase items of 64
  * tasks that any wavefront can take.  0 = the engine's pool_hub_cut (default
- * 1).  Counts do not depend on it.  GM_ERR_ARG outside [0, 2^24]. */
+ * 1, or 8 where a first-phase item holds one root).  Counts do not depend on it.  GM_ERR_ARG outside [0, 2^24]. */
 gm_status gm_set_split(gm_engine *engine, int32_t qid, int32_t split);
 /* The split a count of qid uses now (its own, else the engine's). */
 gm_status gm_get_split(const gm_engine *engine, int32_t qid, int32_t *split);

@@ -865,6 +865,11 @@ bool has_sb(const Plan &p) {
 // were slower there.  Every root still gets one task in the first phase, so it
 // is sampled early; the rest of its list spreads over second-phase items.
 constexpr uint32_t kHubCut = 1;
+// ... unless a first-phase item holds one root (fewer roots than resident
+// wavefronts, as on a candidate graph): a cut of 1 would then give the item a
+// single task, one busy lane in 64.  There the default is 8: on the candidate
+// graph of the G(n, M) workload, cut 1 took the search from 46 to 94 ms.
+constexpr uint32_t kHubCutFewRoots = 8;
 
 // Task split of a query's two-phase pool: its own setting, else the engine's, else the default.
 int32_t query_split(const gm_engine *e, const QueryRec &q) {
@@ -1123,6 +1128,8 @@ gm_status run_virtual(gm_engine *e, const QueryRec *q, const Plan &base_plan, ui
                                              e->opt.merge_ratio == 0)));
         p.rpi = R < waves ? 1u : static_cast<uint32_t>(gm::kWave);
     }
+    if (q->split <= 0 && e->opt.pool_hub_cut <= 0 && p.rpi < static_cast<uint32_t>(gm::kWave))
+        p.hub_cut = std::max(p.hub_cut, kHubCutFewRoots);
     p.item_split = (R + p.rpi - 1) / p.rpi;
     e->lc.h_plans.assign(1, p);
     e->lc.h_streams.assign(1, gm::StreamCtl{});
