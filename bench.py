@@ -727,7 +727,7 @@ def bench_learned(args, gm) -> int:
     must not change; total time, p50 and p99 are compared."""
     from paper_2604_10601_amd import workloads as wl
     train_cap, train_limit, cap, limit = args.train_cap, args.train_limit, args.eval_cap, args.eval_limit
-    n_orders, splits = 4, (8, 16, 32, 64)
+    n_orders, splits = 4, (1, 4, 16, 64)
     xs, ys, starts = [], [], []
     half = max(1, args.train_queries // 2)
     for scale, seed in ((20, 60), (22, 61)):

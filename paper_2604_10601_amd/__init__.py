@@ -461,7 +461,7 @@ class Engine:
         self._check(self._lib.gm_get_split(self._h, qid, ctypes.byref(s)))
         return s.value
 
-    def choose_plan(self, model: "Model", qid: int, splits=(8, 16, 32, 64), max_orders: int = 4, seed: int = 0,
+    def choose_plan(self, model: "Model", qid: int, splits=(1, 4, 16, 64), max_orders: int = 4, seed: int = 0,
                     margin: float = 0.0, probe_cap: int = 0, probe_limit_s: float = 0.0):
         """Let the model pick order and split (gm_choose_plan), judged by a measured probe when
         probe_cap > 0: (order index, split, predictions, probe ms)."""
